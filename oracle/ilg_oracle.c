@@ -1,0 +1,383 @@
+/*
+ * Plain CPU oracle for the diffusive integer lattice gas step with the flip
+ * (over-relaxation) operator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this file's library.  The product
+ * library never links it, and it shares no code, header, table or constant
+ * generator with the product's HIP sources.
+ *
+ * What it computes (paper: Strand & Wagner, "Over-Relaxation in Diffusive
+ * Integer Lattice Gas"):
+ *   - lattice-gas evolution with flip, Eq. LGflip: each node first flips its
+ *     occupations, F_i(n) = n_{-i} (Eq. flip, v_{-i} = -v_i), then a sampling
+ *     collision redistributes a random fraction omega* of the particles to
+ *     velocity i with probability w_i (Integer Lattice Gas section, the
+ *     Seekins sampling collision; Over-relaxation section for omega*),
+ *     then every count streams to x + v_i (Eq. ilgeq);
+ *   - mass is the only conserved quantity (sum_i Xi_i = 0).
+ *
+ * Reading of the collision (the paper defers the algorithm to Seekins et al.):
+ * every particle collides independently with probability p = P / 2^32; the
+ * collided particles are redistributed multinomially with the weights w_i.
+ * Sampling is in exact 32-bit fixed point:
+ *   Bin(n, p): n is cut into chunks of 64 (full chunks first, remainder last);
+ *   for a chunk of size m one 32-bit draw U is taken and the chunk's result is
+ *   #{ j < m : T_p[m][j] <= U }, where T_p[m][j] = floor(2^32 * CDF_{m,p}(j)),
+ *   supplied by the caller (built with exact big integers in exact.py).
+ *   p = 0 is passed as a NULL table: the result is 0 but the draws are still
+ *   consumed, so draw alignment does not depend on p.
+ * Draws: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11), key = the 64-bit
+ * seed split into two 32-bit words (low word first), counter =
+ * (node x, step t, realization r, block b).  Draw number j of a node-step is
+ * word (j mod 4) of block j / 4.  Draw order within a node-step: removal
+ * Bin(a_i, P) for i = 0..Q-1, then the redistribution binomials.
+ *
+ * This code is written to be checked by eye, not to be fast.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+#define ORACLE_CHUNK 64
+#define ORACLE_TABLE_ENTRIES 2080 /* rows m = 1..64, m entries each */
+
+/* ------------------------------------------------------------------ Philox */
+
+/* Philox4x32 with 10 rounds.  Round: multiply words 0 and 2 by the two Philox
+ * multipliers (full 64-bit products), then
+ *   out0 = hi(M1*c2) ^ c1 ^ k0,  out1 = lo(M1*c2),
+ *   out2 = hi(M0*c0) ^ c3 ^ k1,  out3 = lo(M0*c0);
+ * the key is advanced by the two Weyl constants between rounds. */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The stream of 32-bit draws of one node-step. */
+typedef struct {
+    uint32_t key[2];
+    uint32_t ctr[4];   /* x, t, r, block */
+    uint32_t block[4];
+    uint64_t used;     /* number of draws consumed so far */
+} draw_stream;
+
+static void stream_init(draw_stream *s, uint64_t seed, uint32_t x, uint32_t t, uint32_t r)
+{
+    s->key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
+    s->key[1] = (uint32_t)(seed >> 32);
+    s->ctr[0] = x;
+    s->ctr[1] = t;
+    s->ctr[2] = r;
+    s->ctr[3] = 0;
+    s->used = 0;
+}
+
+static uint32_t next_draw(draw_stream *s)
+{
+    uint64_t j = s->used;
+    if (j % 4 == 0) {
+        s->ctr[3] = (uint32_t)(j / 4);
+        oracle_philox4x32_10(s->ctr, s->key, s->block);
+    }
+    s->used = j + 1;
+    return s->block[j % 4];
+}
+
+/* ---------------------------------------------------------------- binomial */
+
+static const uint32_t *table_row(const uint32_t *table, uint32_t m)
+{
+    return table + (size_t)(m - 1) * m / 2;
+}
+
+/* Bin(n, p) by chunked inverse CDF; table == NULL means p = 0. */
+static uint64_t binomial(uint64_t n, const uint32_t *table, draw_stream *s)
+{
+    uint64_t total = 0;
+    while (n > 0) {
+        uint32_t m = n >= ORACLE_CHUNK ? ORACLE_CHUNK : (uint32_t)n;
+        uint32_t U = next_draw(s);
+        if (table != NULL) {
+            const uint32_t *row = table_row(table, m);
+            for (uint32_t j = 0; j < m; ++j)
+                if (row[j] <= U)
+                    total += 1;
+        }
+        n -= m;
+    }
+    return total;
+}
+
+/* ------------------------------------------------------------ node update */
+
+typedef struct {
+    int q;                     /* 2: v = (-1,+1); 3: v = (-1,0,+1) */
+    int flip;                  /* apply F before the collision */
+    const uint32_t *tab_p;     /* removal fraction P (NULL: P = 0) */
+    const uint32_t *tab_half;  /* P = 2^31 */
+    const uint32_t *tab_rest;  /* P = (1 - theta) 2^32, Q = 3 only */
+    uint64_t seed;
+    uint32_t realization;
+} oracle_params;
+
+/* One node: flip, then removal binomials, then multinomial redistribution.
+ * Returns the post-collision counts c_i = a_i - k_i + m_i (before streaming). */
+static void collide_node(const oracle_params *pp, const uint64_t n_in[3], uint32_t x, uint32_t t,
+                         uint64_t c_out[3])
+{
+    const int q = pp->q;
+    uint64_t a[3] = {0, 0, 0}, k[3] = {0, 0, 0}, m[3] = {0, 0, 0};
+    draw_stream s;
+    stream_init(&s, pp->seed, x, t, pp->realization);
+
+    /* Flip, Eq. flip: a_i = n_{-i}; with index order (-1, [0,] +1) the mirror
+     * of index i is q-1-i. */
+    for (int i = 0; i < q; ++i)
+        a[i] = pp->flip ? n_in[q - 1 - i] : n_in[i];
+
+    /* Each particle of velocity i collides with probability p. */
+    uint64_t M = 0;
+    for (int i = 0; i < q; ++i) {
+        k[i] = binomial(a[i], pp->tab_p, &s);
+        M += k[i];
+    }
+
+    /* The M collided particles go to velocity i with probability w_i. */
+    if (q == 2) {
+        m[0] = binomial(M, pp->tab_half, &s);   /* w_- = 1/2 */
+        m[1] = M - m[0];
+    } else {
+        m[1] = binomial(M, pp->tab_rest, &s);   /* w_0 = 1 - theta */
+        uint64_t R = M - m[1];
+        m[0] = binomial(R, pp->tab_half, &s);   /* w_- / (w_- + w_+) = 1/2 */
+        m[2] = R - m[0];
+    }
+    for (int i = 0; i < q; ++i)
+        c_out[i] = a[i] - k[i] + m[i];
+}
+
+static uint64_t load_count(const void *buf, int count_bytes, size_t idx)
+{
+    if (count_bytes == 2)
+        return ((const uint16_t *)buf)[idx];
+    return ((const uint32_t *)buf)[idx];
+}
+
+static void store_count(void *buf, int count_bytes, size_t idx, uint64_t v)
+{
+    if (count_bytes == 2)
+        ((uint16_t *)buf)[idx] = (uint16_t)v;
+    else
+        ((uint32_t *)buf)[idx] = (uint32_t)v;
+}
+
+/* ----------------------------------------------------------- lattice step */
+
+typedef struct {
+    const oracle_params *pp;
+    int count_bytes;
+    uint64_t length;   /* global lattice length L (periodic) */
+    uint64_t x0;       /* global index of window position 0 */
+    uint64_t width;    /* window width W (== L for a whole periodic lattice) */
+    int periodic;      /* 1: whole lattice, wrap; 0: window, drop what leaves */
+    const void *in;    /* [q][W] */
+    void *out;         /* [q][W] */
+    uint32_t t;
+    uint64_t w_begin, w_end;
+    int overflow;
+} step_job;
+
+static void *step_worker(void *arg)
+{
+    step_job *job = (step_job *)arg;
+    const int q = job->pp->q;
+    const uint64_t maxval = job->count_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu;
+    for (uint64_t w = job->w_begin; w < job->w_end; ++w) {
+        uint64_t n[3] = {0, 0, 0}, c[3];
+        for (int i = 0; i < q; ++i)
+            n[i] = load_count(job->in, job->count_bytes, (size_t)i * job->width + w);
+        uint32_t xg = (uint32_t)((job->x0 + w) % job->length);
+        collide_node(job->pp, n, xg, job->t, c);
+        for (int i = 0; i < q; ++i) {
+            /* velocity of index i: -1, (0,) +1 */
+            int64_t v = (q == 2) ? (i == 0 ? -1 : 1) : (int64_t)i - 1;
+            int64_t dst = (int64_t)w + v;
+            if (job->periodic) {
+                dst = (dst + (int64_t)job->width) % (int64_t)job->width;
+            } else if (dst < 0 || dst >= (int64_t)job->width) {
+                continue;
+            }
+            if (c[i] > maxval)
+                job->overflow = 1;
+            store_count(job->out, job->count_bytes, (size_t)i * job->width + (size_t)dst, c[i]);
+        }
+    }
+    return NULL;
+}
+
+/* One time step t -> t+1 over a window (or the whole periodic lattice).
+ * In window mode the first and last node of `out` receive nothing from outside
+ * and are set to 0; after s steps only nodes [s, W-s) are valid.
+ * Returns 1 if any post-collision count exceeded the count type, else 0. */
+int oracle_step(int q, int count_bytes, uint64_t length, uint64_t x0, uint64_t width, int periodic,
+                int flip, const uint32_t *tab_p, const uint32_t *tab_half, const uint32_t *tab_rest,
+                uint64_t seed, uint32_t realization, uint32_t t, const void *in, void *out,
+                int nthreads)
+{
+    oracle_params pp = {q, flip, tab_p, tab_half, tab_rest, seed, realization};
+    if (!periodic)
+        memset(out, 0, (size_t)q * width * (size_t)count_bytes);
+    if (nthreads < 1)
+        nthreads = 1;
+    if ((uint64_t)nthreads > width)
+        nthreads = (int)(width > 0 ? width : 1);
+    step_job *jobs = (step_job *)calloc((size_t)nthreads, sizeof(step_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    for (int k = 0; k < nthreads; ++k) {
+        step_job j = {&pp, count_bytes, length, x0, width, periodic, in, out, t,
+                      width * (uint64_t)k / (uint64_t)nthreads,
+                      width * (uint64_t)(k + 1) / (uint64_t)nthreads, 0};
+        jobs[k] = j;
+    }
+    for (int k = 1; k < nthreads; ++k)
+        pthread_create(&th[k], NULL, step_worker, &jobs[k]);
+    step_worker(&jobs[0]);
+    for (int k = 1; k < nthreads; ++k)
+        pthread_join(th[k], NULL);
+    int overflow = 0;
+    for (int k = 0; k < nthreads; ++k)
+        overflow |= jobs[k].overflow;
+    free(jobs);
+    free(th);
+    return overflow;
+}
+
+/* ------------------------------------------------------------------ hash */
+
+static uint64_t splitmix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Order-independent state fingerprint: sum over (x, i) of
+ * splitmix64(((x*q + i) << 32) ^ n_i(x)) modulo 2^64. */
+uint64_t oracle_hash(int q, int count_bytes, uint64_t length, const void *state)
+{
+    uint64_t h = 0;
+    for (uint64_t x = 0; x < length; ++x)
+        for (int i = 0; i < q; ++i) {
+            uint64_t n = load_count(state, count_bytes, (size_t)i * length + x);
+            h += splitmix64(((x * (uint64_t)q + (uint64_t)i) << 32) ^ n);
+        }
+    return h;
+}
+
+/* nsteps whole-lattice steps starting at absolute step t0; `state` is updated
+ * in place.  If hashes != NULL, hashes[s] is the hash after step s+1.
+ * Returns 1 on count overflow (state then undefined), else 0. */
+int oracle_run(int q, int count_bytes, uint64_t length, int flip, const uint32_t *tab_p,
+               const uint32_t *tab_half, const uint32_t *tab_rest, uint64_t seed,
+               uint32_t realization, uint64_t t0, uint64_t nsteps, void *state, uint64_t *hashes,
+               int nthreads)
+{
+    size_t bytes = (size_t)q * length * (size_t)count_bytes;
+    void *tmp = malloc(bytes);
+    int overflow = 0;
+    for (uint64_t s = 0; s < nsteps; ++s) {
+        overflow |= oracle_step(q, count_bytes, length, 0, length, 1, flip, tab_p, tab_half,
+                                tab_rest, seed, realization, (uint32_t)(t0 + s), state, tmp,
+                                nthreads);
+        memcpy(state, tmp, bytes);
+        if (hashes)
+            hashes[s] = oracle_hash(q, count_bytes, length, state);
+    }
+    free(tmp);
+    return overflow;
+}
+
+/* Window run for light-cone sampling: `state` holds [q][width] counts of the
+ * global nodes x0 .. x0+width-1 (mod length) at step t0; after nsteps steps the
+ * nodes [nsteps, width-nsteps) hold the exact state of those global nodes. */
+int oracle_run_window(int q, int count_bytes, uint64_t length, uint64_t x0, uint64_t width,
+                      int flip, const uint32_t *tab_p, const uint32_t *tab_half,
+                      const uint32_t *tab_rest, uint64_t seed, uint32_t realization, uint64_t t0,
+                      uint64_t nsteps, void *state, int nthreads)
+{
+    size_t bytes = (size_t)q * width * (size_t)count_bytes;
+    void *tmp = malloc(bytes);
+    int overflow = 0;
+    for (uint64_t s = 0; s < nsteps; ++s) {
+        overflow |= oracle_step(q, count_bytes, length, x0, width, 0, flip, tab_p, tab_half,
+                                tab_rest, seed, realization, (uint32_t)(t0 + s), state, tmp,
+                                nthreads);
+        memcpy(state, tmp, bytes);
+    }
+    free(tmp);
+    return overflow;
+}
+
+/* ---------------------------------------------- sampler-level entry points */
+
+/* One node-step collision (no streaming): c_out[i] for input counts n_in. */
+void oracle_collide_node(int q, int flip, const uint32_t *tab_p, const uint32_t *tab_half,
+                         const uint32_t *tab_rest, uint64_t seed, uint32_t realization,
+                         uint32_t x, uint32_t t, const uint64_t *n_in, uint64_t *c_out)
+{
+    oracle_params pp = {q, flip, tab_p, tab_half, tab_rest, seed, realization};
+    uint64_t n[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+    for (int i = 0; i < q; ++i)
+        n[i] = n_in[i];
+    collide_node(&pp, n, x, t, c);
+    for (int i = 0; i < q; ++i)
+        c_out[i] = c[i];
+}
+
+/* nsamples collisions of the same input, sample s keyed at node x = s. */
+void oracle_collide_samples(int q, int flip, const uint32_t *tab_p, const uint32_t *tab_half,
+                            const uint32_t *tab_rest, uint64_t seed, uint32_t realization,
+                            uint32_t t, const uint64_t *n_in, uint64_t nsamples, uint64_t *c_out)
+{
+    oracle_params pp = {q, flip, tab_p, tab_half, tab_rest, seed, realization};
+    uint64_t n[3] = {0, 0, 0};
+    for (int i = 0; i < q; ++i)
+        n[i] = n_in[i];
+    for (uint64_t s = 0; s < nsamples; ++s) {
+        uint64_t c[3] = {0, 0, 0};
+        collide_node(&pp, n, (uint32_t)s, t, c);
+        for (int i = 0; i < q; ++i)
+            c_out[s * (uint64_t)q + (uint64_t)i] = c[i];
+    }
+}
+
+/* nsamples draws of Bin(n, p), sample s keyed at counter (s, 0, 0, b). */
+void oracle_binomial_samples(uint64_t n, const uint32_t *table, uint64_t seed, uint64_t nsamples,
+                             uint64_t *out)
+{
+    for (uint64_t s = 0; s < nsamples; ++s) {
+        draw_stream st;
+        stream_init(&st, seed, (uint32_t)s, 0, 0);
+        out[s] = binomial(n, table, &st);
+    }
+}

@@ -1,0 +1,170 @@
+"""ctypes front end of the plain C oracle (ilg_oracle.c) plus its build step.
+
+TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the
+benchmark's CPU-baseline leg.  Nothing in the product package imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+from . import exact
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ilg_oracle.c")
+_BUILD_DIR = os.path.join(_HERE, "_build")
+_LIB_PATH = os.path.join(_BUILD_DIR, "libilg_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (plain -O2, pthreads)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    os.makedirs(_BUILD_DIR, exist_ok=True)
+    tmp = _LIB_PATH + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-pthread",
+                    _SRC, "-o", tmp], check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        vp = ctypes.c_void_p
+        L.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                  ctypes.c_uint64, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                  ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, vp, vp,
+                                  ctypes.c_int]
+        L.oracle_step.restype = ctypes.c_int
+        L.oracle_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, vp, vp,
+                                 vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                 ctypes.c_uint64, vp, vp, ctypes.c_int]
+        L.oracle_run.restype = ctypes.c_int
+        L.oracle_run_window.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, vp, vp, vp,
+                                        ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                        ctypes.c_uint64, vp, ctypes.c_int]
+        L.oracle_run_window.restype = ctypes.c_int
+        L.oracle_hash.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, vp]
+        L.oracle_hash.restype = ctypes.c_uint64
+        L.oracle_collide_node.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_uint64,
+                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, vp,
+                                          vp]
+        L.oracle_collide_node.restype = None
+        L.oracle_collide_samples.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                             ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                             vp, ctypes.c_uint64, vp]
+        L.oracle_collide_samples.restype = None
+        L.oracle_binomial_samples.argtypes = [ctypes.c_uint64, vp, ctypes.c_uint64,
+                                              ctypes.c_uint64, vp]
+        L.oracle_binomial_samples.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"]
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Params:
+    """Fixed-point collision parameters and their exact tables."""
+
+    def __init__(self, q: int, omega: float, theta: float = 1.0 / 3.0, flip: str = "auto"):
+        self.q = q
+        self.omega = omega
+        self.theta = theta
+        fp = exact.fixed_point_params(omega, theta, flip)
+        self.flip = fp["flip"]
+        self.omega_star = fp["omega_star"]
+        self.P, self.P_half, self.P_rest = fp["P"], fp["P_half"], fp["P_rest"]
+        self.tab_p = exact.binomial_table(self.P)
+        self.tab_half = _cached_table(self.P_half)
+        self.tab_rest = _cached_table(self.P_rest) if q == 3 else None
+
+
+_table_cache = {}
+
+
+def _cached_table(P: int):
+    if P not in _table_cache:
+        _table_cache[P] = exact.binomial_table(P)
+    return _table_cache[P]
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib().oracle_philox4x32_10(c.ctypes.data_as(u32p), k.ctypes.data_as(u32p),
+                               out.ctypes.data_as(u32p))
+    return out
+
+
+def state_hash(state: np.ndarray) -> int:
+    q, L = state.shape
+    s = np.ascontiguousarray(state)
+    return int(lib().oracle_hash(q, s.dtype.itemsize, L, _ptr(s)))
+
+
+def run(params: Params, state: np.ndarray, nsteps: int, seed: int, realization: int = 0,
+        t0: int = 0, hashes: bool = False, nthreads: Optional[int] = None):
+    """Advance a whole periodic lattice; returns (new_state, hashes or None, overflow)."""
+    s = np.array(state, copy=True, order="C")
+    q, L = s.shape
+    assert q == params.q
+    hs = np.zeros(max(nsteps, 1), dtype=np.uint64) if hashes else None
+    ov = lib().oracle_run(q, s.dtype.itemsize, L, int(params.flip), _ptr(params.tab_p),
+                          _ptr(params.tab_half), _ptr(params.tab_rest), seed, realization, t0,
+                          nsteps, _ptr(s), _ptr(hs), nthreads or default_threads())
+    return s, (hs[:nsteps] if hashes else None), bool(ov)
+
+
+def run_window(params: Params, window: np.ndarray, length: int, x0: int, nsteps: int, seed: int,
+               realization: int = 0, t0: int = 0, nthreads: Optional[int] = None):
+    """Light-cone run of the window [x0, x0+W) (global indices mod length);
+    returns the window after nsteps, valid on [nsteps, W - nsteps)."""
+    s = np.array(window, copy=True, order="C")
+    q, W = s.shape
+    ov = lib().oracle_run_window(q, s.dtype.itemsize, length, x0, W, int(params.flip),
+                                 _ptr(params.tab_p), _ptr(params.tab_half), _ptr(params.tab_rest),
+                                 seed, realization, t0, nsteps, _ptr(s),
+                                 nthreads or default_threads())
+    return s, bool(ov)
+
+
+def collide_samples(params: Params, n_in, nsamples: int, seed: int, realization: int = 0,
+                    t: int = 0) -> np.ndarray:
+    n = np.zeros(3, dtype=np.uint64)
+    n[:params.q] = n_in
+    out = np.zeros((nsamples, params.q), dtype=np.uint64)
+    lib().oracle_collide_samples(params.q, int(params.flip), _ptr(params.tab_p),
+                                 _ptr(params.tab_half), _ptr(params.tab_rest), seed, realization,
+                                 t, _ptr(n), nsamples, _ptr(out))
+    return out
+
+
+def binomial_samples(n: int, table: Optional[np.ndarray], nsamples: int, seed: int) -> np.ndarray:
+    out = np.zeros(nsamples, dtype=np.uint64)
+    lib().oracle_binomial_samples(n, _ptr(table), seed, nsamples, _ptr(out))
+    return out
