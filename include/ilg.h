@@ -1,0 +1,164 @@
+/*
+ * ilg.h -- C ABI of the MI355X (gfx950) diffusive integer lattice gas library.
+ *
+ * The library advances integer occupation numbers n_i(x, t) of a periodic 1D
+ * lattice by the lattice-gas evolution with the flip operator of Strand &
+ * Wagner, "Over-Relaxation in Diffusive Integer Lattice Gas":
+ *   n_i(x + v_i, t + 1) = F_i(n) + Xi_i({F(n)})            (Eq. LGflip)
+ * where F_i(n) = n_{-i} (Eq. flip) and Xi is the sampling collision of the
+ * Integer Lattice Gas section: a fraction omega* of the particles, each picked
+ * independently, is redistributed to velocity i with probability w_i.  Mass is
+ * the only conserved quantity (sum_i Xi_i = 0).  The relaxation rate of the
+ * current is omega^j = 2 - omega* with the flip (Eq. omegaj), omega* without,
+ * and the density obeys diffusion with D = theta (1/omega^j - 1/2).
+ *
+ * Sampling is exact 32-bit fixed point with Philox4x32-10 draws keyed by
+ * (seed; node x, step t, realization r, block b), so every run is
+ * bit-reproducible and independent of launch shapes, batching or placement.
+ *
+ * Conventions for every function:
+ *   - Return value: ILG_OK (0) or a negative ilg_status.  No exception or abort
+ *     crosses the ABI; ilg_last_error() gives a thread-local message.
+ *   - Host pointers are read or written before the call returns unless stated;
+ *     device pointers are HIP device addresses on the handle's device.
+ *   - "stream" arguments are hipStream_t values (NULL: the legacy default
+ *     stream).  Work is enqueued on that stream; functions marked "syncs"
+ *     wait for it.
+ *   - A handle must not be used from two threads at once; distinct handles may.
+ *   - Device-side errors (a count exceeding its type) are sticky: they are
+ *     reported as ILG_E_OVERFLOW by the next syncing call, and the state is
+ *     undefined afterwards.
+ */
+#ifndef ILG_H
+#define ILG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ILG_ABI_VERSION 1u
+#define ILG_MAX_K 64u          /* largest structure-factor mode count */
+#define ILG_TABLE_ENTRIES 2080u /* fixed-point CDF table: rows m = 1..64 */
+
+typedef enum ilg_status {
+    ILG_OK = 0,
+    ILG_E_INVALID = -1,  /* bad argument or configuration */
+    ILG_E_NOMEM = -2,    /* device or host allocation failed */
+    ILG_E_DEVICE = -3,   /* a HIP call failed */
+    ILG_E_OVERFLOW = -4, /* a post-collision count exceeded the count type */
+    ILG_E_RANGE = -5,    /* step index would pass 2^32 - 1 */
+    ILG_E_BUSY = -6      /* resource budget exhausted (serving) */
+} ilg_status;
+
+/* ilg_config.flags */
+#define ILG_FLIP_AUTO 0u  /* flip iff omega > 1 (over-relaxation) */
+#define ILG_FLIP_OFF 1u   /* never flip; needs omega <= 1 */
+#define ILG_FLIP_ON 2u    /* always flip; needs omega >= 1 */
+#define ILG_FLIP_MASK 3u
+
+/* One lattice run.  Velocity index order is fixed: q = 2 -> v = (-1, +1),
+ * q = 3 -> v = (-1, 0, +1).  Weights: (1/2, 1/2) and (theta/2, 1-theta,
+ * theta/2); theta is the second velocity moment of the weights
+ * (Eq. Thetadef) and D1Q3 uses the transformation matrix of Eq. transform. */
+typedef struct ilg_config {
+    uint32_t abi_version; /* ILG_ABI_VERSION */
+    uint32_t q;           /* 2 or 3 */
+    uint32_t count_bytes; /* 2 (uint16 counts) or 4 (uint32 counts) */
+    uint32_t flags;       /* ILG_FLIP_* */
+    uint64_t length;      /* L, 1 <= L < 2^31, periodic */
+    double omega;         /* target rate omega^j in (0, 2]; with the flip the
+                             collision fraction is omega* = 2 - omega, else
+                             omega* = omega (Over-relaxation section) */
+    double theta;         /* q = 3 only, in (0, 1); 0 selects 1/3 */
+    uint64_t seed;        /* Philox key (low word, high word) */
+    uint32_t realization; /* Philox counter word 2 */
+    uint32_t reserved;    /* must be 0 */
+    uint64_t t0;          /* absolute index of the first step to take */
+} ilg_config;
+
+/* Fixed-point form of a configuration. */
+typedef struct ilg_fixed {
+    uint32_t flip;     /* 1 if the flip is applied */
+    uint32_t q;
+    uint64_t p;        /* round-half-even(omega* 2^32), in [0, 2^32] */
+    uint64_t p_half;   /* 2^31 */
+    uint64_t p_rest;   /* round-half-even((1 - theta) 2^32), q = 3 */
+    double omega_star;
+} ilg_fixed;
+
+/* Reductions of the current state. */
+typedef struct ilg_summary {
+    uint64_t mass;      /* sum over x, i of n_i(x) (exact) */
+    uint64_t step;      /* absolute step index of the state */
+    uint64_t hash;      /* sum of splitmix64(((x q + i) << 32) ^ n_i(x)) mod 2^64 */
+    double amplitude;   /* A^LG = sum_x sin(2 pi x/L) N(x) / sum_x sin^2(2 pi x/L) */
+    uint32_t nk;        /* number of S(k) values filled */
+    uint32_t reserved;
+    double sk[ILG_MAX_K]; /* S(k) = |sum_x N(x) e^{-2 pi i k x/L}|^2 / sum_x N(x), k = 1..nk */
+} ilg_summary;
+
+typedef struct ilg_handle ilg_handle; /* opaque; owned by the library */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *ilg_last_error(void);
+
+/* Fixed-point parameters for cfg (host only, no device work). */
+int ilg_fixed_point(const ilg_config *cfg, ilg_fixed *out);
+
+/* Exact table T_p[m][j] = floor(2^32 CDF_{m, p/2^32}(j)), m = 1..64,
+ * j = 0..m-1, row m at offset (m-1)m/2, written to out[ILG_TABLE_ENTRIES]
+ * (host).  p in (0, 2^32]; p = 0 has no table (ILG_E_INVALID). */
+int ilg_binomial_table(uint64_t p, uint32_t *out);
+
+/* Device layout of a lattice state: velocity-major [q][pitch] counts of
+ * count_bytes each, pitch = L rounded up to a multiple of 64; entries
+ * beyond L are padding and never read.  Returns the byte size. */
+uint64_t ilg_state_bytes(const ilg_config *cfg);
+uint64_t ilg_state_pitch(const ilg_config *cfg);
+
+/* Create a lattice; init_host is [q][L] counts (compact, count_bytes each),
+ * copied before return.  Device buffers are owned by the handle. */
+int ilg_create(const ilg_config *cfg, const void *init_host, void *stream, ilg_handle **out);
+
+/* Create a lattice on caller-owned device buffers of ilg_state_bytes(cfg)
+ * each.  buf0 must already hold the initial state in the device layout; buf1
+ * is scratch.  The buffers are borrowed: they must outlive the handle and are
+ * never freed by the library. */
+int ilg_create_on(const ilg_config *cfg, void *buf0, void *buf1, void *stream, ilg_handle **out);
+
+/* Device address of the buffer holding the current state (device layout). */
+void *ilg_state_device(const ilg_handle *h);
+
+/* Enqueue nsteps time steps (flip, collide, stream) on the handle's stream. */
+int ilg_step(ilg_handle *h, uint64_t nsteps);
+
+/* Copy the current state to host [q][L] (compact).  Syncs. */
+int ilg_get_state(ilg_handle *h, void *host_out);
+
+/* Replace the state by host [q][L] counts and set the absolute step index of
+ * the next step to t (checkpoint restore).  Syncs. */
+int ilg_set_state(ilg_handle *h, const void *host_in, uint64_t t);
+
+/* Reductions of the current state (device kernels, then a small copy).
+ * rho, j, e: optional host arrays of L int64 receiving the per-node raw
+ * moments sum_i n_i, sum_i v_i n_i, sum_i v_i^2 n_i (NULL to skip).
+ * nk <= ILG_MAX_K structure-factor modes are computed.  Syncs. */
+int ilg_moments(ilg_handle *h, int64_t *rho, int64_t *j, int64_t *e, uint32_t nk,
+                ilg_summary *out);
+
+/* Order-independent 64-bit hash of the current state.  Syncs. */
+int ilg_state_hash(ilg_handle *h, uint64_t *out);
+
+/* Absolute index of the next step. */
+uint64_t ilg_current_step(const ilg_handle *h);
+
+/* Wait for the handle's work, report sticky errors, free what it owns. */
+int ilg_destroy(ilg_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ILG_H */

@@ -1,0 +1,218 @@
+"""ctypes binding of libilg.so (include/ilg.h).
+
+Argument marshalling only: every step of the lattice-gas path runs in the HIP
+kernels of libilg.so.  PyTorch supplies device memory and streams.  If the
+library is not built this module raises at import time; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libilg.so")
+
+ABI_VERSION = 1
+MAX_K = 64
+TABLE_ENTRIES = 2080
+FLIP_MODES = {"auto": 0, "off": 1, "on": 2}
+STATUS = {0: "ILG_OK", -1: "ILG_E_INVALID", -2: "ILG_E_NOMEM", -3: "ILG_E_DEVICE",
+          -4: "ILG_E_OVERFLOW", -5: "ILG_E_RANGE", -6: "ILG_E_BUSY"}
+
+
+class IlgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class IlgConfig(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("q", ctypes.c_uint32),
+                ("count_bytes", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("length", ctypes.c_uint64), ("omega", ctypes.c_double),
+                ("theta", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("realization", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("t0", ctypes.c_uint64)]
+
+
+class IlgFixed(ctypes.Structure):
+    _fields_ = [("flip", ctypes.c_uint32), ("q", ctypes.c_uint32), ("p", ctypes.c_uint64),
+                ("p_half", ctypes.c_uint64), ("p_rest", ctypes.c_uint64),
+                ("omega_star", ctypes.c_double)]
+
+
+class IlgSummary(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_uint64), ("step", ctypes.c_uint64), ("hash", ctypes.c_uint64),
+                ("amplitude", ctypes.c_double), ("nk", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("sk", ctypes.c_double * MAX_K)]
+
+
+def _load():
+    # torch ships a HIP runtime with the same SONAME as the system one; loading
+    # torch first makes libilg.so bind to that single runtime instance, so
+    # torch-allocated buffers and streams are valid in the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2203_01380_amd/build.py` "
+                          "(the lattice-gas path has no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    cfgp = ctypes.POINTER(IlgConfig)
+    hp = ctypes.c_void_p
+    sig = {
+        "ilg_last_error": ([], ctypes.c_char_p),
+        "ilg_fixed_point": ([cfgp, ctypes.POINTER(IlgFixed)], i32),
+        "ilg_binomial_table": ([u64, vp], i32),
+        "ilg_state_bytes": ([cfgp], u64),
+        "ilg_state_pitch": ([cfgp], u64),
+        "ilg_create": ([cfgp, vp, vp, ctypes.POINTER(hp)], i32),
+        "ilg_create_on": ([cfgp, vp, vp, vp, ctypes.POINTER(hp)], i32),
+        "ilg_state_device": ([hp], vp),
+        "ilg_step": ([hp, u64], i32),
+        "ilg_get_state": ([hp, vp], i32),
+        "ilg_set_state": ([hp, vp, u64], i32),
+        "ilg_moments": ([hp, vp, vp, vp, u32, ctypes.POINTER(IlgSummary)], i32),
+        "ilg_state_hash": ([hp, ctypes.POINTER(u64)], i32),
+        "ilg_current_step": ([hp], u64),
+        "ilg_destroy": ([hp], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+lib = _load()
+
+
+def check(rc: int):
+    if rc != 0:
+        raise IlgError(rc, lib.ilg_last_error().decode())
+
+
+def make_config(q: int, length: int, count_bytes: int, omega: float, seed: int,
+                realization: int = 0, t0: int = 0, theta: float = 0.0,
+                flip: str = "auto") -> IlgConfig:
+    return IlgConfig(ABI_VERSION, q, count_bytes, FLIP_MODES[flip], length, omega, theta, seed,
+                     realization, 0, t0)
+
+
+def fixed_point(cfg: IlgConfig) -> IlgFixed:
+    out = IlgFixed()
+    check(lib.ilg_fixed_point(ctypes.byref(cfg), ctypes.byref(out)))
+    return out
+
+
+def binomial_table(p: int) -> np.ndarray:
+    out = np.zeros(TABLE_ENTRIES, dtype=np.uint32)
+    check(lib.ilg_binomial_table(p, out.ctypes.data))
+    return out
+
+
+def _dtype(count_bytes: int):
+    return np.uint16 if count_bytes == 2 else np.uint32
+
+
+class Lattice:
+    """One periodic lattice on the GPU.
+
+    By default the two state buffers are torch CUDA tensors (ilg_create_on)
+    and work is enqueued on torch's current stream; with use_torch=False the
+    library allocates them itself (ilg_create)."""
+
+    def __init__(self, q: int, length: int, count_bytes: int, omega: float, seed: int,
+                 init: np.ndarray, realization: int = 0, t0: int = 0, theta: float = 0.0,
+                 flip: str = "auto", use_torch: bool = True, stream=None):
+        self.cfg = make_config(q, length, count_bytes, omega, seed, realization, t0, theta, flip)
+        self.q, self.length, self.count_bytes = q, length, count_bytes
+        init = np.ascontiguousarray(init, dtype=_dtype(count_bytes))
+        if init.shape != (q, length):
+            raise ValueError(f"init must have shape {(q, length)}, got {init.shape}")
+        self._h = ctypes.c_void_p()
+        self._bufs = None
+        if use_torch:
+            import torch
+            if stream is None:
+                stream = torch.cuda.current_stream()
+            self._stream = stream
+            nbytes = int(lib.ilg_state_bytes(ctypes.byref(self.cfg)))
+            pitch = int(lib.ilg_state_pitch(ctypes.byref(self.cfg)))
+            padded = np.zeros((q, pitch), dtype=init.dtype)
+            padded[:, :length] = init
+            host = torch.from_numpy(padded.view(np.uint8).reshape(-1))
+            b0 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            b1 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            with torch.cuda.stream(stream):
+                b0.copy_(host)
+            stream.synchronize()
+            self._bufs = (b0, b1)
+            check(lib.ilg_create_on(ctypes.byref(self.cfg), ctypes.c_void_p(b0.data_ptr()),
+                                    ctypes.c_void_p(b1.data_ptr()),
+                                    ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._h)))
+        else:
+            self._stream = None
+            sp = None if stream is None else ctypes.c_void_p(int(stream))
+            check(lib.ilg_create(ctypes.byref(self.cfg), init.ctypes.data, sp,
+                                 ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def step(self, nsteps: int = 1):
+        check(lib.ilg_step(self._h, nsteps))
+
+    @property
+    def t(self) -> int:
+        return int(lib.ilg_current_step(self._h))
+
+    def state(self) -> np.ndarray:
+        out = np.empty((self.q, self.length), dtype=_dtype(self.count_bytes))
+        check(lib.ilg_get_state(self._h, out.ctypes.data))
+        return out
+
+    def set_state(self, state: np.ndarray, t: int):
+        s = np.ascontiguousarray(state, dtype=_dtype(self.count_bytes))
+        check(lib.ilg_set_state(self._h, s.ctypes.data, t))
+
+    def hash(self) -> int:
+        out = ctypes.c_uint64()
+        check(lib.ilg_state_hash(self._h, ctypes.byref(out)))
+        return int(out.value)
+
+    def moments(self, per_node: bool = False, nk: int = 0) -> dict:
+        s = IlgSummary()
+        arrs = [np.empty(self.length, dtype=np.int64) for _ in range(3)] if per_node else None
+        ptrs = [a.ctypes.data for a in arrs] if per_node else [None, None, None]
+        check(lib.ilg_moments(self._h, *ptrs, nk, ctypes.byref(s)))
+        out = dict(mass=int(s.mass), step=int(s.step), hash=int(s.hash),
+                   amplitude=float(s.amplitude), sk=np.array(s.sk[:nk], dtype=np.float64))
+        if per_node:
+            out.update(rho=arrs[0], j=arrs[1], e=arrs[2])
+        return out
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, ctypes.c_void_p()
+            check(lib.ilg_destroy(h))
+        self._bufs = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib.ilg_destroy(self._h)
+        except Exception:
+            pass

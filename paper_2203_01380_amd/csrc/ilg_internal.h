@@ -1,0 +1,95 @@
+// Internal declarations shared by the runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ilg {
+
+// Binomial draws work on chunks of at most 64 trials; a fixed-point CDF table
+// holds rows m = 1..64 with m entries each, row m at offset (m-1)m/2.
+constexpr int kChunk = 64;
+constexpr int kTableEntries = kChunk * (kChunk + 1) / 2;  // 2080
+// Guide tables for the inverse-CDF search: for row m and bucket b (the top
+// kGuideBits bits of the draw), the number of row entries <= b << (32 - bits).
+constexpr int kGuideBits = 6;
+constexpr int kGuideBuckets = 1 << kGuideBits;
+constexpr int kGuideEntries = kChunk * kGuideBuckets;  // bytes per table
+// A "table set" holds the removal table (P), the half table (P = 2^31) and the
+// rest table (P = (1-theta) 2^32) with their guides, contiguous on the device.
+constexpr int kTablesPerSet = 3;
+constexpr size_t kTableSetBytes =
+    kTablesPerSet * (kTableEntries * sizeof(uint32_t) + kGuideEntries);
+enum TableId : int { kTabP = 0, kTabHalf = 1, kTabRest = 2 };
+
+__host__ __device__ inline const uint32_t *table_ptr(const void *set, int id)
+{
+    return reinterpret_cast<const uint32_t *>(set) + id * kTableEntries;
+}
+__host__ __device__ inline const uint8_t *guide_ptr(const void *set, int id)
+{
+    return reinterpret_cast<const uint8_t *>(set) +
+           kTablesPerSet * kTableEntries * sizeof(uint32_t) + id * kGuideEntries;
+}
+
+// Host: exact fixed-point tables (multiword integer arithmetic) and guides.
+void build_binomial_table(uint64_t p, uint32_t *out);
+void build_guide(const uint32_t *table, uint8_t *guide);
+// Fill a host table set for (p, p_rest); p = 0 leaves the P table zeroed
+// (the kernels never read it then).
+void build_table_set(uint64_t p, uint64_t p_rest, void *host_set);
+
+struct Fixed {
+    int flip;
+    uint64_t p, p_half, p_rest;
+    double omega_star;
+};
+
+// Arguments of one lattice step (one launch).
+struct StepArgs {
+    const void *in;        // [q][pitch] counts at step t
+    void *out;             // [q][pitch] counts at step t+1
+    uint64_t pitch;
+    uint32_t length;
+    uint32_t t;            // absolute step index being taken
+    uint32_t realization;
+    uint32_t key0, key1;   // Philox key
+    uint32_t flip;
+    uint32_t p_zero;       // collision fraction is exactly 0
+    const void *tables;    // device table set
+    uint32_t *err;         // sticky error word (bit 0: overflow)
+};
+
+// Launch one step of a q-velocity, count_bytes lattice on stream.
+hipError_t launch_step(int q, int count_bytes, const StepArgs &a, hipStream_t stream);
+
+// Diagnostics of one state.
+struct DiagArgs {
+    const void *state;
+    uint64_t pitch;
+    uint32_t length;
+    uint32_t q;
+    uint32_t count_bytes;
+    uint32_t nk;
+    int64_t *rho, *j, *e;  // device per-node moments or null
+    void *partials;        // device scratch, diag_partials_bytes(nk) per block
+    void *result;          // device DiagResult
+};
+
+struct DiagResult {
+    uint64_t mass;
+    uint64_t hash;
+    double sin_num;        // sum_x sin(2 pi x/L) N(x)
+    double sin_den;        // sum_x sin^2(2 pi x/L)
+    double mass_f;
+    double sk_re[64];
+    double sk_im[64];
+};
+
+constexpr int kDiagBlocks = 512;
+size_t diag_partials_bytes();
+hipError_t launch_diag(const DiagArgs &a, hipStream_t stream);
+
+int device_cu_count();
+
+}  // namespace ilg
