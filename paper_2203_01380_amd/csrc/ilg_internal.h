@@ -12,7 +12,8 @@ constexpr int kChunk = 64;
 constexpr int kTableEntries = kChunk * (kChunk + 1) / 2;  // 2080
 // Guide tables for the inverse-CDF search: for row m and bucket b (the top
 // kGuideBits bits of the draw), the number of row entries <= b << (32 - bits).
-constexpr int kGuideBits = 6;
+// Kernels may stage a coarser view (every 2^k-th bucket) in LDS.
+constexpr int kGuideBits = 8;
 constexpr int kGuideBuckets = 1 << kGuideBits;
 constexpr int kGuideEntries = kChunk * kGuideBuckets;  // bytes per table
 // A "table set" holds the removal table (P), the half table (P = 2^31) and the
