@@ -158,6 +158,62 @@ uint64_t ilg_current_step(const ilg_handle *h);
 /* Wait for the handle's work, report sticky errors, free what it owns. */
 int ilg_destroy(ilg_handle *h);
 
+
+/* ------------------------------------------------------------------------
+ * Batched ensembles: many independent realizations (the ensemble average of
+ * the Integer Lattice Gas section), each with its own length, relaxation
+ * rate, seed, realization id and start step, advanced by one persistent
+ * launch captured in a HIP graph.  All members share q, count_bytes and
+ * theta.  Every member's result is bit-identical to the same configuration
+ * run alone through ilg_create/ilg_step (draws depend only on the member's
+ * own seed, realization, step and node).
+ * ---------------------------------------------------------------------- */
+#define ILG_BATCH_MAX_K 16u
+
+typedef struct ilg_batch ilg_batch; /* opaque; owned by the library */
+
+typedef struct ilg_batch_diag {
+    uint32_t sk_every;  /* add S(k), k = 1..nk, to each member's sum every
+                           sk_every steps of its own step count (0: off) */
+    uint32_t nk;        /* 1..ILG_BATCH_MAX_K when sk_every > 0 */
+    uint32_t amp_every; /* record A^LG every amp_every steps (0: off) */
+    uint32_t max_amp;   /* capacity of each member's amplitude series */
+} ilg_batch_diag;
+
+/* cfgs[nreal] and inits[nreal] (host [q][L_r] compact counts, copied before
+ * return).  diag may be NULL (no diagnostics). */
+int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *inits,
+                     const ilg_batch_diag *diag, void *stream, ilg_batch **out);
+
+/* Advance every member by nsteps: one persistent launch (members taken
+ * longest first from a device queue), replayed from a HIP graph. */
+int ilg_batch_run(ilg_batch *b, uint64_t nsteps);
+
+/* Autotuner: time each launch shape for tune_steps steps on a scratch copy of
+ * the ensemble (the ensemble itself is not advanced) and keep the fastest for
+ * later ilg_batch_run calls.  *chosen (nullable) receives the shape index.
+ * Shapes differ only in speed, never in results.  Syncs. */
+int ilg_batch_tune(ilg_batch *b, uint32_t tune_steps, uint32_t *chosen);
+
+/* Launch shape used by later ilg_batch_run calls (an index below
+ * ilg_batch_shape_count(); shapes differ only in speed, never in results). */
+int ilg_batch_set_shape(ilg_batch *b, uint32_t shape);
+uint32_t ilg_batch_shape_count(void);
+
+/* Member r's state as host [q][L_r] counts.  Syncs. */
+int ilg_batch_get_state(ilg_batch *b, uint32_t r, void *host_out);
+
+/* Sum over samples of S(k) (sk_sum[nreal][nk]) and the sample counts
+ * (count[nreal]); host arrays.  Syncs. */
+int ilg_batch_structure_factor(ilg_batch *b, double *sk_sum, uint64_t *count);
+
+/* Recorded A^LG series (amp[nreal][max_amp]) and their lengths
+ * (count[nreal]); host arrays.  Syncs. */
+int ilg_batch_amplitudes(ilg_batch *b, double *amp, uint32_t *count);
+
+/* Wait for the batch's work, report sticky errors, free what it owns. */
+int ilg_batch_destroy(ilg_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

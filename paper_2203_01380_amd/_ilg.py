@@ -50,6 +50,14 @@ class IlgSummary(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("sk", ctypes.c_double * MAX_K)]
 
 
+class IlgBatchDiag(ctypes.Structure):
+    _fields_ = [("sk_every", ctypes.c_uint32), ("nk", ctypes.c_uint32),
+                ("amp_every", ctypes.c_uint32), ("max_amp", ctypes.c_uint32)]
+
+
+BATCH_MAX_K = 16
+
+
 def _load():
     # torch ships a HIP runtime with the same SONAME as the system one; loading
     # torch first makes libilg.so bind to that single runtime instance, so
@@ -81,6 +89,16 @@ def _load():
         "ilg_state_hash": ([hp, ctypes.POINTER(u64)], i32),
         "ilg_current_step": ([hp], u64),
         "ilg_destroy": ([hp], i32),
+        "ilg_batch_create": ([cfgp, u32, ctypes.POINTER(ctypes.c_void_p),
+                              ctypes.POINTER(IlgBatchDiag), vp, ctypes.POINTER(hp)], i32),
+        "ilg_batch_run": ([hp, u64], i32),
+        "ilg_batch_tune": ([hp, u32, ctypes.POINTER(u32)], i32),
+        "ilg_batch_set_shape": ([hp, u32], i32),
+        "ilg_batch_shape_count": ([], u32),
+        "ilg_batch_get_state": ([hp, u32, vp], i32),
+        "ilg_batch_structure_factor": ([hp, vp, vp], i32),
+        "ilg_batch_amplitudes": ([hp, vp, vp], i32),
+        "ilg_batch_destroy": ([hp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -214,5 +232,95 @@ class Lattice:
         try:
             if self._h:
                 lib.ilg_destroy(self._h)
+        except Exception:
+            pass
+
+
+class Batch:
+    """An ensemble of independent lattices advanced by one persistent launch.
+
+    members: sequence of dicts with keys q, length, count_bytes, omega, seed
+    and optionally realization, t0, theta, flip; inits: matching [q][L]
+    arrays.  Work goes to torch's current stream unless `stream` is given."""
+
+    def __init__(self, members, inits, sk_every: int = 0, nk: int = 0, amp_every: int = 0,
+                 max_amp: int = 0, stream=None):
+        n = len(members)
+        if n == 0 or len(inits) != n:
+            raise ValueError("need one initial state per member")
+        cfgs = (IlgConfig * n)()
+        keep = []
+        ptrs = (ctypes.c_void_p * n)()
+        for r, (m, init) in enumerate(zip(members, inits)):
+            cfgs[r] = make_config(m["q"], m["length"], m["count_bytes"], m["omega"], m["seed"],
+                                  m.get("realization", 0), m.get("t0", 0), m.get("theta", 0.0),
+                                  m.get("flip", "auto"))
+            a = np.ascontiguousarray(init, dtype=_dtype(m["count_bytes"]))
+            if a.shape != (m["q"], m["length"]):
+                raise ValueError(f"member {r}: init shape {a.shape}")
+            keep.append(a)
+            ptrs[r] = a.ctypes.data
+        self.members = [dict(m) for m in members]
+        self.nreal = n
+        self.q, self.count_bytes = members[0]["q"], members[0]["count_bytes"]
+        self.nk = nk if sk_every else 0
+        self.max_amp = max_amp if amp_every else 0
+        diag = IlgBatchDiag(sk_every, nk, amp_every, max_amp)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        self._h = ctypes.c_void_p()
+        check(lib.ilg_batch_create(cfgs, n, ptrs, ctypes.byref(diag),
+                                   ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._h)))
+
+    def run(self, nsteps: int):
+        check(lib.ilg_batch_run(self._h, nsteps))
+
+    def tune(self, steps: int = 20) -> int:
+        out = ctypes.c_uint32()
+        check(lib.ilg_batch_tune(self._h, steps, ctypes.byref(out)))
+        return int(out.value)
+
+    def set_shape(self, shape: int):
+        check(lib.ilg_batch_set_shape(self._h, shape))
+
+    @staticmethod
+    def shape_count() -> int:
+        return int(lib.ilg_batch_shape_count())
+
+    def state(self, r: int) -> np.ndarray:
+        m = self.members[r]
+        out = np.empty((m["q"], m["length"]), dtype=_dtype(m["count_bytes"]))
+        check(lib.ilg_batch_get_state(self._h, r, out.ctypes.data))
+        return out
+
+    def structure_factor(self):
+        sums = np.zeros((self.nreal, max(self.nk, 1)), dtype=np.float64)
+        cnt = np.zeros(self.nreal, dtype=np.uint64)
+        check(lib.ilg_batch_structure_factor(self._h, sums.ctypes.data, cnt.ctypes.data))
+        return sums[:, :self.nk], cnt
+
+    def amplitudes(self):
+        amp = np.zeros((self.nreal, max(self.max_amp, 1)), dtype=np.float64)
+        cnt = np.zeros(self.nreal, dtype=np.uint32)
+        check(lib.ilg_batch_amplitudes(self._h, amp.ctypes.data, cnt.ctypes.data))
+        return amp[:, :self.max_amp], cnt
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, ctypes.c_void_p()
+            check(lib.ilg_batch_destroy(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib.ilg_batch_destroy(self._h)
         except Exception:
             pass

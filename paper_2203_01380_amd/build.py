@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libilg.so")
 ARCH = os.environ.get("ILG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["runtime.cpp", "tables.cpp", "step.hip", "diag.hip"]
+SOURCES = ["runtime.cpp", "tables.cpp", "batch_runtime.cpp", "step.hip", "diag.hip", "batch.hip"]
 
 
 def hipcc() -> str:

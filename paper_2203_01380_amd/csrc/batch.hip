@@ -1,0 +1,342 @@
+// Batched ensembles in one persistent launch.
+//
+// Independent realizations (the ensemble of the Boltzmann average,
+// f_i = <n_i>) each advance nsteps steps of the lattice gas with flip
+// (Eq. LGflip).  Each workgroup repeatedly takes the next member from a device
+// queue (members sorted longest first, so the long ones start early and the
+// short ones fill the tail), stages that member's removal table in LDS, builds
+// its guide, and runs all of the member's steps with one workgroup barrier
+// per step.  The member's double-buffered state lives in its slice of the HBM
+// arena; at these sizes (tens of KB per member) it stays resident in L2 and
+// the MALL while the member runs, so LDS holds only tables and several
+// workgroups fit on a CU.  The per-node update is the same code as the plain
+// kernel (sampler.h), so every member is bit-identical to a plain run.
+//
+// Diagnostics on the member's own step clock: every sk_every steps the
+// structure factor S(k) = |sum_x N(x) e^{-2 pi i k x/L}|^2 / sum_x N(x),
+// k = 1..nk, is added to the member's sums (FP64; the phase e^{-2 pi i x/L}
+// comes from sincospi and its powers by complex multiplication); every
+// amp_every steps A^LG = sum_x sin(2 pi x/L) N(x) / sum_x sin^2(2 pi x/L)
+// (Results section) is appended to the member's series.
+#include "ilg_internal.h"
+#include "sampler.h"
+
+namespace ilg {
+
+namespace {
+
+using sampler::Wide;
+
+template <int BLOCK>
+__device__ __forceinline__ double block_sum_d(double v, double *scratch)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+        scratch[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < BLOCK / 64; ++w)
+            r += scratch[w];
+    __syncthreads();
+    return r;  // valid in thread 0
+}
+
+template <int BLOCK>
+__device__ __forceinline__ unsigned long long block_sum_u(unsigned long long v,
+                                                          unsigned long long *scratch)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+        scratch[wid] = v;
+    __syncthreads();
+    unsigned long long r = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < BLOCK / 64; ++w)
+            r += scratch[w];
+    __syncthreads();
+    return r;
+}
+
+// Guide of one LDS table: entry (m, b) = #{j < m : T[m][j] <= b << (32 - GB)},
+// by binary search on the nondecreasing row.
+template <int GB, int BLOCK>
+__device__ __forceinline__ void build_guide_lds(const uint32_t *tab, uint8_t *guide)
+{
+    constexpr int kRow = 1 << GB;
+    for (int e = threadIdx.x; e < kChunk * kRow; e += BLOCK) {
+        const uint32_t m = (uint32_t)(e >> GB) + 1u;
+        const uint32_t edge = (uint32_t)(e & (kRow - 1)) << (32 - GB);
+        const uint32_t *row = tab + (((m - 1u) * m) >> 1);
+        uint32_t lo = 0, hi = m;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (row[mid] <= edge)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        guide[e] = (uint8_t)lo;
+    }
+}
+
+// Adds S(k), k = 1..nk, of the state st to member r's sums.  Modes are
+// accumulated kModesPerPass at a time (each pass re-reads N(x) from L2) to
+// bound the number of live FP64 accumulators.
+template <int Q, typename T, int BLOCK>
+__device__ __forceinline__ void sk_sample(const BatchArgs &a, uint32_t r, const T *st, uint32_t L,
+                                       uint64_t pitch, double *s_red, unsigned long long *s_redu)
+{
+    constexpr int kModesPerPass = 8;
+    unsigned long long mass = 0;
+    for (uint32_t x = threadIdx.x; x < L; x += BLOCK)
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            mass += st[(uint64_t)i * pitch + x];
+    const unsigned long long tot = block_sum_u<BLOCK>(mass, s_redu);
+    for (uint32_t k0 = 0; k0 < a.nk; k0 += kModesPerPass) {
+        double re[kModesPerPass], im[kModesPerPass];
+#pragma unroll
+        for (int k = 0; k < kModesPerPass; ++k)
+            re[k] = im[k] = 0.0;
+        for (uint32_t x = threadIdx.x; x < L; x += BLOCK) {
+            uint64_t N = 0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                N += st[(uint64_t)i * pitch + x];
+            const double Nd = (double)N;
+            double sv, cv;
+            sincospi(2.0 * (double)x / (double)L, &sv, &cv);
+            const double zr = cv, zi = -sv;  // e^{-2 pi i x / L}
+            // p = z^(k0 + 1) by repeated multiplication, then successive powers
+            double pr = zr, pim = zi;
+            for (uint32_t e = 0; e < k0; ++e) {
+                const double nr = pr * zr - pim * zi;
+                pim = pr * zi + pim * zr;
+                pr = nr;
+            }
+#pragma unroll
+            for (int k = 0; k < kModesPerPass; ++k) {
+                re[k] += Nd * pr;
+                im[k] += Nd * pim;
+                const double nr = pr * zr - pim * zi;
+                pim = pr * zi + pim * zr;
+                pr = nr;
+            }
+        }
+        for (int k = 0; k < kModesPerPass; ++k) {
+            if (k0 + k >= a.nk)
+                break;
+            const double fr = block_sum_d<BLOCK>(re[k], s_red);
+            const double fi = block_sum_d<BLOCK>(im[k], s_red);
+            if (threadIdx.x == 0 && tot > 0)
+                a.sk_sum[(size_t)r * a.nk + k0 + k] += (fr * fr + fi * fi) / (double)tot;
+        }
+    }
+    if (threadIdx.x == 0)
+        a.sk_cnt[r] += 1ull;
+}
+
+// The diagnostics (FP64 phases) need about twice the registers of the step
+// loop; the occupancy attribute caps the register count so that the rare
+// diagnostic code spills instead of the step loop losing waves.
+template <int Q, typename T, int BLOCK, int GB>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void batch_kernel(
+    BatchArgs a)
+{
+    using W = typename Wide<T>::type;
+    constexpr int NB = (Q == 3) ? 2 : 1;
+    constexpr int kTabs = (Q == 3) ? 3 : 2;
+    constexpr int kRowGuide = 1 << GB;
+    constexpr int kG = kChunk * kRowGuide;
+    constexpr int kWaves = BLOCK / 64;
+    __shared__ uint32_t s_tab[kTabs * kTableEntries];
+    __shared__ uint8_t s_guide[kTabs * kG];
+    __shared__ uint32_t s_next;
+    __shared__ double s_red[kWaves];
+    __shared__ unsigned long long s_redu[kWaves];
+
+    // Shared tables (P = 2^31 and, for q = 3, P_rest) and their guides, once.
+    for (int i = threadIdx.x; i < (kTabs - 1) * kTableEntries; i += BLOCK)
+        s_tab[kTableEntries + i] = a.tabs_shared[i];
+    __syncthreads();
+    for (int s = 1; s < kTabs; ++s)
+        build_guide_lds<GB, BLOCK>(s_tab + s * kTableEntries, s_guide + s * kG);
+
+    const uint32_t *tab_p = s_tab, *tab_half = s_tab + kTableEntries;
+    const uint32_t *tab_rest = s_tab + 2 * kTableEntries;
+    const uint8_t *g_p = s_guide, *g_half = s_guide + kG, *g_rest = s_guide + 2 * kG;
+    constexpr W kMax = (W)(T)~(T)0;
+    bool overflow = false;
+
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_next = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const uint32_t idx = s_next;
+        if (idx >= a.nreal)
+            break;
+        const uint32_t r = a.order[idx];
+        const BatchMeta m = a.meta[r];
+        const bool p_zero = m.p_zero != 0;
+        const bool flip = m.flip != 0;
+        if (!p_zero) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.tabs_p + (size_t)r * kTableEntries);
+            uint4 *dst = reinterpret_cast<uint4 *>(s_tab);
+            for (int i = threadIdx.x; i < kTableEntries / 4; i += BLOCK)
+                dst[i] = src[i];
+            __syncthreads();
+            build_guide_lds<GB, BLOCK>(s_tab, s_guide);
+        }
+        __syncthreads();
+
+        const uint32_t L = m.length;
+        const uint64_t pitch = m.pitch, qp = (uint64_t)Q * m.pitch;
+        T *base = reinterpret_cast<T *>(a.arena) + m.off;
+        uint32_t cur = m.cur;
+        for (uint32_t s = 0; s < a.nsteps; ++s) {
+            const T *in = base + cur * qp;
+            T *out = base + (cur ^ 1u) * qp;
+            const uint32_t t = m.t + s;
+            for (uint32_t x = threadIdx.x; x < L; x += BLOCK) {
+                W av[Q], cn[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    av[i] = (W)in[(uint64_t)(flip ? Q - 1 - i : i) * pitch + x];
+                sampler::node_update<Q, W, NB, GB>(av, cn, x, t, m.realization, m.key0, m.key1,
+                                                   tab_p, g_p, tab_half, g_half, tab_rest, g_rest,
+                                                   p_zero);
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    overflow |= cn[i] > kMax;
+                const uint32_t xm = (x == 0) ? L - 1 : x - 1;
+                const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+                out[xm] = (T)cn[0];
+                out[(uint64_t)(Q - 1) * pitch + xp] = (T)cn[Q - 1];
+                if constexpr (Q == 3)
+                    out[pitch + x] = (T)cn[1];
+            }
+            __syncthreads();
+            cur ^= 1u;
+            const uint32_t t_after = t + 1u;
+            const T *st = base + cur * qp;
+            if (a.sk_every != 0 && t_after % a.sk_every == 0)
+                sk_sample<Q, T, BLOCK>(a, r, st, L, pitch, s_red, s_redu);
+            if (a.amp_every != 0 && t_after % a.amp_every == 0) {
+                double num = 0.0, den = 0.0;
+                for (uint32_t x = threadIdx.x; x < L; x += BLOCK) {
+                    uint64_t N = 0;
+#pragma unroll
+                    for (int i = 0; i < Q; ++i)
+                        N += st[(uint64_t)i * pitch + x];
+                    const double sv = sinpi(2.0 * (double)x / (double)L);
+                    num += sv * (double)N;
+                    den += sv * sv;
+                }
+                const double tn = block_sum_d<BLOCK>(num, s_red);
+                const double td = block_sum_d<BLOCK>(den, s_red);
+                if (threadIdx.x == 0) {
+                    const uint32_t c = a.amp_cnt[r];
+                    if (c < a.max_amp)
+                        a.amp[(size_t)r * a.max_amp + c] = td > 0.0 ? tn / td : 0.0;
+                    a.amp_cnt[r] = c + 1u;
+                }
+            }
+        }
+        if (threadIdx.x == 0) {
+            a.meta[r].t = m.t + a.nsteps;
+            a.meta[r].cur = cur;
+        }
+    }
+    if (overflow)
+        atomicOr(a.err, 1u);
+}
+
+__global__ void batch_reset_kernel(uint32_t *queue)
+{
+    if (threadIdx.x == 0)
+        *queue = 0u;
+}
+
+struct Shape {
+    int block;
+    int wg_per_cu_q2;
+    int wg_per_cu_q3;
+};
+// LDS per workgroup: q = 2 about 17 KB, q = 3 about 37 KB (tables + 64-bucket
+// guides), so LDS allows up to 9 (q = 2) or 4 (q = 3) workgroups per CU.
+constexpr Shape kShapes[] = {{256, 6, 4}, {512, 3, 2}, {1024, 2, 2}, {128, 8, 4}};
+
+template <int Q, typename T, int BLOCK>
+hipError_t launch_shape(const BatchArgs &a, hipStream_t stream, int wg_per_cu)
+{
+    static int cus = 0;
+    if (cus == 0)
+        cus = device_cu_count();
+    uint32_t grid = (uint32_t)cus * (uint32_t)wg_per_cu;
+    if (grid > a.nreal)
+        grid = a.nreal;
+    if (grid == 0)
+        grid = 1;
+    hipLaunchKernelGGL((batch_kernel<Q, T, BLOCK, kBatchGuideBits>), dim3(grid), dim3(BLOCK), 0,
+                       stream, a);
+    return hipGetLastError();
+}
+
+template <int Q, typename T>
+hipError_t launch_qt(int shape, const BatchArgs &a, hipStream_t stream)
+{
+    const Shape &s = kShapes[shape];
+    const int wg = (Q == 3) ? s.wg_per_cu_q3 : s.wg_per_cu_q2;
+    switch (s.block) {
+    case 128:
+        return launch_shape<Q, T, 128>(a, stream, wg);
+    case 512:
+        return launch_shape<Q, T, 512>(a, stream, wg);
+    case 1024:
+        return launch_shape<Q, T, 1024>(a, stream, wg);
+    default:
+        return launch_shape<Q, T, 256>(a, stream, wg);
+    }
+}
+
+}  // namespace
+
+int batch_shape_count()
+{
+    return (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+}
+
+void batch_shape(int shape, int q, int *block, int *wg_per_cu)
+{
+    *block = kShapes[shape].block;
+    *wg_per_cu = q == 3 ? kShapes[shape].wg_per_cu_q3 : kShapes[shape].wg_per_cu_q2;
+}
+
+hipError_t launch_batch_reset(uint32_t *queue, hipStream_t stream)
+{
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(int q, int count_bytes, int shape, const BatchArgs &a, hipStream_t stream)
+{
+    if (shape < 0 || shape >= batch_shape_count())
+        return hipErrorInvalidValue;
+    if (q == 2 && count_bytes == 2)
+        return launch_qt<2, uint16_t>(shape, a, stream);
+    if (q == 2 && count_bytes == 4)
+        return launch_qt<2, uint32_t>(shape, a, stream);
+    if (q == 3 && count_bytes == 2)
+        return launch_qt<3, uint16_t>(shape, a, stream);
+    if (q == 3 && count_bytes == 4)
+        return launch_qt<3, uint32_t>(shape, a, stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ilg

@@ -3,6 +3,9 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <string>
+
+#include "ilg.h"
 
 namespace ilg {
 
@@ -91,6 +94,49 @@ constexpr int kDiagBlocks = 512;
 size_t diag_partials_bytes();
 hipError_t launch_diag(const DiagArgs &a, hipStream_t stream);
 
+// Compute units of the current device (cached after the first call).
 int device_cu_count();
+// Validation and fixed-point parameters of a configuration (runtime.cpp).
+int check_config(const struct ilg_config *cfg, Fixed *fx);
+// Message returned by ilg_last_error() on this thread.
+void set_last_error(const std::string &msg);
+
+// ---------------------------------------------------------------- batched
+// One ensemble member: its buffer pair in the arena and its draw keys.
+struct BatchMeta {
+    uint64_t off;          // element offset of buffer 0; buffer 1 follows at q*pitch
+    uint32_t length, pitch;
+    uint32_t t;            // absolute index of the next step
+    uint32_t realization, key0, key1;
+    uint32_t flip, p_zero;
+    uint32_t cur;          // which buffer holds the current state
+    uint32_t pad;
+};
+
+constexpr int kBatchMaxK = 16;
+constexpr int kBatchGuideBits = 6;
+
+struct BatchArgs {
+    void *arena;
+    BatchMeta *meta;
+    const uint32_t *tabs_p;       // [nreal][kTableEntries] removal tables
+    const uint32_t *tabs_shared;  // [2][kTableEntries]: P = 2^31, P = P_rest
+    const uint32_t *order;        // members, longest first
+    uint32_t *queue;              // next index into order
+    uint32_t nreal;
+    uint32_t nsteps;
+    uint32_t sk_every, nk, amp_every, max_amp;
+    double *sk_sum;               // [nreal][nk]
+    unsigned long long *sk_cnt;   // [nreal]
+    double *amp;                  // [nreal][max_amp]
+    uint32_t *amp_cnt;            // [nreal]
+    uint32_t *err;
+};
+
+int batch_shape_count();
+// Launch geometry of a shape: threads per workgroup and workgroups per CU.
+void batch_shape(int shape, int q, int *block, int *wg_per_cu);
+hipError_t launch_batch_reset(uint32_t *queue, hipStream_t stream);
+hipError_t launch_batch(int q, int count_bytes, int shape, const BatchArgs &a, hipStream_t stream);
 
 }  // namespace ilg

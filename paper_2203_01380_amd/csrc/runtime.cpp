@@ -61,13 +61,21 @@ namespace ilg {
 
 int device_cu_count()
 {
+    static int cached = 0;
+    if (cached > 0)
+        return cached;
     int dev = 0, n = 0;
-    if (hipGetDevice(&dev) != hipSuccess)
-        return 256;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         n <= 0)
-        return 256;
+        n = 256;
+    cached = n;
     return n;
+}
+
+void set_last_error(const std::string &msg)
+{
+    g_last_error = msg;
 }
 
 // Validates cfg and derives the fixed-point parameters (Over-relaxation

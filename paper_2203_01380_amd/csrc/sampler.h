@@ -1,0 +1,299 @@
+// Device-side sampler shared by the plain and batched lattice-gas kernels:
+// Philox draws of one node-step, the chunked fixed-point binomial, and the
+// node update (flip, removal binomials, multinomial redistribution).
+//
+// Per node x at step t (Eq. LGflip):
+//   a_i   = n_{q-1-i}(x) if the flip is on, else n_i(x)          (Eq. flip)
+//   k_i   = Bin(a_i, P)          removal: each particle collides w.p. P/2^32
+//   M     = sum_i k_i
+//   q = 2: m_0 = Bin(M, 2^31), m_1 = M - m_0
+//   q = 3: m_1 = Bin(M, P_rest), R = M - m_1, m_0 = Bin(R, 2^31), m_2 = R - m_0
+//   c_i   = a_i - k_i + m_i   (streamed afterwards to x + v_i)
+// Bin(n, p) takes ceil(n/64) 32-bit draws (full chunks of 64 first, then the
+// remainder); a chunk of m trials with draw U yields #{j < m : T[m][j] <= U}.
+// Draw j of a node-step is word j%4 of Philox4x32-10 block j/4 with counter
+// (x, t, realization, j/4).
+//
+// gfx950 notes.  The work is integer VALU bound (Philox rounds and the
+// inverse-CDF searches):
+//  * the search starts at a guide entry (2^GB buckets per row) and makes two
+//    table compares; longer scans run only for the lanes that need them;
+//  * one wave-uniform test per node selects straight-line code with constant
+//    draw-word indices when every lane shares the common chunk layout
+//    (node_fast); the generic path picks words by a scalar switch when the
+//    index is wave-uniform and by a select tree otherwise;
+//  * the first NB Philox blocks are computed up front, later ones on demand.
+#pragma once
+
+#include <type_traits>
+
+#include "ilg_internal.h"
+#include "philox.h"
+
+namespace ilg {
+namespace sampler {
+
+template <typename T, int N>
+struct alignas(N * sizeof(T)) VecT {
+    T v[N];
+};
+
+// Compile-time loop: f(std::integral_constant<int, K>) for K = B..E-1, so
+// register arrays are only ever indexed by constants.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+__device__ __forceinline__ bool wave_any(bool p)
+{
+    return __builtin_amdgcn_ballot_w64(p) != 0ull;
+}
+
+template <int NB>
+struct Draws {
+    uint32_t w[4 * NB];
+    uint32_t x, t, r, k0, k1;
+
+    __device__ __forceinline__ void init(uint32_t x_, uint32_t t_, uint32_t r_, uint32_t k0_,
+                                         uint32_t k1_)
+    {
+        x = x_; t = t_; r = r_; k0 = k0_; k1 = k1_;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const uint4 o = philox4x32_10(x, t, r, (uint32_t)b, k0, k1);
+            w[4 * b + 0] = o.x; w[4 * b + 1] = o.y; w[4 * b + 2] = o.z; w[4 * b + 3] = o.w;
+        }
+    }
+};
+
+__device__ __forceinline__ uint32_t pick4(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                          uint32_t s)
+{
+    const uint32_t lo = (s & 1u) ? b : a;
+    const uint32_t hi = (s & 1u) ? d : c;
+    return (s & 2u) ? hi : lo;
+}
+
+// Word j of the lane's draw stream (lanes may ask for different j).
+template <int NB>
+__device__ __forceinline__ uint32_t draw_word(const Draws<NB> &d, uint32_t j)
+{
+    constexpr uint32_t kEager = 4 * NB;
+    const uint32_t j0 = __builtin_amdgcn_readfirstlane(j);
+    uint32_t r;
+    if (!wave_any(j != j0) && j0 < kEager) {
+        // wave-uniform index: scalar branches pick the register
+        switch (j0) {
+        case 0: r = d.w[0]; break;
+        case 1: r = d.w[1]; break;
+        case 2: r = d.w[2]; break;
+        case 3: r = d.w[3]; break;
+        case 4: r = d.w[4 % kEager]; break;
+        case 5: r = d.w[5 % kEager]; break;
+        case 6: r = d.w[6 % kEager]; break;
+        default: r = d.w[kEager - 1]; break;
+        }
+    } else {
+        const uint32_t jc = j < kEager ? j : kEager - 1;
+        if constexpr (NB == 1) {
+            r = pick4(d.w[0], d.w[1], d.w[2], d.w[3], jc);
+        } else {
+            const uint32_t lo = pick4(d.w[0], d.w[1], d.w[2], d.w[3], jc & 3u);
+            const uint32_t hi = pick4(d.w[4], d.w[5], d.w[6], d.w[7], jc & 3u);
+            r = (jc & 4u) ? hi : lo;
+        }
+        if (wave_any(j >= kEager)) {
+            if (j >= kEager) {
+                const uint4 o = philox4x32_10(d.x, d.t, d.r, j >> 2, d.k0, d.k1);
+                r = pick4(o.x, o.y, o.z, o.w, j & 3u);
+            }
+        }
+    }
+    return r;
+}
+
+// Inverse-CDF count of one chunk of m >= 1 trials: #{j < m : row[j] <= u}.
+// The guide gives the count at the lower edge of u's bucket; rows are
+// nondecreasing, so counting continues from there to the first entry above u.
+template <int GB>
+__device__ __forceinline__ uint32_t chunk_count(const uint32_t *tab, const uint8_t *guide,
+                                                uint32_t m, uint32_t u)
+{
+    const uint32_t *row = tab + (((m - 1u) * m) >> 1);
+    const uint32_t g = guide[((m - 1u) << GB) + (u >> (32 - GB))];
+    // Two compares cover almost every lane: entries g and g+1 (clamped to the
+    // row; a clamped read is masked by the bound test).
+    const uint32_t t0 = row[g < m ? g : m - 1u];
+    const uint32_t t1 = row[g + 1u < m ? g + 1u : m - 1u];
+    const bool s0 = (g < m) && (t0 <= u);
+    const bool s1 = s0 && (g + 1u < m) && (t1 <= u);
+    uint32_t c = g + (s0 ? 1u : 0u) + (s1 ? 1u : 0u);
+    if (wave_any(s1)) {
+        bool go = s1;
+        while (go) {
+            go = (c < m) && (row[c] <= u);
+            c += go ? 1u : 0u;
+        }
+    }
+    return c;
+}
+
+// Bin(n, table) with the chunked rule, consuming draws from index j on.
+// p_zero: the probability is 0 (draws are still consumed).
+template <typename W, int NB, int GB>
+__device__ __forceinline__ W binomial(W n, uint32_t &j, const uint32_t *tab, const uint8_t *guide,
+                                      bool p_zero, const Draws<NB> &d)
+{
+    if (!wave_any(n > (W)kChunk)) {
+        // at most one chunk per lane
+        const bool has = n != 0;
+        const uint32_t u = draw_word<NB>(d, j);
+        j += has ? 1u : 0u;
+        if (p_zero)
+            return 0;
+        const uint32_t m = has ? (uint32_t)n : 1u;
+        const uint32_t c = chunk_count<GB>(tab, guide, m, u);
+        return has ? (W)c : (W)0;
+    }
+    W total = 0;
+    while (n > 0) {
+        const uint32_t m = n >= (W)kChunk ? (uint32_t)kChunk : (uint32_t)n;
+        const uint32_t u = draw_word<NB>(d, j);
+        ++j;
+        if (!p_zero)
+            total += chunk_count<GB>(tab, guide, m, u);
+        n -= m;
+    }
+    return total;
+}
+
+// One chunk whose draw word is known: m in [0, 64] trials (m = 0 gives 0).
+template <int GB>
+__device__ __forceinline__ uint32_t chunk_or_zero(const uint32_t *tab, const uint8_t *guide,
+                                                  uint32_t m, uint32_t u)
+{
+    const uint32_t c = chunk_count<GB>(tab, guide, m != 0 ? m : 1u, u);
+    return m != 0 ? c : 0u;
+}
+
+// Node update when the whole wave shares the common draw layout: every
+// removal binomial has 1..64 trials except the middle one (q = 3), which has
+// D1 chunks (1..64 or 65..128 trials).  Draw j then belongs to a fixed
+// binomial, so every word index is a compile-time constant.  Returns false
+// (nothing written) if the redistribution does not fit one chunk per
+// binomial; the caller then takes the generic path from scratch.
+template <int Q, int D1, typename W, int NB, int GB>
+__device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Draws<NB> &d,
+                                          const uint32_t *tab_p, const uint8_t *g_p,
+                                          const uint32_t *tab_half, const uint8_t *g_half,
+                                          const uint32_t *tab_rest, const uint8_t *g_rest,
+                                          bool p_zero)
+{
+    W kv[Q];
+    if (p_zero) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            kv[i] = 0;
+    } else if constexpr (Q == 2) {
+        kv[0] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[0], d.w[0]);
+        kv[1] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[1], d.w[1]);
+    } else {
+        kv[0] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[0], d.w[0]);
+        if constexpr (D1 == 1) {
+            kv[1] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[1], d.w[1]);
+        } else {
+            kv[1] = chunk_count<GB>(tab_p, g_p, (uint32_t)kChunk, d.w[1]) +
+                    chunk_count<GB>(tab_p, g_p, (uint32_t)av[1] - (uint32_t)kChunk, d.w[2]);
+        }
+        kv[2] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[2], d.w[1 + D1]);
+    }
+    W M = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        M += kv[i];
+    if (wave_any(M > (W)kChunk))
+        return false;
+    constexpr int kFirst = (Q == 2) ? 2 : 2 + D1;  // first redistribution draw
+    W mv[Q];
+    if constexpr (Q == 2) {
+        mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)M, d.w[kFirst]);
+        mv[1] = M - mv[0];
+    } else {
+        // m_0 uses the next word only if m_1 consumed one (M > 0); if M = 0
+        // then R = 0 and m_0 consumes nothing, so the word is irrelevant.
+        mv[1] = chunk_or_zero<GB>(tab_rest, g_rest, (uint32_t)M, d.w[kFirst]);
+        const W R = M - mv[1];
+        mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, d.w[kFirst + 1]);
+        mv[2] = R - mv[0];
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        c[i] = av[i] - kv[i] + mv[i];
+    return true;
+}
+
+template <typename T> struct Wide;
+template <> struct Wide<uint16_t> { using type = uint32_t; };
+template <> struct Wide<uint32_t> { using type = uint64_t; };
+
+// Full node update: av holds the (already flipped) occupations; cn receives
+// the post-collision counts.  Table pointers are LDS addresses.
+template <int Q, typename W, int NB, int GB>
+__device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32_t x, uint32_t t,
+                                            uint32_t r, uint32_t key0, uint32_t key1,
+                                            const uint32_t *tab_p, const uint8_t *g_p,
+                                            const uint32_t *tab_half, const uint8_t *g_half,
+                                            const uint32_t *tab_rest, const uint8_t *g_rest,
+                                            bool p_zero)
+{
+    W kv[Q], mv[Q];
+    Draws<NB> d;
+    d.init(x, t, r, key0, key1);
+    // Common draw layout, decided once per wave for this node slot.
+    bool ok = true, two = false;
+    if constexpr (Q == 2) {
+        ok = av[0] >= 1 && av[0] <= (W)kChunk && av[1] >= 1 && av[1] <= (W)kChunk;
+    } else {
+        ok = av[0] >= 1 && av[0] <= (W)kChunk && av[2] >= 1 && av[2] <= (W)kChunk &&
+             av[1] >= 1 && av[1] <= (W)(2 * kChunk);
+        two = av[1] > (W)kChunk;
+    }
+    bool done = false;
+    if (!wave_any(!ok)) {
+        if (!wave_any(two))
+            done = node_fast<Q, 1, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
+                                              g_rest, p_zero);
+        else if (Q == 3 && !wave_any(!two))
+            done = node_fast<Q, 2, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
+                                              g_rest, p_zero);
+    }
+    if (!done) {
+        uint32_t j = 0;
+        W M = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            kv[i] = binomial<W, NB, GB>(av[i], j, tab_p, g_p, p_zero, d);
+            M += kv[i];
+        }
+        if constexpr (Q == 2) {
+            mv[0] = binomial<W, NB, GB>(M, j, tab_half, g_half, false, d);
+            mv[1] = M - mv[0];
+        } else {
+            mv[1] = binomial<W, NB, GB>(M, j, tab_rest, g_rest, false, d);
+            const W R = M - mv[1];
+            mv[0] = binomial<W, NB, GB>(R, j, tab_half, g_half, false, d);
+            mv[2] = R - mv[0];
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            cn[i] = av[i] - kv[i] + mv[i];
+    }
+}
+
+}  // namespace sampler
+}  // namespace ilg
