@@ -1,11 +1,19 @@
-"""Benchmark of the fused lattice-gas step (flip -> sampling collision -> stream).
+"""Benchmark of the lattice-gas step with flip (flip -> sampling collision -> stream).
 
-Workload: D1Q3, L = 2^24 periodic nodes, uint16 counts, Poisson(50) i.i.d.
-initial state, omega = 1.8 (flip on, omega* = 0.2), Philox seed 1.  A "step"
-is one full lattice time step; the state is resident in HBM before timing.
-Prints one JSON line: node-updates/s, the HBM roofline of the step kernel
-(algorithmic 12 bytes per node-update: 3 uint16 counts read and written), and
-the CPU oracle timed on a bounded sample on the host cores.
+Headline workload (the JSON line's value): D1Q3, L = 2^24 periodic nodes,
+uint16 counts, Poisson(50) i.i.d. initial state, omega = 1.8 (flip on,
+omega* = 0.2), Philox seed 1.  A "step" is one full lattice time step; the
+state is resident in HBM before timing; timing uses HIP events on the stream
+the kernels run on.
+
+Also reported (extra JSON objects): the batched ensemble form on the ragged
+D1Q2 ensemble (4096 members, L log-uniform in [64, 8192], 5000 steps, S(k)
+every 10 steps) against the plain per-realization loop on a sample of the same
+members, the batched D1Q3 decay sweep (6 x 1024 members, L = 4096, uint32,
+10^4 steps), the continuous-batching server on a Poisson request stream
+(q in {2, 3}, L log-uniform 2^8..2^20, 100..10000 steps, uint16) at 1, 1/2 and
+1/4 of 200 requests/s with p50/p99 latency, and the CPU oracle timed on a
+bounded sample on the host cores.
 """
 from __future__ import annotations
 
@@ -23,18 +31,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit integer VALU lane operations
+# per second (one wave64 VALU instruction per SIMD every 4 cycles).
+INT_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic integer work per node-update of the headline workload at
+# steady state: 6 draws (one chunk each for a_-, a_+, M, R; two for the rest
+# population a_0 ~ 100) -> 2 Philox4x32-10 blocks of 10 rounds x (2 full
+# 32x32 multiplies + 4 xors) = 120 ops, plus one table compare per draw.
+ALG_INT_OPS_PER_NODE = 2 * 10 * 6 + 6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_d1q3_u16_l2p24.json")
-STEP_SOURCE = os.path.join(ROOT, "paper_2203_01380_amd", "csrc", "step.hip")
+STEP_SOURCES = [os.path.join(ROOT, "paper_2203_01380_amd", "csrc", f)
+                for f in ("step.hip", "sampler.h")]
 
 
 def step_source_digest() -> str:
-    with open(STEP_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in STEP_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def counter_traffic():
-    """HBM bytes per launch from the committed PMC summary, or None if absent or
-    taken on a different version of the step kernel."""
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary, or None if absent or taken on a different version of the kernel."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -43,6 +63,22 @@ def counter_traffic():
     if rec.get("step_source_sha256_16") != step_source_digest():
         return None
     return rec.get("bytes_per_launch")
+
+
+def say(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def timed(stream, fn):
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
 
 
 def cpu_baseline(init, spec, seconds: float):
@@ -66,6 +102,108 @@ def cpu_baseline(init, spec, seconds: float):
                       f"({spec.length * steps} node-updates, {el:.1f} s)"}
 
 
+def bench_batched_ragged(ilg, W, stream, steps: int, loop_members: int):
+    ens = W.ensemble_ragged_d1q2(steps=steps)
+    members = [dict(q=s.q, length=s.length, count_bytes=s.count_bytes, omega=s.omega,
+                    seed=s.seed, realization=s.realization) for s in ens.specs]
+    b = ilg.Batch(members, ens.inits, sk_every=10, nk=16)
+    shape = b.tune(10)
+    sec = timed(stream, lambda: b.run(steps))
+    nu = ens.total_nodes * steps
+    b.close()
+    # plain form, one member after another, on an evenly spaced sample by length
+    lens = np.array([s.length for s in ens.specs])
+    order = np.argsort(-lens, kind="stable")
+    pick = order[np.linspace(0, len(order) - 1, loop_members).astype(int)]
+    lats = [ilg.Lattice(s.q, s.length, s.count_bytes, s.omega, s.seed, ens.inits[r],
+                        realization=s.realization) for r, s in ((r, ens.specs[r]) for r in pick)]
+
+    def loop():
+        for lat in lats:
+            lat.step(steps)
+
+    sec_loop = timed(stream, loop)
+    nu_loop = int(lens[pick].sum()) * steps
+    for lat in lats:
+        lat.close()
+    rate, rate_loop = nu / sec, nu_loop / sec_loop
+    return {
+        "workload": f"4096 independent D1Q2 lattices, L log-uniform in [64, 8192] "
+                    f"(sum {ens.total_nodes}), omega ~ U[1, 1.95], own seeds, uint16, "
+                    f"Poisson(30), {steps} steps, S(k) k=1..16 every 10 steps",
+        "node_updates_per_s": rate, "seconds": sec, "node_updates": nu, "shape": shape,
+        "plain_loop": {"node_updates_per_s": rate_loop, "seconds": sec_loop,
+                       "members": int(loop_members), "node_updates": nu_loop,
+                       "note": "same members one after another through the plain API "
+                               "(no diagnostics), evenly spaced by length"},
+        "batched_over_plain_loop": rate / rate_loop,
+    }
+
+
+def bench_batched_decay(ilg, W, stream, steps: int):
+    ens = W.ensemble_decay_sweep(steps=steps)
+    members = [dict(q=s.q, length=s.length, count_bytes=s.count_bytes, omega=s.omega,
+                    seed=s.seed, realization=s.realization) for s in ens.specs]
+    b = ilg.Batch(members, ens.inits, amp_every=100, max_amp=steps // 100 + 1)
+    shape = b.tune(10)
+    sec = timed(stream, lambda: b.run(steps))
+    b.close()
+    nu = ens.total_nodes * steps
+    return {"workload": f"6 omega x 1024 D1Q3 lattices, L=4096, uint32, Poisson sine init "
+                        f"(100 + 40 sin), {steps} steps, A^LG every 100 steps",
+            "node_updates_per_s": nu / sec, "seconds": sec, "node_updates": nu, "shape": shape}
+
+
+def bench_serving(ilg, W, rate: float, duration: float, budget: int, quantum: int):
+    """Replay a Poisson request stream in real time through the server: each
+    request is submitted once its arrival time has passed, every loop iteration
+    polls once (admit, one quantum of shared launches, retire).  Latency is
+    completion minus arrival."""
+    reqs = W.request_stream(rate_per_s=rate, duration_s=duration)
+    pool = W.RequestInitPool()
+    srv = ilg.Server(budget, quantum)
+    clock = ilg.Server.clock
+    t0 = clock()
+    i = 0
+    pending = {}
+    lat, work = [], 0
+    polls = 0
+    peak = 0
+    while i < len(reqs) or pending:
+        now = clock() - t0
+        while i < len(reqs) and reqs[i].arrival_s <= now:
+            rq = reqs[i]
+            m = dict(q=rq.spec.q, length=rq.spec.length, count_bytes=2, omega=rq.spec.omega,
+                     seed=rq.spec.seed, realization=rq.spec.realization)
+            rid = srv.submit(m, pool.init(i, m["q"], m["length"]), rq.spec.steps)
+            pending[rid] = (t0 + rq.arrival_s, rq.spec.length * rq.spec.steps)
+            i += 1
+        st = srv.poll()
+        polls += 1
+        peak = max(peak, st["bytes_peak"])
+        if st["finished"]:
+            for rid in list(pending):
+                info = srv.info(rid)
+                if info["state"] == "done":
+                    arr, nu = pending.pop(rid)
+                    lat.append(info["t_done"] - arr)
+                    work += nu
+                    srv.result(rid)
+        if not pending and i < len(reqs):
+            wait = t0 + reqs[i].arrival_s - clock()
+            if wait > 0:
+                time.sleep(wait)
+    t_end = clock()
+    srv.close()
+    lat = np.array(lat)
+    return {"rate_per_s": rate, "requests": len(reqs), "duration_s": duration,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_latency_s": float(lat.mean()),
+            "node_updates_per_s": work / (t_end - t0), "wall_s": t_end - t0, "polls": polls,
+            "peak_bytes": int(peak), "budget_bytes": budget, "quantum_steps": quantum}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,13 +212,23 @@ def main():
     ap.add_argument("--length", type=int, default=1 << 24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="plain,batched,decay,serving",
+                    help="comma list of plain (always), batched, decay, serving")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--serve-quantum", type=int, default=100)
+    ap.add_argument("--batched-steps", type=int, default=5000)
+    ap.add_argument("--decay-steps", type=int, default=10000)
+    ap.add_argument("--loop-members", type=int, default=32)
     ap.add_argument("--copy-probe", action="store_true",
-                    help="after timing, run one plain device copy of 768 MiB (counter scale)")
+                    help="after timing, one plain device copy of 768 MiB (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(ensembles and lattices would shard by realization or along x).", file=sys.stderr)
+              "(ensembles would shard by realization, one lattice along x).", file=sys.stderr)
         sys.exit(2)
+    forms = set(args.forms.split(","))
 
     import torch
 
@@ -88,37 +236,29 @@ def main():
     import paper_2203_01380_amd as ilg
 
     torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
     spec, init = W.workload_d1q3_big(length=args.length, steps=args.steps)
     mass0 = int(init.astype(np.int64).sum())
     lat = ilg.Lattice(spec.q, spec.length, spec.count_bytes, spec.omega, spec.seed, init)
-    stream = torch.cuda.current_stream()
-
-    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    say(f"warmup {args.warmup} steps")
     lat.step(args.warmup)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
-    ev0.record(stream)
-    lat.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    mass1 = lat.moments()["mass"]
-    if mass1 != mass0:
-        raise SystemExit(f"mass not conserved: {mass0} -> {mass1}")
-
+    say(f"timing {args.steps} steps")
+    sec = timed(stream, lambda: lat.step(args.steps))
+    if lat.moments()["mass"] != mass0:
+        raise SystemExit("mass not conserved")
+    lat.close()
     if args.copy_probe:
         a = torch.empty(768 << 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
 
-    sec = ms / 1e3
-    ms_per_step = ms / args.steps
+    ms_per_step = sec * 1e3 / args.steps
     value = spec.length * args.steps / sec
     alg_bytes = 2 * spec.q * spec.count_bytes * spec.length   # per launch
-    achieved = alg_bytes / (ms_per_step / 1e3) / 1e9
+    gbs = alg_bytes / (ms_per_step / 1e3) / 1e9
+    tops = ALG_INT_OPS_PER_NODE * spec.length / (ms_per_step / 1e3) / 1e12
     out = {
         "metric": "node-updates/s",
         "value": value,
@@ -136,13 +276,30 @@ def main():
                                "Poisson(50) per velocity, omega=1.8, Philox seed 1",
                    "q": spec.q, "length": spec.length, "count_bytes": spec.count_bytes,
                    "omega": spec.omega, "form": "plain"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic()},
+        "roofline": {"bound": "alu", "achieved": tops, "peak": INT_VALU_PEAK_TOPS,
+                     "unit": "TOP/s", "frac": tops / INT_VALU_PEAK_TOPS,
+                     "traffic": counter_traffic(),
+                     "alg_ops_per_node_update": ALG_INT_OPS_PER_NODE},
+        "hbm_roofline": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "alg_bytes_per_node_update": 12},
     }
+    if "batched" in forms:
+        say("batched ragged ensemble")
+        out["batched"] = bench_batched_ragged(ilg, W, stream, args.batched_steps,
+                                              args.loop_members)
+    if "decay" in forms:
+        say("batched decay sweep")
+        out["batched_decay"] = bench_batched_decay(ilg, W, stream, args.decay_steps)
+    if "serving" in forms:
+        out["serving"] = []
+        for frac in (1.0, 0.5, 0.25):
+            say(f"serving at {frac:g} x {args.serve_rate:g} req/s for {args.serve_seconds:g} s")
+            out["serving"].append(bench_serving(ilg, W, args.serve_rate * frac, args.serve_seconds,
+                                                int(args.serve_budget_gib * (1 << 30)),
+                                                args.serve_quantum))
     if not args.no_cpu_baseline:
-        print(f"# cpu baseline (~{args.cpu_seconds:.0f} s)", file=sys.stderr, flush=True)
+        say(f"cpu baseline (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(init, spec, args.cpu_seconds)
-    lat.close()
     print(json.dumps(out), flush=True)
 
 

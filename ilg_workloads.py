@@ -182,3 +182,18 @@ def request_stream(rate_per_s: float = 200.0, duration_s: float = 60.0, lmin_log
         out.append(Request(arrival_s=t, spec=spec, init_seed=10_000_000 + i))
         i += 1
     return out
+
+
+class RequestInitPool:
+    """Initial states for a request stream without drawing a fresh lattice per
+    request: `npool` arrays of [3][2^lmax_log2] i.i.d. Poisson(mean) uint16
+    counts; request i uses the first q rows and L columns of array i % npool
+    (i.i.d. entries, so every slice is itself i.i.d. Poisson(mean))."""
+
+    def __init__(self, npool: int = 8, lmax_log2: int = 20, mean: float = 40.0, seed: int = 6):
+        rng = np.random.default_rng(seed)
+        self.pool = [rng.poisson(mean, size=(3, 1 << lmax_log2)).astype(np.uint16)
+                     for _ in range(npool)]
+
+    def init(self, i: int, q: int, length: int) -> np.ndarray:
+        return np.ascontiguousarray(self.pool[i % len(self.pool)][:q, :length])

@@ -214,6 +214,67 @@ int ilg_batch_amplitudes(ilg_batch *b, double *amp, uint32_t *count);
 /* Wait for the batch's work, report sticky errors, free what it owns. */
 int ilg_batch_destroy(ilg_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Serving: a continuous-batching request server.  Requests (a configuration,
+ * its initial state and a step count) queue in FIFO order until their device
+ * memory (double-buffered state and fixed-point tables) fits the budget;
+ * admitted requests become active slots whose state stays on the device.
+ * Each ilg_server_poll admits what fits, advances every active request by
+ * up to quantum_steps steps in shared launches (one per step and per
+ * (q, count type) group, groups on separate streams), and retires finished
+ * requests to host memory.  A request's result is bit-identical to the same
+ * configuration run alone through ilg_create/ilg_step.
+ * ---------------------------------------------------------------------- */
+typedef struct ilg_server ilg_server; /* opaque; owned by the library */
+
+#define ILG_REQ_QUEUED 0u
+#define ILG_REQ_ACTIVE 1u
+#define ILG_REQ_DONE 2u
+#define ILG_REQ_CANCELLED 3u
+
+typedef struct ilg_request_info {
+    uint64_t id;
+    uint32_t state;       /* ILG_REQ_* */
+    uint32_t q;
+    uint64_t length;
+    uint64_t steps_total, steps_done;
+    double t_submit, t_admit, t_done; /* ilg_server_clock() seconds; -1 if not yet */
+} ilg_request_info;
+
+typedef struct ilg_poll_info {
+    uint32_t admitted, active, queued, finished; /* in this poll / after it */
+    uint32_t quantum_steps;                      /* longest advance in this poll */
+    uint32_t reserved;
+    uint64_t bytes_in_use, bytes_peak;           /* device budget accounting */
+} ilg_poll_info;
+
+/* Steady clock (seconds) used for the request timestamps. */
+double ilg_server_clock(void);
+
+/* Server owning a device arena of budget_bytes; every poll advances active
+ * requests by up to quantum_steps steps. */
+int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server **out);
+
+/* Queue a request: cfg, host [q][L] initial counts (copied), nsteps > 0.
+ * ILG_E_BUSY if it can never fit the budget. */
+int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_host,
+                      uint64_t nsteps, uint64_t *id);
+
+/* One scheduling round (admit, advance one quantum, retire).  Syncs. */
+int ilg_server_poll(ilg_server *s, ilg_poll_info *info);
+
+/* State and timestamps of a request that has not been collected. */
+int ilg_server_info(ilg_server *s, uint64_t id, ilg_request_info *out);
+
+/* Copy a finished request's final [q][L] counts to host_out and forget it. */
+int ilg_server_result(ilg_server *s, uint64_t id, void *host_out);
+
+/* Drop a queued or active request and release its memory. */
+int ilg_server_cancel(ilg_server *s, uint64_t id);
+
+/* Wait for the server's work and free everything it owns. */
+int ilg_server_destroy(ilg_server *s);
+
 #ifdef __cplusplus
 }
 #endif

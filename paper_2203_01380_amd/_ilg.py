@@ -58,6 +58,20 @@ class IlgBatchDiag(ctypes.Structure):
 BATCH_MAX_K = 16
 
 
+class IlgRequestInfo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("state", ctypes.c_uint32), ("q", ctypes.c_uint32),
+                ("length", ctypes.c_uint64), ("steps_total", ctypes.c_uint64),
+                ("steps_done", ctypes.c_uint64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class IlgPollInfo(ctypes.Structure):
+    _fields_ = [("admitted", ctypes.c_uint32), ("active", ctypes.c_uint32),
+                ("queued", ctypes.c_uint32), ("finished", ctypes.c_uint32),
+                ("quantum_steps", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("bytes_in_use", ctypes.c_uint64), ("bytes_peak", ctypes.c_uint64)]
+
+
 def _load():
     # torch ships a HIP runtime with the same SONAME as the system one; loading
     # torch first makes libilg.so bind to that single runtime instance, so
@@ -99,6 +113,14 @@ def _load():
         "ilg_batch_structure_factor": ([hp, vp, vp], i32),
         "ilg_batch_amplitudes": ([hp, vp, vp], i32),
         "ilg_batch_destroy": ([hp], i32),
+        "ilg_server_clock": ([], ctypes.c_double),
+        "ilg_server_create": ([u64, u32, ctypes.POINTER(hp)], i32),
+        "ilg_server_submit": ([hp, cfgp, vp, u64, ctypes.POINTER(u64)], i32),
+        "ilg_server_poll": ([hp, ctypes.POINTER(IlgPollInfo)], i32),
+        "ilg_server_info": ([hp, u64, ctypes.POINTER(IlgRequestInfo)], i32),
+        "ilg_server_result": ([hp, u64, vp], i32),
+        "ilg_server_cancel": ([hp, u64], i32),
+        "ilg_server_destroy": ([hp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -322,5 +344,75 @@ class Batch:
         try:
             if self._h:
                 lib.ilg_batch_destroy(self._h)
+        except Exception:
+            pass
+
+
+REQ_STATES = {0: "queued", 1: "active", 2: "done", 3: "cancelled"}
+
+
+class Server:
+    """Continuous-batching request server (ilg_server_*)."""
+
+    def __init__(self, budget_bytes: int, quantum_steps: int = 100):
+        self._h = ctypes.c_void_p()
+        check(lib.ilg_server_create(budget_bytes, quantum_steps, ctypes.byref(self._h)))
+        self._shapes = {}
+
+    @staticmethod
+    def clock() -> float:
+        return float(lib.ilg_server_clock())
+
+    def submit(self, member: dict, init: np.ndarray, nsteps: int) -> int:
+        cfg = make_config(member["q"], member["length"], member["count_bytes"], member["omega"],
+                          member["seed"], member.get("realization", 0), member.get("t0", 0),
+                          member.get("theta", 0.0), member.get("flip", "auto"))
+        a = np.ascontiguousarray(init, dtype=_dtype(member["count_bytes"]))
+        if a.shape != (member["q"], member["length"]):
+            raise ValueError(f"init shape {a.shape}")
+        rid = ctypes.c_uint64()
+        check(lib.ilg_server_submit(self._h, ctypes.byref(cfg), a.ctypes.data, nsteps,
+                                    ctypes.byref(rid)))
+        self._shapes[int(rid.value)] = (member["q"], member["length"], member["count_bytes"])
+        return int(rid.value)
+
+    def poll(self) -> dict:
+        info = IlgPollInfo()
+        check(lib.ilg_server_poll(self._h, ctypes.byref(info)))
+        return {f: int(getattr(info, f)) for f, _ in IlgPollInfo._fields_}
+
+    def info(self, rid: int) -> dict:
+        out = IlgRequestInfo()
+        check(lib.ilg_server_info(self._h, rid, ctypes.byref(out)))
+        d = {f: getattr(out, f) for f, _ in IlgRequestInfo._fields_}
+        d["state"] = REQ_STATES[int(d["state"])]
+        return d
+
+    def result(self, rid: int) -> np.ndarray:
+        q, L, cb = self._shapes[rid]
+        out = np.empty((q, L), dtype=_dtype(cb))
+        check(lib.ilg_server_result(self._h, rid, out.ctypes.data))
+        del self._shapes[rid]
+        return out
+
+    def cancel(self, rid: int):
+        check(lib.ilg_server_cancel(self._h, rid))
+        self._shapes.pop(rid, None)
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, ctypes.c_void_p()
+            check(lib.ilg_server_destroy(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib.ilg_server_destroy(self._h)
         except Exception:
             pass

@@ -19,7 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libilg.so")
 ARCH = os.environ.get("ILG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["runtime.cpp", "tables.cpp", "batch_runtime.cpp", "step.hip", "diag.hip", "batch.hip"]
+SOURCES = ["runtime.cpp", "tables.cpp", "batch_runtime.cpp", "scheduler.cpp", "serve_runtime.cpp",
+           "step.hip", "diag.hip", "batch.hip", "serve.hip"]
 
 
 def hipcc() -> str:

@@ -139,4 +139,42 @@ void batch_shape(int shape, int q, int *block, int *wg_per_cu);
 hipError_t launch_batch_reset(uint32_t *queue, hipStream_t stream);
 hipError_t launch_batch(int q, int count_bytes, int shape, const BatchArgs &a, hipStream_t stream);
 
+// ---------------------------------------------------------------- serving
+// One active request of the server: its buffer pair and table set in the
+// server's arena and its draw keys; steps is this quantum's advance.
+struct ServeSlot {
+    uint64_t state_off;    // element offset of buffer 0 (buffer 1 at q*pitch)
+    uint64_t table_off;    // byte offset of the slot's table set
+    uint32_t length, pitch;
+    uint32_t t0;           // absolute index of the quantum's first step
+    uint32_t steps;        // steps in this quantum
+    uint32_t realization, key0, key1;
+    uint32_t flip, p_zero, cur0;
+};
+struct ServeTile {
+    uint32_t slot;
+    uint32_t x0;
+};
+constexpr int kServeGuideBits = 8;
+constexpr int kServeTile = 1024;  // nodes per tile (one workgroup pass)
+// Slot table set: removal table, rest table (q = 3), then their guides.
+constexpr size_t kServeTableBytes = kTableEntries * sizeof(uint32_t);
+constexpr size_t kServeGuideBytes = (size_t)kChunk << kServeGuideBits;
+inline size_t serve_table_set_bytes(int q)
+{
+    return (q == 3 ? 2 : 1) * (kServeTableBytes + kServeGuideBytes);
+}
+
+struct ServeArgs {
+    void *arena;
+    const ServeSlot *slots;
+    const ServeTile *tiles;
+    uint32_t ntiles;
+    uint32_t j;             // step index within the quantum
+    const void *shared;     // half table then its guide
+    uint32_t *err;
+};
+
+hipError_t launch_serve(int q, int count_bytes, const ServeArgs &a, hipStream_t stream);
+
 }  // namespace ilg

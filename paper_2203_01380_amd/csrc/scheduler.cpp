@@ -1,0 +1,175 @@
+// Continuous-batching scheduler: FIFO admission under a device-memory
+// budget, quantum advances of all active slots, retirement.
+#include "scheduler.h"
+
+#include <algorithm>
+
+namespace ilg {
+namespace serve {
+
+namespace {
+constexpr uint64_t kAlign = 256;
+uint64_t round_up(uint64_t x)
+{
+    return (x + kAlign - 1) / kAlign * kAlign;
+}
+}  // namespace
+
+Arena::Arena(uint64_t size) : size_(size / kAlign * kAlign)
+{
+    if (size_ > 0)
+        free_[0] = size_;
+}
+
+bool Arena::alloc(uint64_t bytes, uint64_t *off)
+{
+    const uint64_t need = round_up(std::max<uint64_t>(bytes, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second >= need) {
+            *off = it->first;
+            const uint64_t rest = it->second - need, start = it->first + need;
+            free_.erase(it);
+            if (rest)
+                free_[start] = rest;
+            used_ += need;
+            peak_ = std::max(peak_, used_);
+            return true;
+        }
+    }
+    return false;
+}
+
+void Arena::free(uint64_t off, uint64_t bytes)
+{
+    const uint64_t len = round_up(std::max<uint64_t>(bytes, 1));
+    used_ -= len;
+    auto it = free_.emplace(off, len).first;
+    // merge with the following block
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        free_.erase(nx);
+    }
+    // merge with the preceding block
+    if (it != free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            free_.erase(it);
+        }
+    }
+}
+
+Scheduler::Scheduler(uint64_t budget_bytes, uint32_t quantum_steps)
+    : budget_(budget_bytes), quantum_(quantum_steps ? quantum_steps : 1), arena_(budget_bytes)
+{
+}
+
+bool Scheduler::submit(std::unique_ptr<Req> r, Executor &ex, uint64_t *id, double now)
+{
+    r->bytes = ex.footprint(*r);
+    if (round_up(r->bytes) > arena_.size() || r->total == 0)
+        return false;
+    r->id = next_id_++;
+    r->t_submit = now;
+    r->state = ReqState::Queued;
+    Req *raw = r.get();
+    all_[raw->id] = std::move(r);
+    queue_.push_back(raw);
+    *id = raw->id;
+    return true;
+}
+
+int Scheduler::poll(Executor &ex, PollStats *st, double (*clock)())
+{
+    PollStats s;
+    // Admission: strict FIFO, so a large request is never starved by later
+    // small ones.
+    while (!queue_.empty()) {
+        Req *r = queue_.front();
+        uint64_t off = 0;
+        if (!arena_.alloc(r->bytes, &off))
+            break;
+        r->mem_off = off;
+        int rc = ex.load(*r);
+        if (rc != 0) {
+            arena_.free(off, r->bytes);
+            return rc;
+        }
+        r->state = ReqState::Active;
+        r->t_admit = clock();
+        queue_.pop_front();
+        active_.push_back(r);
+        ++s.admitted;
+    }
+    if (!active_.empty()) {
+        std::vector<uint32_t> steps(active_.size());
+        for (size_t i = 0; i < active_.size(); ++i) {
+            const uint64_t left = active_[i]->total - active_[i]->done;
+            steps[i] = (uint32_t)std::min<uint64_t>(left, quantum_);
+            s.quantum_steps = std::max(s.quantum_steps, steps[i]);
+        }
+        int rc = ex.run(active_, steps);
+        if (rc != 0)
+            return rc;
+        const double now = clock();
+        std::vector<Req *> still;
+        for (size_t i = 0; i < active_.size(); ++i) {
+            Req *r = active_[i];
+            r->done += steps[i];
+            if (r->done >= r->total) {
+                rc = ex.unload(*r);
+                if (rc != 0)
+                    return rc;
+                arena_.free(r->mem_off, r->bytes);
+                r->state = ReqState::Done;
+                r->t_done = now;
+                ++s.finished;
+            } else {
+                still.push_back(r);
+            }
+        }
+        active_.swap(still);
+    }
+    s.active = (uint32_t)active_.size();
+    s.queued = (uint32_t)queue_.size();
+    if (st)
+        *st = s;
+    return 0;
+}
+
+Req *Scheduler::find(uint64_t id)
+{
+    auto it = all_.find(id);
+    return it == all_.end() ? nullptr : it->second.get();
+}
+
+bool Scheduler::cancel(uint64_t id)
+{
+    Req *r = find(id);
+    if (!r)
+        return false;
+    if (r->state == ReqState::Queued) {
+        queue_.erase(std::find(queue_.begin(), queue_.end(), r));
+    } else if (r->state == ReqState::Active) {
+        active_.erase(std::find(active_.begin(), active_.end(), r));
+        arena_.free(r->mem_off, r->bytes);
+    } else {
+        return false;
+    }
+    r->state = ReqState::Cancelled;
+    r->payload.reset();
+    return true;
+}
+
+bool Scheduler::release(uint64_t id)
+{
+    Req *r = find(id);
+    if (!r || (r->state != ReqState::Done && r->state != ReqState::Cancelled))
+        return false;
+    all_.erase(id);
+    return true;
+}
+
+}  // namespace serve
+}  // namespace ilg

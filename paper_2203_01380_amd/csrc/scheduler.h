@@ -1,0 +1,97 @@
+// Continuous-batching scheduler for lattice-gas requests (host only, no HIP).
+//
+// Requests wait in a FIFO queue until their device memory (state buffers and
+// tables) fits the budget; admitted requests become active slots, and every
+// poll advances all active slots by one quantum of steps (fewer for a slot
+// that finishes earlier) through an Executor, then retires the finished ones
+// and frees their memory for the next admissions.  The executor does the
+// device work; the scheduler only does bookkeeping, so it is tested on the
+// CPU with a counting executor.
+#pragma once
+
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <vector>
+
+namespace ilg {
+namespace serve {
+
+enum class ReqState : uint32_t { Queued = 0, Active = 1, Done = 2, Cancelled = 3 };
+
+struct Req {
+    uint64_t id = 0;
+    uint32_t q = 0;
+    uint64_t bytes = 0;     // device bytes while active (from the executor's layout)
+    uint64_t total = 0;     // steps requested
+    uint64_t done = 0;      // steps taken so far
+    double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;  // steady-clock seconds
+    ReqState state = ReqState::Queued;
+    uint64_t mem_off = 0;   // arena offset while active
+    std::shared_ptr<void> payload;  // executor data (initial / final state, tables)
+};
+
+// First-fit allocator over [0, size) with coalescing free list.
+class Arena {
+public:
+    explicit Arena(uint64_t size);
+    bool alloc(uint64_t bytes, uint64_t *off);  // 256-byte aligned blocks
+    void free(uint64_t off, uint64_t bytes);
+    uint64_t size() const { return size_; }
+    uint64_t used() const { return used_; }
+    uint64_t peak() const { return peak_; }
+
+private:
+    uint64_t size_, used_ = 0, peak_ = 0;
+    std::map<uint64_t, uint64_t> free_;  // offset -> length
+};
+
+class Executor {
+public:
+    virtual ~Executor() = default;
+    // Bytes of device memory a request needs while active.
+    virtual uint64_t footprint(const Req &r) = 0;
+    // Place the request's initial state and tables at r.mem_off.
+    virtual int load(Req &r) = 0;
+    // Advance active[i] by steps[i] >= 1 steps; returns when the work is done.
+    virtual int run(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) = 0;
+    // Copy a finished request's final state out of the device.
+    virtual int unload(Req &r) = 0;
+};
+
+struct PollStats {
+    uint32_t admitted = 0, active = 0, queued = 0, finished = 0;
+    uint32_t quantum_steps = 0;  // steps of the longest slot advance in this poll
+};
+
+class Scheduler {
+public:
+    Scheduler(uint64_t budget_bytes, uint32_t quantum_steps);
+    // Queue a request; ILG_E_BUSY-style failure (returns false) if it could
+    // never fit the budget.
+    bool submit(std::unique_ptr<Req> r, Executor &ex, uint64_t *id, double now);
+    // Admit what fits (FIFO), run one quantum, retire finished requests.
+    int poll(Executor &ex, PollStats *st, double (*clock)());
+    Req *find(uint64_t id);
+    // Cancel a queued or active request (its memory is released).
+    bool cancel(uint64_t id);
+    // Forget a finished or cancelled request.
+    bool release(uint64_t id);
+    uint64_t peak_bytes() const { return arena_.peak(); }
+    uint64_t used_bytes() const { return arena_.used(); }
+    size_t queued() const { return queue_.size(); }
+    size_t active() const { return active_.size(); }
+
+private:
+    uint64_t budget_;
+    uint32_t quantum_;
+    Arena arena_;
+    uint64_t next_id_ = 1;
+    std::deque<Req *> queue_;
+    std::vector<Req *> active_;
+    std::map<uint64_t, std::unique_ptr<Req>> all_;
+};
+
+}  // namespace serve
+}  // namespace ilg

@@ -1,0 +1,134 @@
+// Multi-slot lattice-gas step for the continuous-batching server.
+//
+// One launch advances every active request (slot) of one (q, count type) by
+// one step: the host lists the slots' tiles of 1024 nodes, slot by slot, and
+// each workgroup of a persistent grid walks a contiguous range of that list.
+// When the walk enters a new slot the workgroup stages the slot's removal and
+// rest tables with their guides in LDS (the half table is shared and staged
+// once).  Slots whose quantum is shorter than the current step index are
+// skipped.  The node update is the same code as the plain kernel (sampler.h),
+// so every request's result equals the same configuration run alone.
+#include "ilg_internal.h"
+#include "sampler.h"
+
+namespace ilg {
+
+namespace {
+
+using sampler::Wide;
+
+constexpr int kBlock = kServeTile;  // one node per thread per tile
+
+template <int Q, typename T>
+__global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
+{
+    using W = typename Wide<T>::type;
+    constexpr int NB = (Q == 3) ? 2 : 1;
+    constexpr int GB = kServeGuideBits;
+    constexpr int kTabs = (Q == 3) ? 3 : 2;
+    constexpr int kG = kChunk << GB;
+    __shared__ uint32_t s_tab[kTabs * kTableEntries];
+    __shared__ uint8_t s_guide[kTabs * kG];
+
+    // shared half table (slot 1 in LDS) and its guide
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.shared);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_tab + kTableEntries);
+        for (int i = threadIdx.x; i < kTableEntries / 4; i += kBlock)
+            dst[i] = src[i];
+        const uint4 *gsrc = reinterpret_cast<const uint4 *>(
+            reinterpret_cast<const uint8_t *>(a.shared) + kServeTableBytes);
+        uint4 *gdst = reinterpret_cast<uint4 *>(s_guide + kG);
+        for (int i = threadIdx.x; i < kG / 16; i += kBlock)
+            gdst[i] = gsrc[i];
+    }
+    const uint32_t *tab_p = s_tab, *tab_half = s_tab + kTableEntries;
+    const uint32_t *tab_rest = s_tab + 2 * kTableEntries;
+    const uint8_t *g_p = s_guide, *g_half = s_guide + kG, *g_rest = s_guide + 2 * kG;
+    constexpr W kMax = (W)(T)~(T)0;
+    bool overflow = false;
+
+    const uint32_t lo = (uint32_t)((uint64_t)a.ntiles * blockIdx.x / gridDim.x);
+    const uint32_t hi = (uint32_t)((uint64_t)a.ntiles * (blockIdx.x + 1) / gridDim.x);
+    uint32_t staged = 0xFFFFFFFFu;
+    for (uint32_t tile = lo; tile < hi; ++tile) {
+        const ServeTile tl = a.tiles[tile];
+        const ServeSlot sl = a.slots[tl.slot];
+        if (a.j >= sl.steps)
+            continue;
+        if (tl.slot != staged) {
+            __syncthreads();  // previous slot's readers are done with LDS
+            const uint8_t *set = reinterpret_cast<const uint8_t *>(a.arena) + sl.table_off;
+            const int nt = (Q == 3) ? 2 : 1;  // removal (+ rest) tables
+            for (int t = 0; t < nt; ++t) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(set + t * kServeTableBytes);
+                uint4 *dst = reinterpret_cast<uint4 *>(s_tab + (t == 0 ? 0 : 2) * kTableEntries);
+                for (int i = threadIdx.x; i < kTableEntries / 4; i += kBlock)
+                    dst[i] = src[i];
+                const uint4 *gsrc = reinterpret_cast<const uint4 *>(
+                    set + nt * kServeTableBytes + t * kServeGuideBytes);
+                uint4 *gdst = reinterpret_cast<uint4 *>(s_guide + (t == 0 ? 0 : 2) * kG);
+                for (int i = threadIdx.x; i < kG / 16; i += kBlock)
+                    gdst[i] = gsrc[i];
+            }
+            staged = tl.slot;
+        }
+        __syncthreads();
+        const uint32_t x = tl.x0 + threadIdx.x;
+        const uint32_t L = sl.length;
+        if (x >= L)
+            continue;
+        const uint64_t pitch = sl.pitch, qp = (uint64_t)Q * sl.pitch;
+        const uint32_t cur = sl.cur0 ^ (a.j & 1u);
+        const T *in = reinterpret_cast<const T *>(a.arena) + sl.state_off + cur * qp;
+        T *out = reinterpret_cast<T *>(a.arena) + sl.state_off + (cur ^ 1u) * qp;
+        W av[Q], cn[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            av[i] = (W)in[(uint64_t)(sl.flip ? Q - 1 - i : i) * pitch + x];
+        sampler::node_update<Q, W, NB, GB>(av, cn, x, sl.t0 + a.j, sl.realization, sl.key0,
+                                           sl.key1, tab_p, g_p, tab_half, g_half, tab_rest,
+                                           g_rest, sl.p_zero != 0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            overflow |= cn[i] > kMax;
+        const uint32_t xm = (x == 0) ? L - 1 : x - 1;
+        const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+        out[xm] = (T)cn[0];
+        out[(uint64_t)(Q - 1) * pitch + xp] = (T)cn[Q - 1];
+        if constexpr (Q == 3)
+            out[pitch + x] = (T)cn[1];
+    }
+    if (overflow)
+        atomicOr(a.err, 1u);
+}
+
+template <int Q, typename T>
+hipError_t launch_qt(const ServeArgs &a, hipStream_t stream)
+{
+    const uint32_t cus = (uint32_t)device_cu_count();
+    uint32_t grid = cus * 2;  // two 1024-thread workgroups per CU
+    if (grid > a.ntiles)
+        grid = a.ntiles;
+    if (grid == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((serve_kernel<Q, T>), dim3(grid), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_serve(int q, int count_bytes, const ServeArgs &a, hipStream_t stream)
+{
+    if (q == 2 && count_bytes == 2)
+        return launch_qt<2, uint16_t>(a, stream);
+    if (q == 2 && count_bytes == 4)
+        return launch_qt<2, uint32_t>(a, stream);
+    if (q == 3 && count_bytes == 2)
+        return launch_qt<3, uint16_t>(a, stream);
+    if (q == 3 && count_bytes == 4)
+        return launch_qt<3, uint32_t>(a, stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ilg

@@ -1,0 +1,419 @@
+// Continuous-batching server behind ilg_server_* (include/ilg.h): the
+// device executor of the scheduler (scheduler.h).  One device arena of the
+// budget's size holds every active request's double-buffered state and its
+// table set; each poll admits what fits, advances all active requests by a
+// quantum with the multi-slot step kernel (one launch per step and per
+// (q, count type) group, groups on their own streams so their work
+// overlaps), and copies finished states back to host memory.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ilg.h"
+#include "ilg_internal.h"
+#include "scheduler.h"
+
+namespace {
+
+using ilg::serve::Req;
+using ilg::serve::ReqState;
+
+int sfail(int code, const std::string &msg)
+{
+    ilg::set_last_error(msg);
+    return code;
+}
+
+int shfail(hipError_t e, const char *what)
+{
+    return sfail(ILG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define SHIP(call)                                     \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess)                          \
+            return shfail(e_, #call);                  \
+    } while (0)
+
+double steady_now()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+uint64_t pitch_of(uint64_t length)
+{
+    return (length + 63) / 64 * 64;
+}
+
+uint64_t align256(uint64_t x)
+{
+    return (x + 255) / 256 * 256;
+}
+
+// Per-request data kept by the executor.
+struct Payload {
+    ilg_config cfg;
+    ilg::Fixed fx;
+    std::vector<unsigned char> host;  // initial state, later the final state ([q][L])
+    uint64_t t = 0;                   // absolute index of the next step
+    uint32_t cur = 0;                 // buffer holding the current state
+};
+
+Payload *payload_of(Req &r)
+{
+    return static_cast<Payload *>(r.payload.get());
+}
+
+uint64_t state_bytes(const ilg_config &c)
+{
+    return align256(2ull * c.q * pitch_of(c.length) * c.count_bytes);
+}
+
+class DeviceExecutor : public ilg::serve::Executor {
+public:
+    void *arena = nullptr;
+    void *shared = nullptr;  // half table + guide
+    uint32_t *err = nullptr;
+    hipStream_t streams[4] = {nullptr, nullptr, nullptr, nullptr};  // (q, count type) groups
+    ilg::ServeSlot *d_slots[4] = {nullptr, nullptr, nullptr, nullptr};
+    ilg::ServeTile *d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};
+    size_t cap_slots[4] = {0, 0, 0, 0}, cap_tiles[4] = {0, 0, 0, 0};
+    hipStream_t io = nullptr;  // copies in and out
+    int last_rc = ILG_OK;
+
+    static int group(uint32_t q, uint32_t cb)
+    {
+        return (q == 3 ? 2 : 0) + (cb == 4 ? 1 : 0);
+    }
+
+    uint64_t footprint(const Req &r) override
+    {
+        const Payload *p = static_cast<const Payload *>(r.payload.get());
+        return state_bytes(p->cfg) + align256(ilg::serve_table_set_bytes((int)p->cfg.q));
+    }
+
+    int load(Req &r) override
+    {
+        Payload *p = payload_of(r);
+        const ilg_config &c = p->cfg;
+        const size_t cb = c.count_bytes, pitch = pitch_of(c.length);
+        unsigned char *base = static_cast<unsigned char *>(arena) + r.mem_off;
+        SHIP(hipMemcpy2DAsync(base, pitch * cb, p->host.data(), c.length * cb, c.length * cb, c.q,
+                              hipMemcpyHostToDevice, io));
+        // table set: removal table (+ rest table for q = 3) then their guides
+        const int nt = c.q == 3 ? 2 : 1;
+        std::vector<unsigned char> set(ilg::serve_table_set_bytes((int)c.q), 0);
+        const uint64_t ps[2] = {p->fx.p, p->fx.p_rest};
+        for (int t = 0; t < nt; ++t) {
+            uint32_t *tab = reinterpret_cast<uint32_t *>(set.data() + t * ilg::kServeTableBytes);
+            if (ps[t] == 0)
+                continue;
+            ilg::build_binomial_table(ps[t], tab);
+            guide(tab, set.data() + nt * ilg::kServeTableBytes + t * ilg::kServeGuideBytes);
+        }
+        SHIP(hipMemcpyAsync(base + state_bytes(c), set.data(), set.size(), hipMemcpyHostToDevice,
+                            io));
+        SHIP(hipStreamSynchronize(io));
+        p->t = c.t0;
+        p->cur = 0;
+        return ILG_OK;
+    }
+
+    // Guide of a removal/rest table: #{j < m : T[m][j] <= b << (32 - bits)}
+    // per row m and bucket b, by binary search on the nondecreasing row.
+    static void guide(const uint32_t *tab, unsigned char *g)
+    {
+        constexpr int kRow = 1 << ilg::kServeGuideBits;
+        for (int m = 1; m <= ilg::kChunk; ++m) {
+            const uint32_t *row = tab + (m - 1) * m / 2;
+            for (int b = 0; b < kRow; ++b) {
+                const uint64_t edge = uint64_t(b) << (32 - ilg::kServeGuideBits);
+                int lo = 0, hi = m;
+                while (lo < hi) {
+                    const int mid = (lo + hi) / 2;
+                    if (row[mid] <= edge)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                g[(m - 1) * kRow + b] = (unsigned char)lo;
+            }
+        }
+    }
+
+    int run(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) override
+    {
+        std::vector<ilg::ServeSlot> slots[4];
+        std::vector<ilg::ServeTile> tiles[4];
+        uint32_t maxsteps[4] = {0, 0, 0, 0};
+        for (size_t i = 0; i < active.size(); ++i) {
+            Req &r = *active[i];
+            Payload *p = payload_of(r);
+            const ilg_config &c = p->cfg;
+            const int g = group(c.q, c.count_bytes);
+            ilg::ServeSlot s;
+            std::memset(&s, 0, sizeof(s));
+            s.state_off = r.mem_off / c.count_bytes;
+            s.table_off = r.mem_off + state_bytes(c);
+            s.length = (uint32_t)c.length;
+            s.pitch = (uint32_t)pitch_of(c.length);
+            s.t0 = (uint32_t)p->t;
+            s.steps = steps[i];
+            s.realization = c.realization;
+            s.key0 = (uint32_t)(c.seed & 0xFFFFFFFFu);
+            s.key1 = (uint32_t)(c.seed >> 32);
+            s.flip = (uint32_t)p->fx.flip;
+            s.p_zero = p->fx.p == 0 ? 1u : 0u;
+            s.cur0 = p->cur;
+            const uint32_t idx = (uint32_t)slots[g].size();
+            slots[g].push_back(s);
+            for (uint64_t x0 = 0; x0 < c.length; x0 += ilg::kServeTile)
+                tiles[g].push_back(ilg::ServeTile{idx, (uint32_t)x0});
+            maxsteps[g] = std::max(maxsteps[g], steps[i]);
+        }
+        for (int g = 0; g < 4; ++g) {
+            if (slots[g].empty())
+                continue;
+            int rc = ensure(g, slots[g].size(), tiles[g].size());
+            if (rc != ILG_OK)
+                return rc;
+            SHIP(hipMemcpyAsync(d_slots[g], slots[g].data(), slots[g].size() * sizeof(ilg::ServeSlot),
+                                hipMemcpyHostToDevice, streams[g]));
+            SHIP(hipMemcpyAsync(d_tiles[g], tiles[g].data(), tiles[g].size() * sizeof(ilg::ServeTile),
+                                hipMemcpyHostToDevice, streams[g]));
+            ilg::ServeArgs a;
+            a.arena = arena;
+            a.slots = d_slots[g];
+            a.tiles = d_tiles[g];
+            a.ntiles = (uint32_t)tiles[g].size();
+            a.shared = shared;
+            a.err = err;
+            const int q = g >= 2 ? 3 : 2, cb = (g & 1) ? 4 : 2;
+            for (uint32_t j = 0; j < maxsteps[g]; ++j) {
+                a.j = j;
+                hipError_t e = ilg::launch_serve(q, cb, a, streams[g]);
+                if (e != hipSuccess)
+                    return shfail(e, "serve launch");
+            }
+        }
+        for (int g = 0; g < 4; ++g)
+            if (!slots[g].empty())
+                SHIP(hipStreamSynchronize(streams[g]));
+        uint32_t e = 0;
+        SHIP(hipMemcpy(&e, err, sizeof(e), hipMemcpyDeviceToHost));
+        if (e & 1u)
+            return sfail(ILG_E_OVERFLOW, "a post-collision count exceeded the count type");
+        for (size_t i = 0; i < active.size(); ++i) {
+            Payload *p = payload_of(*active[i]);
+            p->t += steps[i];
+            p->cur ^= (steps[i] & 1u);
+        }
+        return ILG_OK;
+    }
+
+    int unload(Req &r) override
+    {
+        Payload *p = payload_of(r);
+        const ilg_config &c = p->cfg;
+        const size_t cb = c.count_bytes, pitch = pitch_of(c.length);
+        const unsigned char *src = static_cast<const unsigned char *>(arena) + r.mem_off +
+                                   (size_t)p->cur * c.q * pitch * cb;
+        SHIP(hipMemcpy2DAsync(p->host.data(), c.length * cb, src, pitch * cb, c.length * cb, c.q,
+                              hipMemcpyDeviceToHost, io));
+        SHIP(hipStreamSynchronize(io));
+        return ILG_OK;
+    }
+
+    int ensure(int g, size_t nslots, size_t ntiles)
+    {
+        if (nslots > cap_slots[g]) {
+            (void)hipFree(d_slots[g]);
+            cap_slots[g] = std::max(nslots, 2 * cap_slots[g]);
+            SHIP(hipMalloc((void **)&d_slots[g], cap_slots[g] * sizeof(ilg::ServeSlot)));
+        }
+        if (ntiles > cap_tiles[g]) {
+            (void)hipFree(d_tiles[g]);
+            cap_tiles[g] = std::max(ntiles, 2 * cap_tiles[g]);
+            SHIP(hipMalloc((void **)&d_tiles[g], cap_tiles[g] * sizeof(ilg::ServeTile)));
+        }
+        return ILG_OK;
+    }
+
+    ~DeviceExecutor() override
+    {
+        for (int g = 0; g < 4; ++g) {
+            (void)hipFree(d_slots[g]);
+            (void)hipFree(d_tiles[g]);
+            if (streams[g])
+                (void)hipStreamDestroy(streams[g]);
+        }
+        if (io)
+            (void)hipStreamDestroy(io);
+        (void)hipFree(arena);
+        (void)hipFree(shared);
+        (void)hipFree(err);
+    }
+};
+
+}  // namespace
+
+struct ilg_server {
+    std::unique_ptr<ilg::serve::Scheduler> sched;
+    DeviceExecutor ex;
+};
+
+extern "C" {
+
+double ilg_server_clock(void)
+{
+    return steady_now();
+}
+
+int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server **out)
+{
+    if (!out || budget_bytes < 4096 || quantum_steps == 0)
+        return sfail(ILG_E_INVALID, "need an output, a budget of at least 4 KiB and a quantum > 0");
+    *out = nullptr;
+    (void)ilg::device_cu_count();
+    ilg_server *s = new (std::nothrow) ilg_server;
+    if (!s)
+        return sfail(ILG_E_NOMEM, "host allocation failed");
+    s->sched.reset(new ilg::serve::Scheduler(budget_bytes, quantum_steps));
+    DeviceExecutor &ex = s->ex;
+    hipError_t e = hipMalloc(&ex.arena, budget_bytes);
+    if (e == hipSuccess)
+        e = hipMalloc(&ex.shared, ilg::kServeTableBytes + ilg::kServeGuideBytes);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&ex.err, sizeof(uint32_t));
+    for (int g = 0; g < 4 && e == hipSuccess; ++g)
+        e = hipStreamCreateWithFlags(&ex.streams[g], hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&ex.io, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        std::vector<unsigned char> sh(ilg::kServeTableBytes + ilg::kServeGuideBytes, 0);
+        uint32_t *tab = reinterpret_cast<uint32_t *>(sh.data());
+        ilg::build_binomial_table(uint64_t(1) << 31, tab);
+        DeviceExecutor::guide(tab, sh.data() + ilg::kServeTableBytes);
+        e = hipMemcpy(ex.shared, sh.data(), sh.size(), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess)
+        e = hipMemset(ex.err, 0, sizeof(uint32_t));
+    if (e != hipSuccess) {
+        const int code = e == hipErrorOutOfMemory ? ILG_E_NOMEM : ILG_E_DEVICE;
+        std::string msg = std::string("server setup: ") + hipGetErrorString(e);
+        delete s;
+        return sfail(code, msg);
+    }
+    *out = s;
+    return ILG_OK;
+}
+
+int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_host, uint64_t nsteps,
+                      uint64_t *id)
+{
+    if (!s || !init_host || !id)
+        return sfail(ILG_E_INVALID, "null argument");
+    ilg::Fixed fx;
+    int rc = ilg::check_config(cfg, &fx);
+    if (rc != ILG_OK)
+        return rc;
+    if (nsteps == 0)
+        return sfail(ILG_E_INVALID, "nsteps must be positive");
+    if (cfg->t0 + nsteps > (uint64_t(1) << 32))
+        return sfail(ILG_E_RANGE, "step index would pass 2^32 - 1");
+    auto p = std::make_shared<Payload>();
+    p->cfg = *cfg;
+    p->fx = fx;
+    const size_t bytes = (size_t)cfg->q * cfg->length * cfg->count_bytes;
+    p->host.assign(static_cast<const unsigned char *>(init_host),
+                   static_cast<const unsigned char *>(init_host) + bytes);
+    std::unique_ptr<Req> r(new Req);
+    r->q = cfg->q;
+    r->total = nsteps;
+    r->payload = p;
+    if (!s->sched->submit(std::move(r), s->ex, id, steady_now()))
+        return sfail(ILG_E_BUSY, "request does not fit the server's memory budget");
+    return ILG_OK;
+}
+
+int ilg_server_poll(ilg_server *s, ilg_poll_info *info)
+{
+    if (!s)
+        return sfail(ILG_E_INVALID, "null server");
+    ilg::serve::PollStats st;
+    int rc = s->sched->poll(s->ex, &st, &steady_now);
+    if (rc != 0)
+        return rc;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->admitted = st.admitted;
+        info->active = st.active;
+        info->queued = st.queued;
+        info->finished = st.finished;
+        info->quantum_steps = st.quantum_steps;
+        info->bytes_in_use = s->sched->used_bytes();
+        info->bytes_peak = s->sched->peak_bytes();
+    }
+    return ILG_OK;
+}
+
+int ilg_server_info(ilg_server *s, uint64_t id, ilg_request_info *out)
+{
+    if (!s || !out)
+        return sfail(ILG_E_INVALID, "null argument");
+    Req *r = s->sched->find(id);
+    if (!r)
+        return sfail(ILG_E_INVALID, "unknown request id");
+    const Payload *p = static_cast<const Payload *>(r->payload.get());
+    std::memset(out, 0, sizeof(*out));
+    out->id = r->id;
+    out->state = (uint32_t)r->state;
+    out->q = r->q;
+    out->length = p ? p->cfg.length : 0;
+    out->steps_total = r->total;
+    out->steps_done = r->done;
+    out->t_submit = r->t_submit;
+    out->t_admit = r->t_admit;
+    out->t_done = r->t_done;
+    return ILG_OK;
+}
+
+int ilg_server_result(ilg_server *s, uint64_t id, void *host_out)
+{
+    if (!s || !host_out)
+        return sfail(ILG_E_INVALID, "null argument");
+    Req *r = s->sched->find(id);
+    if (!r || r->state != ReqState::Done)
+        return sfail(ILG_E_INVALID, "request is not finished");
+    const Payload *p = static_cast<const Payload *>(r->payload.get());
+    std::memcpy(host_out, p->host.data(), p->host.size());
+    s->sched->release(id);
+    return ILG_OK;
+}
+
+int ilg_server_cancel(ilg_server *s, uint64_t id)
+{
+    if (!s)
+        return sfail(ILG_E_INVALID, "null server");
+    if (!s->sched->cancel(id))
+        return sfail(ILG_E_INVALID, "request is not queued or active");
+    s->sched->release(id);
+    return ILG_OK;
+}
+
+int ilg_server_destroy(ilg_server *s)
+{
+    if (!s)
+        return ILG_OK;
+    for (int g = 0; g < 4; ++g)
+        if (s->ex.streams[g])
+            (void)hipStreamSynchronize(s->ex.streams[g]);
+    delete s;
+    return ILG_OK;
+}
+
+}  // extern "C"

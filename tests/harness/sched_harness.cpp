@@ -1,0 +1,168 @@
+// Test harness: the serving scheduler (paper_2203_01380_amd/csrc/scheduler.cpp)
+// driven by a counting executor on the CPU, behind a small C API for ctypes.
+// The executor checks the scheduler's contract: a request is loaded once,
+// advanced only while active, never by more than the quantum or past its
+// step count, unloaded once when done; and the arena never exceeds the
+// budget while the sum of active footprints matches the arena's use.
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "scheduler.h"
+
+using namespace ilg::serve;
+
+namespace {
+
+struct Counting : Executor {
+    uint32_t quantum = 0;
+    uint64_t budget = 0;
+    std::map<uint64_t, uint64_t> steps_seen, loads, unloads;
+    std::vector<uint64_t> load_order;
+    uint64_t active_bytes = 0;
+    int violations = 0;
+    uint64_t footprint(const Req &r) override
+    {
+        return *static_cast<const uint64_t *>(r.payload.get());
+    }
+    int load(Req &r) override
+    {
+        loads[r.id] += 1;
+        load_order.push_back(r.id);
+        active_bytes += r.bytes;
+        if (r.mem_off + r.bytes > budget)
+            ++violations;
+        return 0;
+    }
+    int run(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) override
+    {
+        for (size_t i = 0; i < active.size(); ++i) {
+            Req *r = active[i];
+            if (r->state != ReqState::Active || steps[i] == 0 || steps[i] > quantum ||
+                r->done + steps[i] > r->total)
+                ++violations;
+            steps_seen[r->id] += steps[i];
+        }
+        return 0;
+    }
+    int unload(Req &r) override
+    {
+        unloads[r.id] += 1;
+        active_bytes -= r.bytes;
+        if (steps_seen[r.id] != r.total)
+            ++violations;
+        return 0;
+    }
+};
+
+double fake_now = 0.0;
+double fake_clock()
+{
+    fake_now += 1.0;
+    return fake_now;
+}
+
+struct Harness {
+    Scheduler sched;
+    Counting ex;
+    Harness(uint64_t budget, uint32_t quantum) : sched(budget, quantum)
+    {
+        ex.quantum = quantum;
+        ex.budget = budget;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+void *h_new(uint64_t budget, uint32_t quantum)
+{
+    return new Harness(budget, quantum);
+}
+
+void h_free(void *h)
+{
+    delete static_cast<Harness *>(h);
+}
+
+int h_submit(void *hv, uint32_t q, uint64_t bytes, uint64_t steps, uint64_t *id)
+{
+    Harness *h = static_cast<Harness *>(hv);
+    std::unique_ptr<Req> r(new Req);
+    r->q = q;
+    r->total = steps;
+    r->payload = std::make_shared<uint64_t>(bytes);
+    return h->sched.submit(std::move(r), h->ex, id, fake_now) ? 0 : -6;
+}
+
+int h_poll(void *hv, uint32_t *out4)
+{
+    Harness *h = static_cast<Harness *>(hv);
+    PollStats st;
+    int rc = h->sched.poll(h->ex, &st, &fake_clock);
+    out4[0] = st.admitted;
+    out4[1] = st.active;
+    out4[2] = st.queued;
+    out4[3] = st.finished;
+    if (h->sched.used_bytes() > h->ex.budget)
+        ++h->ex.violations;
+    return rc;
+}
+
+int h_state(void *hv, uint64_t id, uint64_t *done, double *t_admit, double *t_done)
+{
+    Req *r = static_cast<Harness *>(hv)->sched.find(id);
+    if (!r)
+        return -1;
+    *done = r->done;
+    *t_admit = r->t_admit;
+    *t_done = r->t_done;
+    return (int)r->state;
+}
+
+int h_cancel(void *hv, uint64_t id)
+{
+    Harness *h = static_cast<Harness *>(hv);
+    Req *r = h->sched.find(id);
+    if (r && r->state == ReqState::Active)
+        h->ex.active_bytes -= r->bytes;
+    return h->sched.cancel(id) ? 0 : -1;
+}
+
+int h_release(void *hv, uint64_t id)
+{
+    return static_cast<Harness *>(hv)->sched.release(id) ? 0 : -1;
+}
+
+uint64_t h_peak(void *hv)
+{
+    return static_cast<Harness *>(hv)->sched.peak_bytes();
+}
+
+uint64_t h_used(void *hv)
+{
+    return static_cast<Harness *>(hv)->sched.used_bytes();
+}
+
+int h_violations(void *hv)
+{
+    Harness *h = static_cast<Harness *>(hv);
+    int v = h->ex.violations;
+    if (h->ex.active_bytes != 0 && h->sched.active() == 0)
+        ++v;
+    return v;
+}
+
+int h_load_order(void *hv, uint64_t *out, int cap)
+{
+    Harness *h = static_cast<Harness *>(hv);
+    int n = (int)h->ex.load_order.size();
+    for (int i = 0; i < n && i < cap; ++i)
+        out[i] = h->ex.load_order[i];
+    return n;
+}
+
+}  // extern "C"

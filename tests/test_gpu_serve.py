@@ -1,0 +1,150 @@
+"""GPU tests of the continuous-batching server: every request's result is
+bit-identical to the same configuration run alone (plain API) and, sampled,
+to the oracle; admission respects the memory budget; requests arriving while
+others run join the shared launches."""
+import sys
+
+import numpy as np
+import pytest
+
+import ilg_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ilg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2203_01380_amd as ilg
+    return ilg
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _requests(n, seed):
+    rng = np.random.default_rng(seed)
+    lens = [1, 2, 63, 1023, 1024, 1025, 3000, 5000] + list(rng.integers(3, 4000, size=n - 8))
+    reqs = []
+    for i, L in enumerate(lens):
+        q = 2 + int(rng.integers(0, 2))
+        cb = 2 if rng.random() < 0.7 else 4
+        om = [2.0, 1.0, 0.7][i] if i < 3 else float(rng.uniform(0.5, 1.99))
+        m = dict(q=q, length=int(L), count_bytes=cb, omega=om, seed=800 + i, realization=i,
+                 t0=int(rng.integers(0, 50)))
+        init = W.init_poisson_iid(q, int(L), 40.0, cb, init_seed=1234 + i)
+        reqs.append((m, init, int(rng.integers(1, 300))))
+    return reqs
+
+
+def _alone(ilg, m, init, nsteps):
+    lat = ilg.Lattice(m["q"], m["length"], m["count_bytes"], m["omega"], m["seed"], init,
+                      realization=m["realization"], t0=m["t0"])
+    lat.step(nsteps)
+    out = lat.state()
+    lat.close()
+    return out
+
+
+def test_mixed_requests_equal_alone_and_oracle(ilg, oracle_lib):
+    """40 requests of both velocity sets and count types, lengths from 1 to
+    5000, 1..300 steps, submitted in three waves while earlier ones run."""
+    reqs = _requests(40, seed=1)
+    srv = ilg.Server(64 << 20, quantum_steps=37)
+    ids = {}
+    for k, (m, init, ns) in enumerate(reqs):
+        ids[k] = srv.submit(m, init, ns)
+        if k in (10, 25):
+            srv.poll()
+    polls = 0
+    while True:
+        st = srv.poll()
+        polls += 1
+        if st["active"] == 0 and st["queued"] == 0:
+            break
+        assert polls < 1000
+    for k, (m, init, ns) in enumerate(reqs):
+        info = srv.info(ids[k])
+        assert info["state"] == "done" and info["steps_done"] == ns
+        assert info["t_done"] >= info["t_admit"] >= info["t_submit"]
+        got = srv.result(ids[k])
+        np.testing.assert_array_equal(got, _alone(ilg, m, init, ns), err_msg=f"request {k}")
+        if k % 8 == 0:
+            p = oracle_lib.Params(m["q"], m["omega"])
+            ref, _, _ = oracle_lib.run(p, init, ns, seed=m["seed"], realization=m["realization"],
+                                       t0=m["t0"])
+            np.testing.assert_array_equal(got, ref, err_msg=f"request {k} vs oracle")
+    srv.close()
+
+
+def test_budget_admission_on_gpu(ilg):
+    """A budget that holds only a few requests: later requests wait, peak use
+    stays within the budget, and results are unchanged."""
+    reqs = [(dict(q=3, length=20000, count_bytes=2, omega=1.6, seed=50 + i, realization=i),
+             W.init_poisson_iid(3, 20000, 40.0, 2, init_seed=60 + i), 40) for i in range(6)]
+    per = 2 * 3 * 20032 * 2 + 2 * (2080 * 4 + 64 * 256)
+    budget = 2 * per + 4096
+    srv = ilg.Server(budget, quantum_steps=16)
+    ids = [srv.submit(m, init, ns) for m, init, ns in reqs]
+    first = srv.poll()
+    assert first["admitted"] == 2 and first["queued"] == 4
+    while True:
+        st = srv.poll()
+        assert st["bytes_peak"] <= budget
+        if st["active"] == 0 and st["queued"] == 0:
+            break
+    for rid, (m, init, ns) in zip(ids, reqs):
+        np.testing.assert_array_equal(srv.result(rid), _alone(ilg, m, init, ns))
+    srv.close()
+
+
+def test_busy_and_cancel(ilg):
+    srv = ilg.Server(1 << 20, quantum_steps=10)
+    big = dict(q=3, length=200000, count_bytes=2, omega=1.5, seed=1)
+    with pytest.raises(ilg.IlgError) as e:
+        srv.submit(big, np.zeros((3, 200000), np.uint16), 10)
+    assert e.value.code == -6
+    m = dict(q=2, length=5000, count_bytes=2, omega=1.5, seed=2)
+    init = W.init_poisson_iid(2, 5000, 30.0, 2, init_seed=3)
+    a = srv.submit(m, init, 100)
+    b = srv.submit(dict(m, seed=3), init, 100)
+    srv.poll()
+    srv.cancel(a)
+    while srv.poll()["active"]:
+        pass
+    assert srv.info(b)["state"] == "done"
+    np.testing.assert_array_equal(srv.result(b), _alone(ilg, dict(m, seed=3, realization=0,
+                                                                  t0=0), init, 100))
+    srv.close()
+
+
+def test_request_stream_replay(ilg):
+    """A short Poisson request stream of the serving workload's mix (q in
+    {2, 3}, L log-uniform 2^8..2^14, 100..600 steps, omega ~ U[1, 1.95]),
+    replayed through poll(): all requests finish, results of a sample equal
+    the plain runs."""
+    reqs = W.request_stream(rate_per_s=400.0, duration_s=0.2, lmax_log2=14, tmax=600)
+    pool = W.RequestInitPool(npool=2, lmax_log2=14)
+    srv = ilg.Server(256 << 20, quantum_steps=50)
+    ids = []
+    for i, rq in enumerate(reqs):
+        m = dict(q=rq.spec.q, length=rq.spec.length, count_bytes=2, omega=rq.spec.omega,
+                 seed=rq.spec.seed, realization=rq.spec.realization)
+        ids.append((srv.submit(m, pool.init(i, m["q"], m["length"]), rq.spec.steps), m, i,
+                    rq.spec.steps))
+        if i % 5 == 4:
+            srv.poll()
+    while True:
+        st = srv.poll()
+        if st["active"] == 0 and st["queued"] == 0:
+            break
+    _say(f"[serve] {len(reqs)} requests done")
+    for rid, m, i, ns in ids:
+        got = srv.result(rid)
+        if i % 7 == 0:
+            np.testing.assert_array_equal(
+                got, _alone(ilg, dict(m, t0=0), pool.init(i, m["q"], m["length"]), ns))
+    srv.close()

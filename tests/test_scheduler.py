@@ -1,0 +1,180 @@
+"""CPU tests of the serving scheduler (paper_2203_01380_amd/csrc/scheduler.cpp)
+with a counting executor: admission under the memory budget, FIFO order,
+quantum advances, retirement, cancellation and the arena allocator."""
+import ctypes
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2203_01380_amd", "csrc")
+HARNESS = os.path.join(ROOT, "tests", "harness", "sched_harness.cpp")
+
+
+@pytest.fixture(scope="module")
+def H(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if not gxx:
+        pytest.skip("g++ not available")
+    so = tmp_path_factory.mktemp("sched") / "libsched_harness.so"
+    subprocess.run([gxx, "-O1", "-g", "-std=c++17", "-fPIC", "-shared", "-Wall", "-I", CSRC,
+                    HARNESS, os.path.join(CSRC, "scheduler.cpp"), "-o", str(so)], check=True)
+    L = ctypes.CDLL(str(so))
+    L.h_new.restype = ctypes.c_void_p
+    L.h_new.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+    L.h_free.argtypes = [ctypes.c_void_p]
+    L.h_submit.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                           ctypes.POINTER(ctypes.c_uint64)]
+    L.h_poll.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]
+    L.h_state.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
+                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.h_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    L.h_release.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    L.h_peak.argtypes = [ctypes.c_void_p]
+    L.h_peak.restype = ctypes.c_uint64
+    L.h_used.argtypes = [ctypes.c_void_p]
+    L.h_used.restype = ctypes.c_uint64
+    L.h_violations.argtypes = [ctypes.c_void_p]
+    L.h_load_order.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
+    return L
+
+
+class Sched:
+    def __init__(self, H, budget, quantum):
+        self.H, self.h = H, H.h_new(budget, quantum)
+
+    def submit(self, q, nbytes, steps):
+        rid = ctypes.c_uint64()
+        rc = self.H.h_submit(self.h, q, nbytes, steps, ctypes.byref(rid))
+        return rc, int(rid.value)
+
+    def poll(self):
+        out = (ctypes.c_uint32 * 4)()
+        assert self.H.h_poll(self.h, out) == 0
+        return dict(admitted=out[0], active=out[1], queued=out[2], finished=out[3])
+
+    def state(self, rid):
+        d, ta, td = ctypes.c_uint64(), ctypes.c_double(), ctypes.c_double()
+        s = self.H.h_state(self.h, rid, ctypes.byref(d), ctypes.byref(ta), ctypes.byref(td))
+        return s, int(d.value), ta.value, td.value
+
+    def load_order(self):
+        buf = (ctypes.c_uint64 * 4096)()
+        n = self.H.h_load_order(self.h, buf, 4096)
+        return list(buf[:n])
+
+    def close(self):
+        self.H.h_free(self.h)
+
+
+def drain(s, limit=100000):
+    for _ in range(limit):
+        st = s.poll()
+        if st["active"] == 0 and st["queued"] == 0:
+            return
+    raise AssertionError("scheduler did not drain")
+
+
+def test_all_requests_complete_exactly(H):
+    s = Sched(H, 1 << 20, 7)
+    ids = [s.submit(2 + (i % 2), 1000 + 37 * i, 1 + 13 * i)[1] for i in range(30)]
+    drain(s)
+    for rid, i in zip(ids, range(30)):
+        st, done, ta, td = s.state(rid)
+        assert st == 2 and done == 1 + 13 * i and td > ta
+    assert H.h_violations(s.h) == 0 and H.h_used(s.h) == 0
+    s.close()
+
+
+def test_budget_admission_fifo_and_reuse(H):
+    budget = 10_000
+    s = Sched(H, budget, 5)
+    sizes = [4000, 4000, 4000, 1000, 9000, 500]
+    ids = [s.submit(3, b, 12)[1] for b in sizes]
+    first = s.poll()
+    assert first["admitted"] == 2 and first["queued"] == 4   # third 4000 does not fit
+    drain(s)
+    assert s.load_order() == ids                             # strict FIFO, no overtaking
+    assert H.h_peak(s.h) <= budget and H.h_violations(s.h) == 0
+    s.close()
+
+
+def test_request_larger_than_budget_is_refused(H):
+    s = Sched(H, 4096, 5)
+    rc, _ = s.submit(2, 5000, 10)
+    assert rc == -6
+    rc, _ = s.submit(2, 4096, 10)
+    assert rc == 0
+    rc, _ = s.submit(2, 100, 0)      # zero steps is refused too
+    assert rc == -6
+    drain(s)
+    s.close()
+
+
+def test_cancel_queued_and_active(H):
+    s = Sched(H, 8000, 3)
+    a = s.submit(2, 5000, 30)[1]
+    b = s.submit(2, 5000, 30)[1]       # waits for a
+    c = s.submit(2, 2000, 30)[1]
+    s.poll()
+    assert s.state(a)[0] == 1 and s.state(b)[0] == 0
+    assert H.h_cancel(s.h, b) == 0     # queued
+    assert H.h_cancel(s.h, a) == 0     # active: memory returns
+    assert H.h_used(s.h) <= 2048 + 256
+    drain(s)
+    assert s.state(c)[0] == 2 and s.state(a)[0] == 3 and s.state(b)[0] == 3
+    assert H.h_cancel(s.h, c) != 0     # finished requests cannot be cancelled
+    assert H.h_release(s.h, c) == 0 and s.state(c)[0] == -1
+    assert H.h_violations(s.h) == 0
+    s.close()
+
+
+def test_latency_bookkeeping(H):
+    s = Sched(H, 1 << 20, 10)
+    rid = s.submit(3, 100, 35)[1]
+    polls = 0
+    while s.state(rid)[0] != 2:
+        s.poll()
+        polls += 1
+    assert polls == 4                   # ceil(35 / 10) quanta after admission
+    _, done, ta, td = s.state(rid)
+    assert done == 35 and td > ta
+    s.close()
+
+
+def test_arena_coalescing_allows_full_budget_again(H):
+    s = Sched(H, 64 * 1024, 2)
+    ids = [s.submit(2, 8 * 1024, 3)[1] for _ in range(8)]
+    drain(s)
+    assert H.h_used(s.h) == 0
+    big = s.submit(2, 64 * 1024, 1)[1]  # needs the whole arena in one block
+    st = s.poll()
+    assert st["admitted"] == 1
+    drain(s)
+    assert s.state(big)[0] == 2 and H.h_violations(s.h) == 0
+    s.close()
+
+
+def test_random_stress(H):
+    rng = np.random.default_rng(7)
+    budget = 200_000
+    s = Sched(H, budget, 16)
+    live = []
+    for it in range(600):
+        if rng.random() < 0.6:
+            rc, rid = s.submit(int(rng.integers(2, 4)), int(rng.integers(1, 60_000)),
+                               int(rng.integers(1, 200)))
+            assert rc == 0
+            live.append(rid)
+        if live and rng.random() < 0.05:
+            rid = live.pop(int(rng.integers(len(live))))
+            H.h_cancel(s.h, rid)
+        s.poll()
+        assert H.h_used(s.h) <= budget
+    drain(s)
+    assert H.h_violations(s.h) == 0 and H.h_used(s.h) == 0
+    assert H.h_peak(s.h) <= budget
+    s.close()
