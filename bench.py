@@ -204,6 +204,37 @@ def bench_serving(ilg, W, rate: float, duration: float, budget: int, quantum: in
             "peak_bytes": int(peak), "budget_bytes": budget, "quantum_steps": quantum}
 
 
+def summarize_counters(fetch_csv: str, write_csv: str, out_path: str):
+    """Turn two rocprofv3 --pmc runs of `bench.py --forms plain --copy-probe`
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) into HBM bytes per step
+    launch.  Each counter is scaled by what it reads for the probe copy of
+    768 MiB (the largest copy dispatch), so the record is in true bytes."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        step = [float(r["Counter_Value"]) for r in rows if "step_kernel" in r["Kernel_Name"]]
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
+                  or "copy" in r["Kernel_Name"].lower()]
+        return float(np.mean(step)), max(copies)
+
+    probe_kib = (768 << 20) / 1024.0
+    f_step, f_copy = per_kernel(fetch_csv, "FETCH_SIZE")
+    w_step, w_copy = per_kernel(write_csv, "WRITE_SIZE")
+    f_scale, w_scale = probe_kib / f_copy, probe_kib / w_copy
+    rec = {"step_source_sha256_16": step_source_digest(),
+           "fetch_kib_raw": f_step, "write_kib_raw": w_step,
+           "copy_probe_fetch_kib_raw": f_copy, "copy_probe_write_kib_raw": w_copy,
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "fetch_bytes_per_launch": f_step * f_scale * 1024,
+           "write_bytes_per_launch": w_step * w_scale * 1024,
+           "bytes_per_launch": (f_step * f_scale + w_step * w_scale) * 1024,
+           "alg_bytes_per_launch": 12 * (1 << 24)}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,7 +254,12 @@ def main():
     ap.add_argument("--loop-members", type=int, default=32)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, one plain device copy of 768 MiB (counter scale)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the counter traffic record from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, TRAFFIC_FILE)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(ensembles would shard by realization, one lattice along x).", file=sys.stderr)

@@ -42,7 +42,7 @@ def _requests(n, seed):
 
 def _alone(ilg, m, init, nsteps):
     lat = ilg.Lattice(m["q"], m["length"], m["count_bytes"], m["omega"], m["seed"], init,
-                      realization=m["realization"], t0=m["t0"])
+                      realization=m.get("realization", 0), t0=m.get("t0", 0))
     lat.step(nsteps)
     out = lat.state()
     lat.close()
