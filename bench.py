@@ -107,7 +107,7 @@ def bench_batched_ragged(ilg, W, stream, steps: int, loop_members: int):
     members = [dict(q=s.q, length=s.length, count_bytes=s.count_bytes, omega=s.omega,
                     seed=s.seed, realization=s.realization) for s in ens.specs]
     b = ilg.Batch(members, ens.inits, sk_every=10, nk=16)
-    shape = b.tune(10)
+    shape = b.tune(40)
     sec = timed(stream, lambda: b.run(steps))
     nu = ens.total_nodes * steps
     b.close()
@@ -145,7 +145,7 @@ def bench_batched_decay(ilg, W, stream, steps: int):
     members = [dict(q=s.q, length=s.length, count_bytes=s.count_bytes, omega=s.omega,
                     seed=s.seed, realization=s.realization) for s in ens.specs]
     b = ilg.Batch(members, ens.inits, amp_every=100, max_amp=steps // 100 + 1)
-    shape = b.tune(10)
+    shape = b.tune(40)
     sec = timed(stream, lambda: b.run(steps))
     b.close()
     nu = ens.total_nodes * steps

@@ -141,12 +141,18 @@ __device__ __forceinline__ void sk_sample(const BatchArgs &a, uint32_t r, const 
         a.sk_cnt[r] += 1ull;
 }
 
-// The diagnostics (FP64 phases) need about twice the registers of the step
-// loop; the occupancy attribute caps the register count so that the rare
-// diagnostic code spills instead of the step loop losing waves.
-template <int Q, typename T, int BLOCK, int GB>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void batch_kernel(
-    BatchArgs a)
+// SK: the launch samples S(k).  Those FP64 accumulators need about twice
+// the registers of the step loop, so the S(k) variant carries an occupancy
+// attribute that caps the register count (the rare diagnostic code spills
+// instead of the step loop losing waves); launches without S(k) use the
+// variant without it.  kMinWaves(BLOCK) is the waves per SIMD needed for two
+// workgroups of 1024 threads (8) or enough smaller ones (6).
+template <int BLOCK>
+constexpr int kMinWaves = BLOCK >= 1024 ? 8 : 6;
+
+template <int Q, typename T, int BLOCK, int GB, bool SK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kMinWaves<BLOCK>, 8)))
+void batch_kernel(BatchArgs a)
 {
     using W = typename Wide<T>::type;
     constexpr int NB = (Q == 3) ? 2 : 1;
@@ -225,8 +231,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
             cur ^= 1u;
             const uint32_t t_after = t + 1u;
             const T *st = base + cur * qp;
-            if (a.sk_every != 0 && t_after % a.sk_every == 0)
-                sk_sample<Q, T, BLOCK>(a, r, st, L, pitch, s_red, s_redu);
+            if constexpr (SK) {
+                if (a.sk_every != 0 && t_after % a.sk_every == 0)
+                    sk_sample<Q, T, BLOCK>(a, r, st, L, pitch, s_red, s_redu);
+            }
             if (a.amp_every != 0 && t_after % a.amp_every == 0) {
                 double num = 0.0, den = 0.0;
                 for (uint32_t x = threadIdx.x; x < L; x += BLOCK) {
@@ -265,27 +273,49 @@ __global__ void batch_reset_kernel(uint32_t *queue)
 
 struct Shape {
     int block;
+    int guide_bits;
     int wg_per_cu_q2;
     int wg_per_cu_q3;
 };
-// LDS per workgroup: q = 2 about 17 KB, q = 3 about 37 KB (tables + 64-bucket
-// guides), so LDS allows up to 9 (q = 2) or 4 (q = 3) workgroups per CU.
-constexpr Shape kShapes[] = {{256, 6, 4}, {512, 3, 2}, {1024, 2, 2}, {128, 8, 4}};
+// LDS per workgroup: tables 8320 B each plus guides of 64 rows x 2^GB bytes;
+// q = 2 holds two tables, q = 3 three.  Workgroups per CU follow from the
+// 160 KB of LDS and 32 waves per CU.
+constexpr Shape kShapes[] = {
+    {256, 6, 6, 4},  {512, 6, 3, 2},  {1024, 6, 2, 2}, {128, 6, 8, 4},
+    {256, 8, 3, 2},  {512, 8, 3, 2},  {1024, 8, 2, 2},
+};
 
-template <int Q, typename T, int BLOCK>
+template <int Q, typename T, int BLOCK, int GB>
 hipError_t launch_shape(const BatchArgs &a, hipStream_t stream, int wg_per_cu)
 {
-    static int cus = 0;
-    if (cus == 0)
-        cus = device_cu_count();
-    uint32_t grid = (uint32_t)cus * (uint32_t)wg_per_cu;
+    const uint32_t cus = (uint32_t)device_cu_count();
+    uint32_t grid = cus * (uint32_t)wg_per_cu;
     if (grid > a.nreal)
         grid = a.nreal;
     if (grid == 0)
         grid = 1;
-    hipLaunchKernelGGL((batch_kernel<Q, T, BLOCK, kBatchGuideBits>), dim3(grid), dim3(BLOCK), 0,
-                       stream, a);
+    if (a.sk_every != 0)
+        hipLaunchKernelGGL((batch_kernel<Q, T, BLOCK, GB, true>), dim3(grid), dim3(BLOCK), 0,
+                           stream, a);
+    else
+        hipLaunchKernelGGL((batch_kernel<Q, T, BLOCK, GB, false>), dim3(grid), dim3(BLOCK), 0,
+                           stream, a);
     return hipGetLastError();
+}
+
+template <int Q, typename T, int GB>
+hipError_t launch_block(int block, const BatchArgs &a, hipStream_t stream, int wg)
+{
+    switch (block) {
+    case 128:
+        return launch_shape<Q, T, 128, GB>(a, stream, wg);
+    case 512:
+        return launch_shape<Q, T, 512, GB>(a, stream, wg);
+    case 1024:
+        return launch_shape<Q, T, 1024, GB>(a, stream, wg);
+    default:
+        return launch_shape<Q, T, 256, GB>(a, stream, wg);
+    }
 }
 
 template <int Q, typename T>
@@ -293,16 +323,9 @@ hipError_t launch_qt(int shape, const BatchArgs &a, hipStream_t stream)
 {
     const Shape &s = kShapes[shape];
     const int wg = (Q == 3) ? s.wg_per_cu_q3 : s.wg_per_cu_q2;
-    switch (s.block) {
-    case 128:
-        return launch_shape<Q, T, 128>(a, stream, wg);
-    case 512:
-        return launch_shape<Q, T, 512>(a, stream, wg);
-    case 1024:
-        return launch_shape<Q, T, 1024>(a, stream, wg);
-    default:
-        return launch_shape<Q, T, 256>(a, stream, wg);
-    }
+    if (s.guide_bits == 8)
+        return launch_block<Q, T, 8>(s.block, a, stream, wg);
+    return launch_block<Q, T, 6>(s.block, a, stream, wg);
 }
 
 }  // namespace
