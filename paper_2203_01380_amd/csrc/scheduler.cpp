@@ -80,11 +80,43 @@ bool Scheduler::submit(std::unique_ptr<Req> r, Executor &ex, uint64_t *id, doubl
     return true;
 }
 
-int Scheduler::poll(Executor &ex, PollStats *st, double (*clock)())
+int Scheduler::settle(Executor &ex, double (*clock)(), uint32_t *finished)
 {
-    PollStats s;
-    // Admission: strict FIFO, so a large request is never starved by later
-    // small ones.
+    uint32_t nfin = 0;
+    if (!inflight_.empty()) {
+        int rc = ex.wait();
+        if (rc != 0)
+            return rc;
+        const double now = clock();
+        for (size_t i = 0; i < inflight_.size(); ++i) {
+            Req *r = inflight_[i];
+            r->done += inflight_steps_[i];
+            if (r->done >= r->total) {
+                rc = ex.unload(*r);
+                if (rc != 0)
+                    return rc;
+                arena_.free(r->mem_off, r->bytes);
+                r->state = ReqState::Done;
+                r->t_done = now;
+                ++nfin;
+            }
+        }
+        std::vector<Req *> still;
+        for (Req *r : active_)
+            if (r->state == ReqState::Active)
+                still.push_back(r);
+        active_.swap(still);
+        inflight_.clear();
+        inflight_steps_.clear();
+    }
+    if (finished)
+        *finished = nfin;
+    return 0;
+}
+
+int Scheduler::admit(Executor &ex, double (*clock)(), uint32_t *admitted)
+{
+    // Strict FIFO, so a large request is never starved by later small ones.
     while (!queue_.empty()) {
         Req *r = queue_.front();
         uint64_t off = 0;
@@ -100,36 +132,38 @@ int Scheduler::poll(Executor &ex, PollStats *st, double (*clock)())
         r->t_admit = clock();
         queue_.pop_front();
         active_.push_back(r);
-        ++s.admitted;
+        ++*admitted;
     }
+    return 0;
+}
+
+int Scheduler::poll(Executor &ex, PollStats *st, double (*clock)())
+{
+    PollStats s;
+    // Admissions into memory that is already free overlap the quantum in
+    // flight (they touch only their own, unused, memory); a second pass after
+    // the quantum has completed uses the memory its finished requests freed.
+    int rc = admit(ex, clock, &s.admitted);
+    if (rc == 0)
+        rc = settle(ex, clock, &s.finished);
+    if (rc == 0)
+        rc = admit(ex, clock, &s.admitted);
+    if (rc != 0)
+        return rc;
     if (!active_.empty()) {
-        std::vector<uint32_t> steps(active_.size());
+        inflight_ = active_;
+        inflight_steps_.resize(active_.size());
         for (size_t i = 0; i < active_.size(); ++i) {
             const uint64_t left = active_[i]->total - active_[i]->done;
-            steps[i] = (uint32_t)std::min<uint64_t>(left, quantum_);
-            s.quantum_steps = std::max(s.quantum_steps, steps[i]);
+            inflight_steps_[i] = (uint32_t)std::min<uint64_t>(left, quantum_);
+            s.quantum_steps = std::max(s.quantum_steps, inflight_steps_[i]);
         }
-        int rc = ex.run(active_, steps);
-        if (rc != 0)
+        rc = ex.launch(inflight_, inflight_steps_);
+        if (rc != 0) {
+            inflight_.clear();
+            inflight_steps_.clear();
             return rc;
-        const double now = clock();
-        std::vector<Req *> still;
-        for (size_t i = 0; i < active_.size(); ++i) {
-            Req *r = active_[i];
-            r->done += steps[i];
-            if (r->done >= r->total) {
-                rc = ex.unload(*r);
-                if (rc != 0)
-                    return rc;
-                arena_.free(r->mem_off, r->bytes);
-                r->state = ReqState::Done;
-                r->t_done = now;
-                ++s.finished;
-            } else {
-                still.push_back(r);
-            }
         }
-        active_.swap(still);
     }
     s.active = (uint32_t)active_.size();
     s.queued = (uint32_t)queue_.size();
@@ -144,7 +178,7 @@ Req *Scheduler::find(uint64_t id)
     return it == all_.end() ? nullptr : it->second.get();
 }
 
-bool Scheduler::cancel(uint64_t id)
+bool Scheduler::cancel(uint64_t id, Executor &ex, double (*clock)())
 {
     Req *r = find(id);
     if (!r)
@@ -152,6 +186,9 @@ bool Scheduler::cancel(uint64_t id)
     if (r->state == ReqState::Queued) {
         queue_.erase(std::find(queue_.begin(), queue_.end(), r));
     } else if (r->state == ReqState::Active) {
+        // the device may still be writing its memory: finish the quantum first
+        if (settle(ex, clock, nullptr) != 0 || r->state != ReqState::Active)
+            return false;
         active_.erase(std::find(active_.begin(), active_.end(), r));
         arena_.free(r->mem_off, r->bytes);
     } else {

@@ -1,12 +1,14 @@
 // Continuous-batching scheduler for lattice-gas requests (host only, no HIP).
 //
 // Requests wait in a FIFO queue until their device memory (state buffers and
-// tables) fits the budget; admitted requests become active slots, and every
-// poll advances all active slots by one quantum of steps (fewer for a slot
-// that finishes earlier) through an Executor, then retires the finished ones
-// and frees their memory for the next admissions.  The executor does the
-// device work; the scheduler only does bookkeeping, so it is tested on the
-// CPU with a counting executor.
+// tables) fits the budget; admitted requests become active slots.  Each poll
+// admits what fits memory that is already free (its copies overlap the quantum
+// in flight), waits for the quantum launched by the previous poll, retires the
+// requests it finished (freeing their memory), admits again, and launches the
+// next quantum for every active slot (fewer steps for a slot that finishes
+// earlier).  It returns while the device works, so the caller's host work
+// overlaps the quantum.  The executor does the device work; the scheduler only
+// does bookkeeping, so it is tested on the CPU with a counting executor.
 #pragma once
 
 #include <cstdint>
@@ -54,15 +56,18 @@ public:
     virtual uint64_t footprint(const Req &r) = 0;
     // Place the request's initial state and tables at r.mem_off.
     virtual int load(Req &r) = 0;
-    // Advance active[i] by steps[i] >= 1 steps; returns when the work is done.
-    virtual int run(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) = 0;
+    // Start advancing active[i] by steps[i] >= 1 steps (may return before the
+    // work is done).
+    virtual int launch(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) = 0;
+    // Wait for the work of the last launch.
+    virtual int wait() = 0;
     // Copy a finished request's final state out of the device.
     virtual int unload(Req &r) = 0;
 };
 
 struct PollStats {
     uint32_t admitted = 0, active = 0, queued = 0, finished = 0;
-    uint32_t quantum_steps = 0;  // steps of the longest slot advance in this poll
+    uint32_t quantum_steps = 0;  // steps of the longest slot advance launched by this poll
 };
 
 class Scheduler {
@@ -71,11 +76,16 @@ public:
     // Queue a request; ILG_E_BUSY-style failure (returns false) if it could
     // never fit the budget.
     bool submit(std::unique_ptr<Req> r, Executor &ex, uint64_t *id, double now);
-    // Admit what fits (FIFO), run one quantum, retire finished requests.
+    // Wait for the previous quantum and retire what it finished, admit what
+    // fits (FIFO), launch the next quantum.  After a poll that reports no
+    // active and no queued request, nothing is in flight.
     int poll(Executor &ex, PollStats *st, double (*clock)());
+    // Wait for the quantum in flight, if any (and retire what it finished).
+    int settle(Executor &ex, double (*clock)(), uint32_t *finished);
     Req *find(uint64_t id);
-    // Cancel a queued or active request (its memory is released).
-    bool cancel(uint64_t id);
+    // Cancel a queued or active request (its memory is released; an active
+    // one only after the quantum in flight has completed).
+    bool cancel(uint64_t id, Executor &ex, double (*clock)());
     // Forget a finished or cancelled request.
     bool release(uint64_t id);
     uint64_t peak_bytes() const { return arena_.peak(); }
@@ -84,12 +94,16 @@ public:
     size_t active() const { return active_.size(); }
 
 private:
+    int admit(Executor &ex, double (*clock)(), uint32_t *admitted);
+
     uint64_t budget_;
     uint32_t quantum_;
     Arena arena_;
     uint64_t next_id_ = 1;
     std::deque<Req *> queue_;
     std::vector<Req *> active_;
+    std::vector<Req *> inflight_;       // slots of the quantum in flight
+    std::vector<uint32_t> inflight_steps_;
     std::map<uint64_t, std::unique_ptr<Req>> all_;
 };
 

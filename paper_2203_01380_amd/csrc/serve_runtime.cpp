@@ -145,10 +145,23 @@ public:
         }
     }
 
-    int run(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) override
+    // Host copies of the last launch's slot and tile lists (kept alive until
+    // the copies from them have completed).
+    std::vector<ilg::ServeSlot> h_slots[4];
+    std::vector<ilg::ServeTile> h_tiles[4];
+    std::vector<Req *> launched;
+    std::vector<uint32_t> launched_steps;
+
+    int launch(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) override
     {
-        std::vector<ilg::ServeSlot> slots[4];
-        std::vector<ilg::ServeTile> tiles[4];
+        std::vector<ilg::ServeSlot> *slots = h_slots;
+        std::vector<ilg::ServeTile> *tiles = h_tiles;
+        for (int g = 0; g < 4; ++g) {
+            slots[g].clear();
+            tiles[g].clear();
+        }
+        launched = active;
+        launched_steps = steps;
         uint32_t maxsteps[4] = {0, 0, 0, 0};
         for (size_t i = 0; i < active.size(); ++i) {
             Req &r = *active[i];
@@ -200,18 +213,25 @@ public:
                     return shfail(e, "serve launch");
             }
         }
+        return ILG_OK;
+    }
+
+    int wait() override
+    {
         for (int g = 0; g < 4; ++g)
-            if (!slots[g].empty())
+            if (!h_slots[g].empty())
                 SHIP(hipStreamSynchronize(streams[g]));
         uint32_t e = 0;
         SHIP(hipMemcpy(&e, err, sizeof(e), hipMemcpyDeviceToHost));
         if (e & 1u)
             return sfail(ILG_E_OVERFLOW, "a post-collision count exceeded the count type");
-        for (size_t i = 0; i < active.size(); ++i) {
-            Payload *p = payload_of(*active[i]);
-            p->t += steps[i];
-            p->cur ^= (steps[i] & 1u);
+        for (size_t i = 0; i < launched.size(); ++i) {
+            Payload *p = payload_of(*launched[i]);
+            p->t += launched_steps[i];
+            p->cur ^= (launched_steps[i] & 1u);
         }
+        launched.clear();
+        launched_steps.clear();
         return ILG_OK;
     }
 
@@ -399,7 +419,7 @@ int ilg_server_cancel(ilg_server *s, uint64_t id)
 {
     if (!s)
         return sfail(ILG_E_INVALID, "null server");
-    if (!s->sched->cancel(id))
+    if (!s->sched->cancel(id, s->ex, &steady_now))
         return sfail(ILG_E_INVALID, "request is not queued or active");
     s->sched->release(id);
     return ILG_OK;
@@ -409,6 +429,7 @@ int ilg_server_destroy(ilg_server *s)
 {
     if (!s)
         return ILG_OK;
+    (void)s->sched->settle(s->ex, &steady_now, nullptr);
     for (int g = 0; g < 4; ++g)
         if (s->ex.streams[g])
             (void)hipStreamSynchronize(s->ex.streams[g]);

@@ -36,8 +36,12 @@ struct Counting : Executor {
             ++violations;
         return 0;
     }
-    int run(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) override
+    bool in_flight = false;
+    int launch(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) override
     {
+        if (in_flight)
+            ++violations;  // a launch before the previous one was waited for
+        in_flight = true;
         for (size_t i = 0; i < active.size(); ++i) {
             Req *r = active[i];
             if (r->state != ReqState::Active || steps[i] == 0 || steps[i] > quantum ||
@@ -47,8 +51,15 @@ struct Counting : Executor {
         }
         return 0;
     }
+    int wait() override
+    {
+        in_flight = false;
+        return 0;
+    }
     int unload(Req &r) override
     {
+        if (in_flight)
+            ++violations;  // results read while their quantum may still run
         unloads[r.id] += 1;
         active_bytes -= r.bytes;
         if (steps_seen[r.id] != r.total)
@@ -127,9 +138,14 @@ int h_cancel(void *hv, uint64_t id)
 {
     Harness *h = static_cast<Harness *>(hv);
     Req *r = h->sched.find(id);
-    if (r && r->state == ReqState::Active)
+    const bool was_active = r && r->state == ReqState::Active;
+    const bool ok = h->sched.cancel(id, h->ex, &fake_clock);
+    if (ok && was_active) {
+        if (h->ex.in_flight)
+            ++h->ex.violations;  // memory freed under a running quantum
         h->ex.active_bytes -= r->bytes;
-    return h->sched.cancel(id) ? 0 : -1;
+    }
+    return ok ? 0 : -1;
 }
 
 int h_release(void *hv, uint64_t id)
