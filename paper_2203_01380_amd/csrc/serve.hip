@@ -48,6 +48,8 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     constexpr W kMax = (W)(T)~(T)0;
     bool overflow = false;
 
+    __syncthreads();  // the shared half table is visible to every wave
+
     const uint32_t lo = (uint32_t)((uint64_t)a.ntiles * blockIdx.x / gridDim.x);
     const uint32_t hi = (uint32_t)((uint64_t)a.ntiles * (blockIdx.x + 1) / gridDim.x);
     uint32_t staged = 0xFFFFFFFFu;
@@ -57,7 +59,10 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         if (a.j >= sl.steps)
             continue;
         if (tl.slot != staged) {
-            __syncthreads();  // previous slot's readers are done with LDS
+            // Barriers only where the walk enters a new slot: before the
+            // restage (readers of the previous slot's tables are done) and
+            // after it (the new tables are visible).
+            __syncthreads();
             const uint8_t *set = reinterpret_cast<const uint8_t *>(a.arena) + sl.table_off;
             const int nt = (Q == 3) ? 2 : 1;  // removal (+ rest) tables
             for (int t = 0; t < nt; ++t) {
@@ -72,8 +77,8 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
                     gdst[i] = gsrc[i];
             }
             staged = tl.slot;
+            __syncthreads();
         }
-        __syncthreads();
         const uint32_t x = tl.x0 + threadIdx.x;
         const uint32_t L = sl.length;
         if (x >= L)
