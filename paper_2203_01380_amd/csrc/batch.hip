@@ -71,7 +71,7 @@ __device__ __forceinline__ void build_guide_lds(const uint32_t *tab, uint8_t *gu
     for (int e = threadIdx.x; e < kChunk * kRow; e += BLOCK) {
         const uint32_t m = (uint32_t)(e >> GB) + 1u;
         const uint32_t edge = (uint32_t)(e & (kRow - 1)) << (32 - GB);
-        const uint32_t *row = tab + (((m - 1u) * m) >> 1);
+        const uint32_t *row = tab + dev_row_offset(m);
         uint32_t lo = 0, hi = m;
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
@@ -160,21 +160,21 @@ void batch_kernel(BatchArgs a)
     constexpr int kRowGuide = 1 << GB;
     constexpr int kG = kChunk * kRowGuide;
     constexpr int kWaves = BLOCK / 64;
-    __shared__ uint32_t s_tab[kTabs * kTableEntries];
+    __shared__ __align__(16) uint32_t s_tab[kTabs * kDevTableEntries];
     __shared__ uint8_t s_guide[kTabs * kG];
     __shared__ uint32_t s_next;
     __shared__ double s_red[kWaves];
     __shared__ unsigned long long s_redu[kWaves];
 
     // Shared tables (P = 2^31 and, for q = 3, P_rest) and their guides, once.
-    for (int i = threadIdx.x; i < (kTabs - 1) * kTableEntries; i += BLOCK)
-        s_tab[kTableEntries + i] = a.tabs_shared[i];
+    for (int i = threadIdx.x; i < (kTabs - 1) * kDevTableEntries; i += BLOCK)
+        s_tab[kDevTableEntries + i] = a.tabs_shared[i];
     __syncthreads();
     for (int s = 1; s < kTabs; ++s)
-        build_guide_lds<GB, BLOCK>(s_tab + s * kTableEntries, s_guide + s * kG);
+        build_guide_lds<GB, BLOCK>(s_tab + s * kDevTableEntries, s_guide + s * kG);
 
-    const uint32_t *tab_p = s_tab, *tab_half = s_tab + kTableEntries;
-    const uint32_t *tab_rest = s_tab + 2 * kTableEntries;
+    const uint32_t *tab_p = s_tab, *tab_half = s_tab + kDevTableEntries;
+    const uint32_t *tab_rest = s_tab + 2 * kDevTableEntries;
     const uint8_t *g_p = s_guide, *g_half = s_guide + kG, *g_rest = s_guide + 2 * kG;
     constexpr W kMax = (W)(T)~(T)0;
     bool overflow = false;
@@ -192,9 +192,9 @@ void batch_kernel(BatchArgs a)
         const bool p_zero = m.p_zero != 0;
         const bool flip = m.flip != 0;
         if (!p_zero) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(a.tabs_p + (size_t)r * kTableEntries);
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.tabs_p + (size_t)r * kDevTableEntries);
             uint4 *dst = reinterpret_cast<uint4 *>(s_tab);
-            for (int i = threadIdx.x; i < kTableEntries / 4; i += BLOCK)
+            for (int i = threadIdx.x; i < kDevTableEntries / 4; i += BLOCK)
                 dst[i] = src[i];
             __syncthreads();
             build_guide_lds<GB, BLOCK>(s_tab, s_guide);

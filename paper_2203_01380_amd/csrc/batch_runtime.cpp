@@ -197,24 +197,35 @@ int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *
             std::memcpy(stage.data() + (b->off[r] + i * pitch) * cb, src + i * L * cb, L * cb);
     }
 
-    // Removal tables per member (host threads), shared half/rest tables.
-    std::vector<uint32_t> tabs((size_t)nreal * ilg::kTableEntries, 0);
+    // Removal tables per member (host threads), shared half/rest tables, all
+    // in the padded device layout.
+    std::vector<uint32_t> tabs((size_t)nreal * ilg::kDevTableEntries, 0);
     {
         const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
         std::vector<std::thread> pool;
         for (unsigned k = 0; k < nth; ++k)
             pool.emplace_back([&, k]() {
+                std::vector<uint32_t> packed(ilg::kTableEntries);
                 for (uint32_t r = k; r < nreal; r += nth)
-                    if (fx[r].p != 0)
-                        ilg::build_binomial_table(fx[r].p, tabs.data() + (size_t)r * ilg::kTableEntries);
+                    if (fx[r].p != 0) {
+                        ilg::build_binomial_table(fx[r].p, packed.data());
+                        ilg::pad_table(packed.data(),
+                                       tabs.data() + (size_t)r * ilg::kDevTableEntries);
+                    }
             });
         for (auto &th : pool)
             th.join();
     }
-    std::vector<uint32_t> shared(2 * ilg::kTableEntries, 0);
-    ilg::build_binomial_table(uint64_t(1) << 31, shared.data());
-    if (q == 3)
-        ilg::build_binomial_table(fx[0].p_rest, shared.data() + ilg::kTableEntries);
+    std::vector<uint32_t> shared(2 * ilg::kDevTableEntries, 0);
+    {
+        std::vector<uint32_t> packed(ilg::kTableEntries);
+        ilg::build_binomial_table(uint64_t(1) << 31, packed.data());
+        ilg::pad_table(packed.data(), shared.data());
+        if (q == 3) {
+            ilg::build_binomial_table(fx[0].p_rest, packed.data());
+            ilg::pad_table(packed.data(), shared.data() + ilg::kDevTableEntries);
+        }
+    }
 
     // Longest first (ties by index), so long members start early.
     std::vector<uint32_t> order(nreal);

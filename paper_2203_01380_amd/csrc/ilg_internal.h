@@ -13,6 +13,15 @@ namespace ilg {
 // holds rows m = 1..64 with m entries each, row m at offset (m-1)m/2.
 constexpr int kChunk = 64;
 constexpr int kTableEntries = kChunk * (kChunk + 1) / 2;  // 2080
+// Device layout of a table: every row is followed by kRowPad all-ones
+// sentinels, so row m starts at (m-1)(m+4)/2 and a two-entry probe at any
+// count 0..m stays inside the row and its padding.
+constexpr int kRowPad = 2;
+constexpr int kDevTableEntries = kTableEntries + kRowPad * kChunk;  // 2208
+__host__ __device__ constexpr uint32_t dev_row_offset(uint32_t m)
+{
+    return ((m - 1u) * (m + 4u)) >> 1;
+}
 // Guide tables for the inverse-CDF search: for row m and bucket b (the top
 // kGuideBits bits of the draw), the number of row entries <= b << (32 - bits).
 // Kernels may stage a coarser view (every 2^k-th bucket) in LDS.
@@ -23,24 +32,26 @@ constexpr int kGuideEntries = kChunk * kGuideBuckets;  // bytes per table
 // rest table (P = (1-theta) 2^32) with their guides, contiguous on the device.
 constexpr int kTablesPerSet = 3;
 constexpr size_t kTableSetBytes =
-    kTablesPerSet * (kTableEntries * sizeof(uint32_t) + kGuideEntries);
+    kTablesPerSet * (kDevTableEntries * sizeof(uint32_t) + kGuideEntries);
 enum TableId : int { kTabP = 0, kTabHalf = 1, kTabRest = 2 };
 
 __host__ __device__ inline const uint32_t *table_ptr(const void *set, int id)
 {
-    return reinterpret_cast<const uint32_t *>(set) + id * kTableEntries;
+    return reinterpret_cast<const uint32_t *>(set) + id * kDevTableEntries;
 }
 __host__ __device__ inline const uint8_t *guide_ptr(const void *set, int id)
 {
     return reinterpret_cast<const uint8_t *>(set) +
-           kTablesPerSet * kTableEntries * sizeof(uint32_t) + id * kGuideEntries;
+           kTablesPerSet * kDevTableEntries * sizeof(uint32_t) + id * kGuideEntries;
 }
 
 // Host: exact fixed-point tables (multiword integer arithmetic) and guides.
 void build_binomial_table(uint64_t p, uint32_t *out);
 void build_guide(const uint32_t *table, uint8_t *guide);
-// Fill a host table set for (p, p_rest); p = 0 leaves the P table zeroed
-// (the kernels never read it then).
+// Packed table (kTableEntries) -> device layout (kDevTableEntries).
+void pad_table(const uint32_t *packed, uint32_t *dev);
+// Fill a host table set (device layout) for (p, p_rest); p = 0 leaves the P
+// table zeroed (the kernels never read it then).
 void build_table_set(uint64_t p, uint64_t p_rest, void *host_set);
 
 struct Fixed {
@@ -119,8 +130,8 @@ constexpr int kBatchGuideBits = 6;
 struct BatchArgs {
     void *arena;
     BatchMeta *meta;
-    const uint32_t *tabs_p;       // [nreal][kTableEntries] removal tables
-    const uint32_t *tabs_shared;  // [2][kTableEntries]: P = 2^31, P = P_rest
+    const uint32_t *tabs_p;       // [nreal][kDevTableEntries] removal tables
+    const uint32_t *tabs_shared;  // [2][kDevTableEntries]: P = 2^31, P = P_rest
     const uint32_t *order;        // members, longest first
     uint32_t *queue;              // next index into order
     uint32_t nreal;
@@ -158,7 +169,7 @@ struct ServeTile {
 constexpr int kServeGuideBits = 8;
 constexpr int kServeTile = 1024;  // nodes per tile (one workgroup pass)
 // Slot table set: removal table, rest table (q = 3), then their guides.
-constexpr size_t kServeTableBytes = kTableEntries * sizeof(uint32_t);
+constexpr size_t kServeTableBytes = kDevTableEntries * sizeof(uint32_t);
 constexpr size_t kServeGuideBytes = (size_t)kChunk << kServeGuideBits;
 inline size_t serve_table_set_bytes(int q)
 {

@@ -20,7 +20,9 @@
 //    table compares; longer scans run only for the lanes that need them;
 //  * one wave-uniform test per node selects straight-line code with constant
 //    draw-word indices when every lane shares the common chunk layout
-//    (node_fast); the generic path picks words by a scalar switch when the
+//    (node_fast); for q = 3 a wave whose middle binomial needs 1, 2 or 3
+//    chunks depending on the lane selects the later words per lane
+//    (node_var3); the generic path picks words by a scalar switch when the
 //    index is wave-uniform and by a select tree otherwise;
 //  * the first NB Philox blocks are computed up front, later ones on demand.
 #pragma once
@@ -79,6 +81,14 @@ __device__ __forceinline__ uint32_t pick4(uint32_t a, uint32_t b, uint32_t c, ui
     return (s & 2u) ? hi : lo;
 }
 
+// c3 ? c : (c2 ? b : a) on values (a conditional over array elements would
+// be an lvalue select, i.e. a dynamically indexed array in scratch memory).
+__device__ __forceinline__ uint32_t pick3(bool c2, bool c3, uint32_t a, uint32_t b, uint32_t c)
+{
+    const uint32_t lo = c2 ? b : a;
+    return c3 ? c : lo;
+}
+
 // Word j of the lane's draw stream (lanes may ask for different j).
 template <int NB>
 __device__ __forceinline__ uint32_t draw_word(const Draws<NB> &d, uint32_t j)
@@ -118,21 +128,21 @@ __device__ __forceinline__ uint32_t draw_word(const Draws<NB> &d, uint32_t j)
 }
 
 // Inverse-CDF count of one chunk of m >= 1 trials: #{j < m : row[j] <= u}.
-// The guide gives the count at the lower edge of u's bucket; rows are
+// The guide gives the count g <= m at the lower edge of u's bucket; rows are
 // nondecreasing, so counting continues from there to the first entry above u.
+// Tables are in the padded device layout: entries g and g + 1 always exist
+// (past the row they are all-ones sentinels), so the two probes need no bound
+// test, and entry g + 1 <= u implies entry g <= u.  A sentinel compares <= u
+// only for u = 2^32 - 1, where the final clamp to m gives the right count.
 template <int GB>
 __device__ __forceinline__ uint32_t chunk_count(const uint32_t *tab, const uint8_t *guide,
                                                 uint32_t m, uint32_t u)
 {
-    const uint32_t *row = tab + (((m - 1u) * m) >> 1);
+    const uint32_t *row = tab + dev_row_offset(m);
     const uint32_t g = guide[((m - 1u) << GB) + (u >> (32 - GB))];
-    // Two compares cover almost every lane: entries g and g+1 (clamped to the
-    // row; a clamped read is masked by the bound test).
-    const uint32_t t0 = row[g < m ? g : m - 1u];
-    const uint32_t t1 = row[g + 1u < m ? g + 1u : m - 1u];
-    const bool s0 = (g < m) && (t0 <= u);
-    const bool s1 = s0 && (g + 1u < m) && (t1 <= u);
-    uint32_t c = g + (s0 ? 1u : 0u) + (s1 ? 1u : 0u);
+    const uint32_t t0 = row[g], t1 = row[g + 1u];
+    const bool s1 = t1 <= u;
+    uint32_t c = g + (t0 <= u ? 1u : 0u) + (s1 ? 1u : 0u);
     if (wave_any(s1)) {
         bool go = s1;
         while (go) {
@@ -140,7 +150,7 @@ __device__ __forceinline__ uint32_t chunk_count(const uint32_t *tab, const uint8
             c += go ? 1u : 0u;
         }
     }
-    return c;
+    return c < m ? c : m;
 }
 
 // Bin(n, table) with the chunked rule, consuming draws from index j on.
@@ -237,6 +247,54 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
     return true;
 }
 
+// q = 3 node update when the outer removal binomials have 1..64 trials but
+// the middle one's chunk count D1 = ceil(a_1 / 64) in {1, 2, 3} differs
+// between lanes: chunks past the first are masked per lane, and the words of
+// the later binomials (draws 1 + D1 .. 3 + D1) are selected per lane.
+// Returns false (nothing written) if the redistribution does not fit one
+// chunk per binomial.
+template <typename W, int NB, int GB>
+__device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Draws<NB> &d,
+                                          const uint32_t *tab_p, const uint8_t *g_p,
+                                          const uint32_t *tab_half, const uint8_t *g_half,
+                                          const uint32_t *tab_rest, const uint8_t *g_rest,
+                                          bool p_zero)
+{
+    static_assert(NB >= 2, "draws 0..6 must be computed up front");
+    const uint32_t a1 = (uint32_t)av[1];
+    const bool c2 = a1 > (uint32_t)kChunk, c3 = a1 > 2u * kChunk;
+    W kv[3];
+    if (p_zero) {
+        kv[0] = kv[1] = kv[2] = 0;
+    } else {
+        kv[0] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[0], d.w[0]);
+        uint32_t k1 = chunk_count<GB>(tab_p, g_p, c2 ? (uint32_t)kChunk : a1, d.w[1]);
+        if (wave_any(c2)) {
+            const uint32_t m2 = c3 ? (uint32_t)kChunk : (c2 ? a1 - kChunk : 0u);
+            k1 += chunk_or_zero<GB>(tab_p, g_p, m2, d.w[2]);
+        }
+        if (wave_any(c3))
+            k1 += chunk_or_zero<GB>(tab_p, g_p, c3 ? a1 - 2u * kChunk : 0u, d.w[3]);
+        kv[1] = (W)k1;
+        const uint32_t u2 = pick3(c2, c3, d.w[2], d.w[3], d.w[4]);
+        kv[2] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[2], u2);
+    }
+    const W M = kv[0] + kv[1] + kv[2];
+    if (wave_any(M > (W)kChunk))
+        return false;
+    const uint32_t um1 = pick3(c2, c3, d.w[3], d.w[4], d.w[5]);
+    const uint32_t um0 = pick3(c2, c3, d.w[4], d.w[5], d.w[6]);
+    W mv[3];
+    mv[1] = chunk_or_zero<GB>(tab_rest, g_rest, (uint32_t)M, um1);
+    const W R = M - mv[1];
+    mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, um0);
+    mv[2] = R - mv[0];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        c[i] = av[i] - kv[i] + mv[i];
+    return true;
+}
+
 template <typename T> struct Wide;
 template <> struct Wide<uint16_t> { using type = uint32_t; };
 template <> struct Wide<uint32_t> { using type = uint64_t; };
@@ -255,22 +313,28 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
     Draws<NB> d;
     d.init(x, t, r, key0, key1);
     // Common draw layout, decided once per wave for this node slot.
-    bool ok = true, two = false;
+    bool ok = true, two = false, three = false;
     if constexpr (Q == 2) {
         ok = av[0] >= 1 && av[0] <= (W)kChunk && av[1] >= 1 && av[1] <= (W)kChunk;
     } else {
         ok = av[0] >= 1 && av[0] <= (W)kChunk && av[2] >= 1 && av[2] <= (W)kChunk &&
-             av[1] >= 1 && av[1] <= (W)(2 * kChunk);
+             av[1] >= 1 && av[1] <= (W)(3 * kChunk);
         two = av[1] > (W)kChunk;
+        three = av[1] > (W)(2 * kChunk);
     }
     bool done = false;
     if (!wave_any(!ok)) {
         if (!wave_any(two))
             done = node_fast<Q, 1, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
                                               g_rest, p_zero);
-        else if (Q == 3 && !wave_any(!two))
-            done = node_fast<Q, 2, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
-                                              g_rest, p_zero);
+        else if constexpr (Q == 3) {
+            if (!wave_any(!two) && !wave_any(three))
+                done = node_fast<Q, 2, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half,
+                                                  tab_rest, g_rest, p_zero);
+            else
+                done = node_var3<W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
+                                            g_rest, p_zero);
+        }
     }
     if (!done) {
         uint32_t j = 0;

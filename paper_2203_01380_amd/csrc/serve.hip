@@ -27,14 +27,14 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     constexpr int GB = kServeGuideBits;
     constexpr int kTabs = (Q == 3) ? 3 : 2;
     constexpr int kG = kChunk << GB;
-    __shared__ uint32_t s_tab[kTabs * kTableEntries];
+    __shared__ __align__(16) uint32_t s_tab[kTabs * kDevTableEntries];
     __shared__ uint8_t s_guide[kTabs * kG];
 
     // shared half table (slot 1 in LDS) and its guide
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.shared);
-        uint4 *dst = reinterpret_cast<uint4 *>(s_tab + kTableEntries);
-        for (int i = threadIdx.x; i < kTableEntries / 4; i += kBlock)
+        uint4 *dst = reinterpret_cast<uint4 *>(s_tab + kDevTableEntries);
+        for (int i = threadIdx.x; i < kDevTableEntries / 4; i += kBlock)
             dst[i] = src[i];
         const uint4 *gsrc = reinterpret_cast<const uint4 *>(
             reinterpret_cast<const uint8_t *>(a.shared) + kServeTableBytes);
@@ -42,8 +42,8 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         for (int i = threadIdx.x; i < kG / 16; i += kBlock)
             gdst[i] = gsrc[i];
     }
-    const uint32_t *tab_p = s_tab, *tab_half = s_tab + kTableEntries;
-    const uint32_t *tab_rest = s_tab + 2 * kTableEntries;
+    const uint32_t *tab_p = s_tab, *tab_half = s_tab + kDevTableEntries;
+    const uint32_t *tab_rest = s_tab + 2 * kDevTableEntries;
     const uint8_t *g_p = s_guide, *g_half = s_guide + kG, *g_rest = s_guide + 2 * kG;
     constexpr W kMax = (W)(T)~(T)0;
     bool overflow = false;
@@ -67,8 +67,8 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
             const int nt = (Q == 3) ? 2 : 1;  // removal (+ rest) tables
             for (int t = 0; t < nt; ++t) {
                 const uint4 *src = reinterpret_cast<const uint4 *>(set + t * kServeTableBytes);
-                uint4 *dst = reinterpret_cast<uint4 *>(s_tab + (t == 0 ? 0 : 2) * kTableEntries);
-                for (int i = threadIdx.x; i < kTableEntries / 4; i += kBlock)
+                uint4 *dst = reinterpret_cast<uint4 *>(s_tab + (t == 0 ? 0 : 2) * kDevTableEntries);
+                for (int i = threadIdx.x; i < kDevTableEntries / 4; i += kBlock)
                     dst[i] = src[i];
                 const uint4 *gsrc = reinterpret_cast<const uint4 *>(
                     set + nt * kServeTableBytes + t * kServeGuideBytes);

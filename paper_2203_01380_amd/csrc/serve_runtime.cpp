@@ -108,12 +108,14 @@ public:
         const int nt = c.q == 3 ? 2 : 1;
         std::vector<unsigned char> set(ilg::serve_table_set_bytes((int)c.q), 0);
         const uint64_t ps[2] = {p->fx.p, p->fx.p_rest};
+        std::vector<uint32_t> packed(ilg::kTableEntries);
         for (int t = 0; t < nt; ++t) {
             uint32_t *tab = reinterpret_cast<uint32_t *>(set.data() + t * ilg::kServeTableBytes);
             if (ps[t] == 0)
                 continue;
-            ilg::build_binomial_table(ps[t], tab);
-            guide(tab, set.data() + nt * ilg::kServeTableBytes + t * ilg::kServeGuideBytes);
+            ilg::build_binomial_table(ps[t], packed.data());
+            guide(packed.data(), set.data() + nt * ilg::kServeTableBytes + t * ilg::kServeGuideBytes);
+            ilg::pad_table(packed.data(), tab);
         }
         SHIP(hipMemcpyAsync(base + state_bytes(c), set.data(), set.size(), hipMemcpyHostToDevice,
                             io));
@@ -315,9 +317,10 @@ int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server 
         e = hipStreamCreateWithFlags(&ex.io, hipStreamNonBlocking);
     if (e == hipSuccess) {
         std::vector<unsigned char> sh(ilg::kServeTableBytes + ilg::kServeGuideBytes, 0);
-        uint32_t *tab = reinterpret_cast<uint32_t *>(sh.data());
-        ilg::build_binomial_table(uint64_t(1) << 31, tab);
-        DeviceExecutor::guide(tab, sh.data() + ilg::kServeTableBytes);
+        std::vector<uint32_t> packed(ilg::kTableEntries);
+        ilg::build_binomial_table(uint64_t(1) << 31, packed.data());
+        DeviceExecutor::guide(packed.data(), sh.data() + ilg::kServeTableBytes);
+        ilg::pad_table(packed.data(), reinterpret_cast<uint32_t *>(sh.data()));
         e = hipMemcpy(ex.shared, sh.data(), sh.size(), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess)

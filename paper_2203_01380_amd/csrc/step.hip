@@ -32,14 +32,14 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     using W = typename Wide<T>::type;
     constexpr int kTabs = (Q == 3) ? 3 : 2;
     constexpr int kRowGuide = 1 << GB;
-    __shared__ uint32_t s_tab[kTabs * kTableEntries];
+    __shared__ __align__(16) uint32_t s_tab[kTabs * kDevTableEntries];
     __shared__ uint8_t s_guide[kTabs * kChunk * kRowGuide];
 
     // Stage tables (16-byte copies) and the 2^GB-bucket view of the guides.
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.tables);
         uint4 *dst = reinterpret_cast<uint4 *>(s_tab);
-        constexpr int n = kTabs * kTableEntries * 4 / 16;
+        constexpr int n = kTabs * kDevTableEntries * 4 / 16;
         for (int i = threadIdx.x; i < n; i += BLOCK)
             dst[i] = src[i];
         const uint8_t *gsrc = guide_ptr(a.tables, 0);
@@ -58,8 +58,8 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     __syncthreads();
 
     const uint32_t *tab_p = s_tab;
-    const uint32_t *tab_half = s_tab + kTableEntries;
-    const uint32_t *tab_rest = s_tab + 2 * kTableEntries;  // q = 3 only
+    const uint32_t *tab_half = s_tab + kDevTableEntries;
+    const uint32_t *tab_rest = s_tab + 2 * kDevTableEntries;  // q = 3 only
     constexpr int kG = kChunk * kRowGuide;
     const uint8_t *g_p = s_guide;
     const uint8_t *g_half = s_guide + kG;

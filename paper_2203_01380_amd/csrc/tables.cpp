@@ -87,18 +87,32 @@ void build_guide(const uint32_t *table, uint8_t *guide)
     }
 }
 
+void pad_table(const uint32_t *packed, uint32_t *dev)
+{
+    for (uint32_t m = 1; m <= (uint32_t)kChunk; ++m) {
+        const uint32_t *src = packed + (m - 1) * m / 2;
+        uint32_t *dst = dev + dev_row_offset(m);
+        for (uint32_t j = 0; j < m; ++j)
+            dst[j] = src[j];
+        for (int k = 0; k < kRowPad; ++k)
+            dst[m + k] = 0xFFFFFFFFu;
+    }
+}
+
 void build_table_set(uint64_t p, uint64_t p_rest, void *host_set)
 {
     std::memset(host_set, 0, kTableSetBytes);
     uint32_t *tabs = reinterpret_cast<uint32_t *>(host_set);
     uint8_t *guides = reinterpret_cast<uint8_t *>(host_set) +
-                      kTablesPerSet * kTableEntries * sizeof(uint32_t);
+                      kTablesPerSet * kDevTableEntries * sizeof(uint32_t);
     const uint64_t ps[kTablesPerSet] = {p, uint64_t(1) << 31, p_rest};
+    std::vector<uint32_t> packed(kTableEntries);
     for (int id = 0; id < kTablesPerSet; ++id) {
         if (ps[id] == 0)
             continue;
-        build_binomial_table(ps[id], tabs + id * kTableEntries);
-        build_guide(tabs + id * kTableEntries, guides + id * kGuideEntries);
+        build_binomial_table(ps[id], packed.data());
+        build_guide(packed.data(), guides + id * kGuideEntries);
+        pad_table(packed.data(), tabs + id * kDevTableEntries);
     }
 }
 

@@ -112,6 +112,41 @@ def test_multi_chunk_counts(ilg, oracle_lib, q):
     _run_both(ilg, oracle_lib, q, 3000, 2, 1.3, init, steps=8, seed=11, check_every=2)
 
 
+@pytest.mark.parametrize("cb,omega", [(2, 1.8), (4, 1.3), (2, 2.0), (4, 0.7)])
+def test_mixed_middle_chunk_layouts(ilg, oracle_lib, cb, omega):
+    """D1Q3 wavefronts whose middle removal binomial needs one, two or three
+    chunks depending on the lane (rest counts around 64, 128 and 192, with the
+    edges 64/65, 128/129, 192/193), outer counts 1..40: each block of 64
+    nodes gets one layout mix (uniform, two/three chunks, one/two/three, one/two,
+    edge values, beyond three chunks).  Rest particles do not stream, so the
+    mixes persist over the compared steps."""
+    rng = np.random.default_rng(31 + cb)
+    nblk = 60
+    L = 64 * nblk + 17
+    dt = np.uint16 if cb == 2 else np.uint32
+    init = np.empty((3, L), dtype=dt)
+    init[0] = rng.integers(1, 41, L)
+    init[2] = rng.integers(1, 41, L)
+    mids = []
+    for b in range(nblk + 1):
+        mode = b % 6
+        if mode == 0:
+            v = rng.integers(65, 129, 64)
+        elif mode == 1:
+            v = rng.integers(65, 193, 64)
+        elif mode == 2:
+            v = rng.integers(1, 193, 64)
+        elif mode == 3:
+            v = rng.integers(1, 129, 64)
+        elif mode == 4:
+            v = rng.choice([1, 63, 64, 65, 127, 128, 129, 191, 192], 64)
+        else:
+            v = rng.integers(100, 260, 64)
+        mids.append(v)
+    init[1] = np.concatenate(mids)[:L]
+    _run_both(ilg, oracle_lib, 3, L, cb, omega, init, steps=6, seed=13)
+
+
 @pytest.mark.parametrize("q,omega,flip", [(3, 2.0, "auto"), (2, 2.0, "auto"), (3, 1.0, "on"),
                                           (3, 1.0, "off"), (2, 0.5, "auto"), (3, 0.3, "auto"),
                                           (3, 1.999, "auto"), (2, 0.01, "auto")])
