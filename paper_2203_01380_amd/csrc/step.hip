@@ -5,12 +5,12 @@
 //
 // Mapping: a persistent grid of 1024-thread workgroups (two per CU), each
 // holding the fixed-point tables and their guides in LDS, staged once.  A
-// tile is BLOCK * NPT consecutive nodes; every thread owns NPT consecutive
-// nodes and reads each velocity row with one vector load.  Tiles are dealt
-// so that the workgroups of one XCD (dispatch is round-robin over the 8
-// XCDs) cover one contiguous eighth of the lattice.  Streaming stores are per
-// element (the +-1 shift breaks vector alignment); the wave still writes
-// contiguous bytes.
+// tile is BLOCK consecutive nodes, one per thread, so every wave reads and
+// writes contiguous bytes of each velocity row.  Tiles are dealt so that the
+// workgroups of one XCD (dispatch is round-robin over the 8 XCDs) cover one
+// contiguous eighth of the lattice.  (Two or four nodes per thread, with
+// vector loads, measured slower: the extra registers cost more than the
+// wider accesses gain in this VALU-bound kernel.)
 #include <cstdlib>
 #include <type_traits>
 
@@ -22,11 +22,9 @@ namespace ilg {
 namespace {
 
 constexpr int kNumXcd = 8;
-using sampler::VecT;
-using sampler::static_for;
 using sampler::Wide;
 
-template <int Q, typename T, int NPT, int NB, int GB, int BLOCK>
+template <int Q, typename T, int NB, int GB, int BLOCK, bool FLIP>
 __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 {
     using W = typename Wide<T>::type;
@@ -65,14 +63,13 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     const uint8_t *g_half = s_guide + kG;
     const uint8_t *g_rest = s_guide + 2 * kG;
     const bool p_zero = a.p_zero != 0;
-    const bool flip = a.flip != 0;
     const uint32_t L = a.length;
     const uint64_t pitch = a.pitch;
     const T *in = reinterpret_cast<const T *>(a.in);
     T *out = reinterpret_cast<T *>(a.out);
     constexpr W kMax = (W)(T)~(T)0;
 
-    constexpr uint32_t kTile = (uint32_t)BLOCK * NPT;
+    constexpr uint32_t kTile = (uint32_t)BLOCK;
     const uint32_t ntiles = (L + kTile - 1) / kTile;
     uint32_t first, stride, end;
     if (gridDim.x % kNumXcd == 0) {
@@ -88,78 +85,41 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 
     bool overflow = false;
     for (uint32_t tile = first; tile < end; tile += stride) {
-        const uint32_t x0 = tile * kTile + threadIdx.x * NPT;
-        if (x0 >= L)
+        const uint32_t x = tile * kTile + threadIdx.x;
+        if (x >= L)
             continue;
-        W n[Q][NPT];
-        if (x0 + NPT <= L) {
+        W n[Q], av[Q], cn[Q];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const VecT<T, NPT> v =
-                    *reinterpret_cast<const VecT<T, NPT> *>(in + i * pitch + x0);
+        for (int i = 0; i < Q; ++i)
+            n[i] = (W)in[i * pitch + x];
 #pragma unroll
-                for (int k = 0; k < NPT; ++k)
-                    n[i][k] = (W)v.v[k];
-            }
-        } else {
+        for (int i = 0; i < Q; ++i)
+            av[i] = FLIP ? n[Q - 1 - i] : n[i];
+        sampler::node_update<Q, W, NB, GB>(av, cn, x, a.t, a.realization, a.key0, a.key1, tab_p,
+                                           g_p, tab_half, g_half, tab_rest, g_rest, p_zero);
+        // a count above the type's maximum has a bit above it set, so the OR
+        // of the counts exceeds the maximum iff one of them does
+        W any = cn[0];
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-#pragma unroll
-                for (int k = 0; k < NPT; ++k)
-                    n[i][k] = (x0 + k < L) ? (W)in[i * pitch + x0 + k] : (W)0;
-        }
-
-        W c[Q][NPT];
-        static_for<0, NPT>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            W av[Q], cn[Q];
-#pragma unroll
-            for (int i = 0; i < Q; ++i)
-                av[i] = flip ? n[Q - 1 - i][k] : n[i][k];
-            sampler::node_update<Q, W, NB, GB>(av, cn, x0 + k, a.t, a.realization, a.key0,
-                                               a.key1, tab_p, g_p, tab_half, g_half, tab_rest,
-                                               g_rest, p_zero);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                c[i][k] = cn[i];
-                overflow |= cn[i] > kMax;
-            }
-        });
-
+        for (int i = 1; i < Q; ++i)
+            any |= cn[i];
+        overflow |= any > kMax;
         // Streaming: velocity -1 to x-1, 0 in place, +1 to x+1 (periodic).
-#pragma unroll
-        for (int k = 0; k < NPT; ++k) {
-            const uint32_t x = x0 + k;
-            if (x < L) {
-                const uint32_t xm = (x == 0) ? L - 1 : x - 1;
-                const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-                out[xm] = (T)c[0][k];
-                out[(uint64_t)(Q - 1) * pitch + xp] = (T)c[Q - 1][k];
-            }
-        }
-        if constexpr (Q == 3) {
-            if (x0 + NPT <= L) {
-                VecT<T, NPT> v;
-#pragma unroll
-                for (int k = 0; k < NPT; ++k)
-                    v.v[k] = (T)c[1][k];
-                *reinterpret_cast<VecT<T, NPT> *>(out + pitch + x0) = v;
-            } else {
-#pragma unroll
-                for (int k = 0; k < NPT; ++k)
-                    if (x0 + k < L)
-                        out[pitch + x0 + k] = (T)c[1][k];
-            }
-        }
+        const uint32_t xm = (x == 0) ? L - 1 : x - 1;
+        const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+        out[xm] = (T)cn[0];
+        out[(uint64_t)(Q - 1) * pitch + xp] = (T)cn[Q - 1];
+        if constexpr (Q == 3)
+            out[pitch + x] = (T)cn[1];
     }
     if (overflow)
         atomicOr(a.err, 1u);
 }
 
-template <int Q, typename T, int NPT, int NB, int GB, int BLOCK>
+template <int Q, typename T, int NB, int GB, int BLOCK>
 hipError_t launch_variant(const StepArgs &a, hipStream_t stream, int wg_per_cu)
 {
-    constexpr uint32_t kTile = (uint32_t)BLOCK * NPT;
+    constexpr uint32_t kTile = (uint32_t)BLOCK;
     const uint32_t ntiles = (a.length + kTile - 1) / kTile;
     static int cus = 0;
     if (cus == 0)
@@ -171,8 +131,12 @@ hipError_t launch_variant(const StepArgs &a, hipStream_t stream, int wg_per_cu)
         grid -= grid % kNumXcd;
     if (grid == 0)
         grid = 1;
-    hipLaunchKernelGGL((step_kernel<Q, T, NPT, NB, GB, BLOCK>), dim3(grid), dim3(BLOCK), 0, stream,
-                       a);
+    if (a.flip)
+        hipLaunchKernelGGL((step_kernel<Q, T, NB, GB, BLOCK, true>), dim3(grid), dim3(BLOCK), 0,
+                           stream, a);
+    else
+        hipLaunchKernelGGL((step_kernel<Q, T, NB, GB, BLOCK, false>), dim3(grid), dim3(BLOCK), 0,
+                           stream, a);
     return hipGetLastError();
 }
 
@@ -193,15 +157,11 @@ hipError_t launch_q(const StepArgs &a, hipStream_t stream)
 {
     switch (step_variant()) {
     case 1:
-        return launch_variant<Q, T, 2, NB, 8, 1024>(a, stream, 2);
+        return launch_variant<Q, T, NB, 7, 1024>(a, stream, 2);
     case 2:
-        return launch_variant<Q, T, 4, NB, 8, 1024>(a, stream, 2);
-    case 3:
-        return launch_variant<Q, T, 1, NB, 7, 1024>(a, stream, 2);
-    case 4:
-        return launch_variant<Q, T, 1, NB, 8, 512>(a, stream, 4);
+        return launch_variant<Q, T, NB, 8, 512>(a, stream, 4);
     default:
-        return launch_variant<Q, T, 1, NB, 8, 1024>(a, stream, 2);
+        return launch_variant<Q, T, NB, 8, 1024>(a, stream, 2);
     }
 }
 
