@@ -39,7 +39,11 @@ INT_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # population a_0 ~ 100) -> 2 Philox4x32-10 blocks of 10 rounds x (2 full
 # 32x32 multiplies + 4 xors) = 120 ops, plus one table compare per draw.
 ALG_INT_OPS_PER_NODE = 2 * 10 * 6 + 6
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_d1q3_u16_l2p24.json")
+def traffic_file(length: int) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_step_d1q3_u16_l2p{length.bit_length() - 1}.json")
+
+
+MALL_FREE_LENGTH = 1 << 26   # 768 MiB of double-buffered state, beyond the 256 MB MALL
 STEP_SOURCES = [os.path.join(ROOT, "paper_2203_01380_amd", "csrc", f)
                 for f in ("step.hip", "sampler.h")]
 
@@ -52,11 +56,12 @@ def step_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic():
+def counter_traffic(length: int):
     """HBM bytes per launch of the step kernel from the committed counter
-    summary, or None if absent or taken on a different version of the kernel."""
+    summary for this lattice length, or None if absent or taken on a different
+    version of the kernel."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(length)) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
@@ -100,6 +105,22 @@ def cpu_baseline(init, spec, seconds: float):
             "kind": "oracle",
             "sample": f"{steps} full steps of the same D1Q3 L={spec.length} lattice "
                       f"({spec.length * steps} node-updates, {el:.1f} s)"}
+
+
+def bench_plain_mall_free(ilg, W, stream, warmup: int, steps: int = 500):
+    """The headline kernel on a lattice whose double-buffered state (768 MiB)
+    does not fit the 256 MB MALL, so every step really streams from HBM."""
+    spec, init = W.workload_d1q3_big(length=MALL_FREE_LENGTH, steps=steps)
+    lat = ilg.Lattice(spec.q, spec.length, spec.count_bytes, spec.omega, spec.seed, init)
+    lat.step(warmup)
+    sec = timed(stream, lambda: lat.step(steps))
+    lat.close()
+    ms = sec * 1e3 / steps
+    alg_bytes = 2 * spec.q * spec.count_bytes * spec.length
+    return {"workload": "same step, D1Q3 L=2^26 periodic, uint16, Poisson(50), omega=1.8",
+            "steps": steps, "ms_per_step": ms, "node_updates_per_s": spec.length / (ms / 1e3),
+            "alg_gbs": alg_bytes / (ms / 1e3) / 1e9,
+            "traffic": counter_traffic(spec.length)}
 
 
 def bench_batched_ragged(ilg, W, stream, steps: int, loop_members: int):
@@ -204,7 +225,7 @@ def bench_serving(ilg, W, rate: float, duration: float, budget: int, quantum: in
             "peak_bytes": int(peak), "budget_bytes": budget, "quantum_steps": quantum}
 
 
-def summarize_counters(fetch_csv: str, write_csv: str, out_path: str):
+def summarize_counters(fetch_csv: str, write_csv: str, length: int):
     """Turn two rocprofv3 --pmc runs of `bench.py --forms plain --copy-probe`
     (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) into HBM bytes per step
     launch.  Each counter is scaled by what it reads for the probe copy of
@@ -229,8 +250,8 @@ def summarize_counters(fetch_csv: str, write_csv: str, out_path: str):
            "fetch_bytes_per_launch": f_step * f_scale * 1024,
            "write_bytes_per_launch": w_step * w_scale * 1024,
            "bytes_per_launch": (f_step * f_scale + w_step * w_scale) * 1024,
-           "alg_bytes_per_launch": 12 * (1 << 24)}
-    with open(out_path, "w") as f:
+           "length": length, "alg_bytes_per_launch": 12 * length}
+    with open(traffic_file(length), "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
 
@@ -243,8 +264,8 @@ def main():
     ap.add_argument("--length", type=int, default=1 << 24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,batched,decay,serving",
-                    help="comma list of plain (always), batched, decay, serving")
+    ap.add_argument("--forms", default="plain,mallfree,batched,decay,serving",
+                    help="comma list of plain (always), mallfree, batched, decay, serving")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
@@ -258,7 +279,7 @@ def main():
                     help="write the counter traffic record from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters, TRAFFIC_FILE)
+        summarize_counters(*args.summarize_counters, args.length)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -308,17 +329,21 @@ def main():
         "vs_baseline": None,
         "dtype": "u16",
         "data": "synthetic",
-        "config": {"workload": "1D diffusive ILG with flip, D1Q3, L=2^24 periodic, uint16 counts, "
-                               "Poisson(50) per velocity, omega=1.8, Philox seed 1",
+        "config": {"workload": f"1D diffusive ILG with flip, D1Q3, L=2^{spec.length.bit_length() - 1} "
+                               "periodic, uint16 counts, Poisson(50) per velocity, omega=1.8, "
+                               "Philox seed 1",
                    "q": spec.q, "length": spec.length, "count_bytes": spec.count_bytes,
                    "omega": spec.omega, "form": "plain"},
         "roofline": {"bound": "alu", "achieved": tops, "peak": INT_VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": tops / INT_VALU_PEAK_TOPS,
-                     "traffic": counter_traffic(),
+                     "traffic": counter_traffic(spec.length),
                      "alg_ops_per_node_update": ALG_INT_OPS_PER_NODE},
         "hbm_roofline": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbs / HBM_PEAK_GBS, "alg_bytes_per_node_update": 12},
     }
+    if "mallfree" in forms and spec.length != MALL_FREE_LENGTH:
+        say("plain step at 2^26 nodes")
+        out["plain_l2p26"] = bench_plain_mall_free(ilg, W, stream, args.warmup)
     if "batched" in forms:
         say("batched ragged ensemble")
         out["batched"] = bench_batched_ragged(ilg, W, stream, args.batched_steps,

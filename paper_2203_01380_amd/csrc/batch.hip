@@ -160,8 +160,11 @@ void batch_kernel(BatchArgs a)
     constexpr int kRowGuide = 1 << GB;
     constexpr int kG = kChunk * kRowGuide;
     constexpr int kWaves = BLOCK / 64;
-    __shared__ __align__(16) uint32_t s_tab[kTabs * kDevTableEntries];
-    __shared__ uint8_t s_guide[kTabs * kG];
+    // tables first, then guides (nonzero guide addresses fold into offsets)
+    constexpr int kTabBytes = kTabs * kDevTableEntries * (int)sizeof(uint32_t);
+    __shared__ __align__(16) uint8_t s_lds[kTabBytes + kTabs * kG];
+    uint32_t *s_tab = reinterpret_cast<uint32_t *>(s_lds);
+    uint8_t *s_guide = s_lds + kTabBytes;
     __shared__ uint32_t s_next;
     __shared__ double s_red[kWaves];
     __shared__ unsigned long long s_redu[kWaves];
@@ -217,9 +220,7 @@ void batch_kernel(BatchArgs a)
                 sampler::node_update<Q, W, NB, GB>(av, cn, x, t, m.realization, m.key0, m.key1,
                                                    tab_p, g_p, tab_half, g_half, tab_rest, g_rest,
                                                    p_zero);
-#pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    overflow |= cn[i] > kMax;
+                overflow |= sampler::any_above<Q, W>(cn, kMax);
                 const uint32_t xm = (x == 0) ? L - 1 : x - 1;
                 const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
                 out[xm] = (T)cn[0];

@@ -295,6 +295,18 @@ __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Dra
     return true;
 }
 
+// Whether some count exceeds kMax = 2^b - 1: exactly then the OR of the
+// counts has a bit above kMax set.
+template <int Q, typename W>
+__device__ __forceinline__ bool any_above(const W (&c)[Q], W kMax)
+{
+    W any = c[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+        any |= c[i];
+    return any > kMax;
+}
+
 template <typename T> struct Wide;
 template <> struct Wide<uint16_t> { using type = uint32_t; };
 template <> struct Wide<uint32_t> { using type = uint64_t; };

@@ -27,8 +27,11 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     constexpr int GB = kServeGuideBits;
     constexpr int kTabs = (Q == 3) ? 3 : 2;
     constexpr int kG = kChunk << GB;
-    __shared__ __align__(16) uint32_t s_tab[kTabs * kDevTableEntries];
-    __shared__ uint8_t s_guide[kTabs * kG];
+    // tables first, then guides (nonzero guide addresses fold into offsets)
+    constexpr int kTabBytes = kTabs * kDevTableEntries * (int)sizeof(uint32_t);
+    __shared__ __align__(16) uint8_t s_lds[kTabBytes + kTabs * kG];
+    uint32_t *s_tab = reinterpret_cast<uint32_t *>(s_lds);
+    uint8_t *s_guide = s_lds + kTabBytes;
 
     // shared half table (slot 1 in LDS) and its guide
     {
@@ -94,9 +97,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         sampler::node_update<Q, W, NB, GB>(av, cn, x, sl.t0 + a.j, sl.realization, sl.key0,
                                            sl.key1, tab_p, g_p, tab_half, g_half, tab_rest,
                                            g_rest, sl.p_zero != 0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            overflow |= cn[i] > kMax;
+        overflow |= sampler::any_above<Q, W>(cn, kMax);
         const uint32_t xm = (x == 0) ? L - 1 : x - 1;
         const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
         out[xm] = (T)cn[0];

@@ -30,8 +30,13 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     using W = typename Wide<T>::type;
     constexpr int kTabs = (Q == 3) ? 3 : 2;
     constexpr int kRowGuide = 1 << GB;
-    __shared__ __align__(16) uint32_t s_tab[kTabs * kDevTableEntries];
-    __shared__ uint8_t s_guide[kTabs * kChunk * kRowGuide];
+    // Tables first, guides after them: every guide then sits at a nonzero
+    // LDS address, which lets the row-and-bucket index fold into the
+    // instruction's offset field.
+    constexpr int kTabBytes = kTabs * kDevTableEntries * (int)sizeof(uint32_t);
+    __shared__ __align__(16) uint8_t s_lds[kTabBytes + kTabs * kChunk * kRowGuide];
+    uint32_t *s_tab = reinterpret_cast<uint32_t *>(s_lds);
+    uint8_t *s_guide = s_lds + kTabBytes;
 
     // Stage tables (16-byte copies) and the 2^GB-bucket view of the guides.
     {
@@ -97,13 +102,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
             av[i] = FLIP ? n[Q - 1 - i] : n[i];
         sampler::node_update<Q, W, NB, GB>(av, cn, x, a.t, a.realization, a.key0, a.key1, tab_p,
                                            g_p, tab_half, g_half, tab_rest, g_rest, p_zero);
-        // a count above the type's maximum has a bit above it set, so the OR
-        // of the counts exceeds the maximum iff one of them does
-        W any = cn[0];
-#pragma unroll
-        for (int i = 1; i < Q; ++i)
-            any |= cn[i];
-        overflow |= any > kMax;
+        overflow |= sampler::any_above<Q, W>(cn, kMax);
         // Streaming: velocity -1 to x-1, 0 in place, +1 to x+1 (periodic).
         const uint32_t xm = (x == 0) ? L - 1 : x - 1;
         const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
