@@ -180,7 +180,7 @@ void batch_kernel(BatchArgs a)
     const uint32_t *tab_rest = s_tab + 2 * kDevTableEntries;
     const uint8_t *g_p = s_guide, *g_half = s_guide + kG, *g_rest = s_guide + 2 * kG;
     constexpr W kMax = (W)(T)~(T)0;
-    bool overflow = false;
+    W ovf = 0;
 
     for (;;) {
         __syncthreads();
@@ -220,7 +220,7 @@ void batch_kernel(BatchArgs a)
                 sampler::node_update<Q, W, NB, GB>(av, cn, x, t, m.realization, m.key0, m.key1,
                                                    tab_p, g_p, tab_half, g_half, tab_rest, g_rest,
                                                    p_zero);
-                overflow |= sampler::any_above<Q, W>(cn, kMax);
+                ovf |= sampler::or_all<Q, W>(cn);
                 const uint32_t xm = (x == 0) ? L - 1 : x - 1;
                 const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
                 out[xm] = (T)cn[0];
@@ -262,7 +262,7 @@ void batch_kernel(BatchArgs a)
             a.meta[r].cur = cur;
         }
     }
-    if (overflow)
+    if (ovf > kMax)
         atomicOr(a.err, 1u);
 }
 

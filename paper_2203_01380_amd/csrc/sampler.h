@@ -191,12 +191,58 @@ __device__ __forceinline__ uint32_t chunk_or_zero(const uint32_t *tab, const uin
     return m != 0 ? c : 0u;
 }
 
+// Bin(n, table) for 0 <= n <= 64 K with the chunked rule when the words of
+// the chunks are known: chunk k (64 trials, the last one n - 64 k) uses u[k];
+// chunks past ceil(n / 64) add nothing, and chunks no lane of the wave needs
+// are skipped.
+template <int K, int GB>
+__device__ __forceinline__ uint32_t chunks_upto(const uint32_t *tab, const uint8_t *guide,
+                                                uint32_t n, const uint32_t (&u)[K])
+{
+    uint32_t total = chunk_or_zero<GB>(tab, guide, n < (uint32_t)kChunk ? n : kChunk, u[0]);
+    static_for<1, K>([&](auto kc) {
+        constexpr uint32_t k = decltype(kc)::value;
+        const bool need = n > k * kChunk;
+        if (wave_any(need)) {
+            const uint32_t rest = n - k * kChunk;
+            total += chunk_or_zero<GB>(tab, guide,
+                                       need ? (rest < (uint32_t)kChunk ? rest : kChunk) : 0u, u[k]);
+        }
+    });
+    return total;
+}
+
+// q = 3 redistribution for M <= 192 given the four draw words from the first
+// redistribution draw on: m_1 = Bin(M, P_rest) over ceil(M / 64) chunks
+// (words u[0..2]), then m_0 = Bin(R, 1/2), R = M - m_1, one chunk at the next
+// word u[ceil(M / 64)] (for M = 0 neither consumes a word).  Returns false
+// (nothing written) if some lane has R > 64.
+template <typename W, int GB>
+__device__ __forceinline__ bool redistribute3(W M, const uint32_t (&u)[4], W (&mv)[3],
+                                              const uint32_t *tab_half, const uint8_t *g_half,
+                                              const uint32_t *tab_rest, const uint8_t *g_rest)
+{
+    const uint32_t m = (uint32_t)M;
+    const uint32_t um1[3] = {u[0], u[1], u[2]};
+    const W m1 = (W)chunks_upto<3, GB>(tab_rest, g_rest, m, um1);
+    const W R = M - m1;
+    if (wave_any(R > (W)kChunk))
+        return false;
+    const uint32_t um0 = pick3(m > (uint32_t)kChunk, m > 2u * kChunk, u[1], u[2], u[3]);
+    mv[1] = m1;
+    mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, um0);
+    mv[2] = R - mv[0];
+    return true;
+}
+
 // Node update when the whole wave shares the common draw layout: every
 // removal binomial has 1..64 trials except the middle one (q = 3), which has
 // D1 chunks (1..64 or 65..128 trials).  Draw j then belongs to a fixed
-// binomial, so every word index is a compile-time constant.  Returns false
-// (nothing written) if the redistribution does not fit one chunk per
-// binomial; the caller then takes the generic path from scratch.
+// binomial, so every word index is a compile-time constant.  The
+// redistribution may take up to two (q = 2) or three (q = 3, m_1) chunks, the
+// extra chunks masked per lane.  Returns false (nothing written) if the
+// redistribution needs more, or m_0 of q = 3 more than one chunk; the caller
+// then takes the generic path from scratch.
 template <int Q, int D1, typename W, int NB, int GB>
 __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Draws<NB> &d,
                                           const uint32_t *tab_p, const uint8_t *g_p,
@@ -226,20 +272,35 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         M += kv[i];
-    if (wave_any(M > (W)kChunk))
-        return false;
     constexpr int kFirst = (Q == 2) ? 2 : 2 + D1;  // first redistribution draw
     W mv[Q];
-    if constexpr (Q == 2) {
-        mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)M, d.w[kFirst]);
+    if (!wave_any(M > (W)kChunk)) {
+        // the common case: every redistribution binomial takes one chunk
+        if constexpr (Q == 2) {
+            mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)M, d.w[kFirst]);
+            mv[1] = M - mv[0];
+        } else {
+            // m_0 uses the next word only if m_1 consumed one (M > 0); if M = 0
+            // then R = 0 and m_0 consumes nothing, so the word is irrelevant.
+            mv[1] = chunk_or_zero<GB>(tab_rest, g_rest, (uint32_t)M, d.w[kFirst]);
+            const W R = M - mv[1];
+            mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, d.w[kFirst + 1]);
+            mv[2] = R - mv[0];
+        }
+    } else if constexpr (Q == 2) {
+        // M <= 128: m_0 over one or two chunks, words 2 and 3
+        if (wave_any(M > (W)(2 * kChunk)))
+            return false;
+        const uint32_t u[2] = {d.w[2], d.w[3]};
+        mv[0] = (W)chunks_upto<2, GB>(tab_half, g_half, (uint32_t)M, u);
         mv[1] = M - mv[0];
     } else {
-        // m_0 uses the next word only if m_1 consumed one (M > 0); if M = 0
-        // then R = 0 and m_0 consumes nothing, so the word is irrelevant.
-        mv[1] = chunk_or_zero<GB>(tab_rest, g_rest, (uint32_t)M, d.w[kFirst]);
-        const W R = M - mv[1];
-        mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, d.w[kFirst + 1]);
-        mv[2] = R - mv[0];
+        // M <= 192: words kFirst .. kFirst + 3 (at most 7 for D1 <= 2)
+        if (wave_any(M > (W)(3 * kChunk)))
+            return false;
+        const uint32_t u[4] = {d.w[kFirst], d.w[kFirst + 1], d.w[kFirst + 2], d.w[kFirst + 3]};
+        if (!redistribute3<W, GB>(M, u, mv, tab_half, g_half, tab_rest, g_rest))
+            return false;
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i)
@@ -250,9 +311,9 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
 // q = 3 node update when the outer removal binomials have 1..64 trials but
 // the middle one's chunk count D1 = ceil(a_1 / 64) in {1, 2, 3} differs
 // between lanes: chunks past the first are masked per lane, and the words of
-// the later binomials (draws 1 + D1 .. 3 + D1) are selected per lane.
-// Returns false (nothing written) if the redistribution does not fit one
-// chunk per binomial.
+// the later binomials (draws 1 + D1 on) are selected per lane.  The
+// redistribution is as in node_fast.  Returns false (nothing written) where
+// node_fast would, or if a needed word lies beyond the eight computed.
 template <typename W, int NB, int GB>
 __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Draws<NB> &d,
                                           const uint32_t *tab_p, const uint8_t *g_p,
@@ -280,31 +341,36 @@ __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Dra
         kv[2] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[2], u2);
     }
     const W M = kv[0] + kv[1] + kv[2];
-    if (wave_any(M > (W)kChunk))
+    // Redistribution words start at 2 + D1; the fourth of them would be draw
+    // 8 (a third Philox block) when D1 = 3 and M > 128: left to the generic path.
+    if (wave_any(M > (W)(3 * kChunk) || (c3 && M > (W)(2 * kChunk))))
         return false;
-    const uint32_t um1 = pick3(c2, c3, d.w[3], d.w[4], d.w[5]);
-    const uint32_t um0 = pick3(c2, c3, d.w[4], d.w[5], d.w[6]);
+    const uint32_t u[4] = {pick3(c2, c3, d.w[3], d.w[4], d.w[5]),
+                           pick3(c2, c3, d.w[4], d.w[5], d.w[6]),
+                           pick3(c2, c3, d.w[5], d.w[6], d.w[7]),
+                           pick3(c2, c3, d.w[6], d.w[7], 0u)};
     W mv[3];
-    mv[1] = chunk_or_zero<GB>(tab_rest, g_rest, (uint32_t)M, um1);
-    const W R = M - mv[1];
-    mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, um0);
-    mv[2] = R - mv[0];
+    if (!redistribute3<W, GB>(M, u, mv, tab_half, g_half, tab_rest, g_rest))
+        return false;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
         c[i] = av[i] - kv[i] + mv[i];
     return true;
 }
 
-// Whether some count exceeds kMax = 2^b - 1: exactly then the OR of the
-// counts has a bit above kMax set.
+// OR of the counts.  Kernels accumulate it over their nodes in an integer
+// register: a count above kMax = 2^b - 1 exists exactly when the accumulated
+// OR exceeds kMax (a loop-carried integer is far cheaper than a loop-carried
+// per-lane flag, which the compiler keeps as a lane mask through every
+// divergent branch of the sampler).
 template <int Q, typename W>
-__device__ __forceinline__ bool any_above(const W (&c)[Q], W kMax)
+__device__ __forceinline__ W or_all(const W (&c)[Q])
 {
     W any = c[0];
 #pragma unroll
     for (int i = 1; i < Q; ++i)
         any |= c[i];
-    return any > kMax;
+    return any;
 }
 
 template <typename T> struct Wide;

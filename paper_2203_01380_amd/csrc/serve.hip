@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     const uint32_t *tab_rest = s_tab + 2 * kDevTableEntries;
     const uint8_t *g_p = s_guide, *g_half = s_guide + kG, *g_rest = s_guide + 2 * kG;
     constexpr W kMax = (W)(T)~(T)0;
-    bool overflow = false;
+    W ovf = 0;
 
     __syncthreads();  // the shared half table is visible to every wave
 
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         sampler::node_update<Q, W, NB, GB>(av, cn, x, sl.t0 + a.j, sl.realization, sl.key0,
                                            sl.key1, tab_p, g_p, tab_half, g_half, tab_rest,
                                            g_rest, sl.p_zero != 0);
-        overflow |= sampler::any_above<Q, W>(cn, kMax);
+        ovf |= sampler::or_all<Q, W>(cn);
         const uint32_t xm = (x == 0) ? L - 1 : x - 1;
         const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
         out[xm] = (T)cn[0];
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         if constexpr (Q == 3)
             out[pitch + x] = (T)cn[1];
     }
-    if (overflow)
+    if (ovf > kMax)
         atomicOr(a.err, 1u);
 }
 

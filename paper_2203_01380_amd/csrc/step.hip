@@ -11,7 +11,6 @@
 // contiguous eighth of the lattice.  (Two or four nodes per thread, with
 // vector loads, measured slower: the extra registers cost more than the
 // wider accesses gain in this VALU-bound kernel.)
-#include <cstdlib>
 #include <type_traits>
 
 #include "ilg_internal.h"
@@ -22,9 +21,14 @@ namespace ilg {
 namespace {
 
 constexpr int kNumXcd = 8;
+// Launch shape: 1024-thread workgroups, two per CU (the LDS tables and guides
+// of one workgroup take 74 KB).  512-thread workgroups and 128-bucket guides
+// measured slower.
+constexpr int kBlock = 1024;
+constexpr int kWgPerCu = 2;
 using sampler::Wide;
 
-template <int Q, typename T, int NB, int GB, int BLOCK, bool FLIP>
+template <int Q, typename T, int NB, int GB, int BLOCK, bool FLIP, bool PZ>
 __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 {
     using W = typename Wide<T>::type;
@@ -67,7 +71,6 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     const uint8_t *g_p = s_guide;
     const uint8_t *g_half = s_guide + kG;
     const uint8_t *g_rest = s_guide + 2 * kG;
-    const bool p_zero = a.p_zero != 0;
     const uint32_t L = a.length;
     const uint64_t pitch = a.pitch;
     const T *in = reinterpret_cast<const T *>(a.in);
@@ -88,7 +91,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         stride = gridDim.x;
     }
 
-    bool overflow = false;
+    W ovf = 0;
     for (uint32_t tile = first; tile < end; tile += stride) {
         const uint32_t x = tile * kTile + threadIdx.x;
         if (x >= L)
@@ -101,8 +104,8 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         for (int i = 0; i < Q; ++i)
             av[i] = FLIP ? n[Q - 1 - i] : n[i];
         sampler::node_update<Q, W, NB, GB>(av, cn, x, a.t, a.realization, a.key0, a.key1, tab_p,
-                                           g_p, tab_half, g_half, tab_rest, g_rest, p_zero);
-        overflow |= sampler::any_above<Q, W>(cn, kMax);
+                                           g_p, tab_half, g_half, tab_rest, g_rest, PZ);
+        ovf |= sampler::or_all<Q, W>(cn);
         // Streaming: velocity -1 to x-1, 0 in place, +1 to x+1 (periodic).
         const uint32_t xm = (x == 0) ? L - 1 : x - 1;
         const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
@@ -111,57 +114,40 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         if constexpr (Q == 3)
             out[pitch + x] = (T)cn[1];
     }
-    if (overflow)
+    if (ovf > kMax)
         atomicOr(a.err, 1u);
 }
 
-template <int Q, typename T, int NB, int GB, int BLOCK>
-hipError_t launch_variant(const StepArgs &a, hipStream_t stream, int wg_per_cu)
+template <int Q, typename T, int NB, bool FLIP, bool PZ>
+hipError_t launch_mode(const StepArgs &a, hipStream_t stream)
 {
-    constexpr uint32_t kTile = (uint32_t)BLOCK;
+    constexpr uint32_t kTile = (uint32_t)kBlock;
     const uint32_t ntiles = (a.length + kTile - 1) / kTile;
     static int cus = 0;
     if (cus == 0)
         cus = device_cu_count();
-    uint32_t grid = (uint32_t)cus * (uint32_t)wg_per_cu;
+    uint32_t grid = (uint32_t)cus * (uint32_t)kWgPerCu;
     if (ntiles < grid)
         grid = ntiles;
     if (grid >= (uint32_t)kNumXcd)
         grid -= grid % kNumXcd;
     if (grid == 0)
         grid = 1;
-    if (a.flip)
-        hipLaunchKernelGGL((step_kernel<Q, T, NB, GB, BLOCK, true>), dim3(grid), dim3(BLOCK), 0,
-                           stream, a);
-    else
-        hipLaunchKernelGGL((step_kernel<Q, T, NB, GB, BLOCK, false>), dim3(grid), dim3(BLOCK), 0,
-                           stream, a);
+    hipLaunchKernelGGL((step_kernel<Q, T, NB, kGuideBits, kBlock, FLIP, PZ>), dim3(grid),
+                       dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
-// Launch shapes (bit-identical results; only speed differs).  Variant 0 is
-// the default; ILG_STEP_VARIANT selects another for tuning runs.
-int step_variant()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char *e = std::getenv("ILG_STEP_VARIANT");
-        v = e ? std::atoi(e) : 0;
-    }
-    return v;
-}
-
+// The flip and a zero collision fraction are per-lattice constants, so each
+// combination has its own kernel (no per-node tests for them).
 template <int Q, typename T, int NB>
 hipError_t launch_q(const StepArgs &a, hipStream_t stream)
 {
-    switch (step_variant()) {
-    case 1:
-        return launch_variant<Q, T, NB, 7, 1024>(a, stream, 2);
-    case 2:
-        return launch_variant<Q, T, NB, 8, 512>(a, stream, 4);
-    default:
-        return launch_variant<Q, T, NB, 8, 1024>(a, stream, 2);
-    }
+    if (a.p_zero)
+        return a.flip ? launch_mode<Q, T, NB, true, true>(a, stream)
+                      : launch_mode<Q, T, NB, false, true>(a, stream);
+    return a.flip ? launch_mode<Q, T, NB, true, false>(a, stream)
+                  : launch_mode<Q, T, NB, false, false>(a, stream);
 }
 
 }  // namespace

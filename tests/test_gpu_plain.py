@@ -147,6 +147,19 @@ def test_mixed_middle_chunk_layouts(ilg, oracle_lib, cb, omega):
     _run_both(ilg, oracle_lib, 3, L, cb, omega, init, steps=6, seed=13)
 
 
+@pytest.mark.parametrize("q,omega,theta,mean", [(2, 1.0, 0.0, 60.0), (2, 1.1, 0.0, 60.0),
+                                                 (3, 1.0, 0.0, 60.0), (3, 0.9, 0.0, 45.0),
+                                                 (3, 1.05, 0.9, 40.0), (3, 1.0, 0.0, 95.0),
+                                                 (3, 1.2, 0.0, 70.0)])
+def test_multi_chunk_redistribution(ilg, oracle_lib, q, omega, theta, mean):
+    """Collision fractions near one remove most particles, so M = sum k_i spans
+    one to three chunks (and beyond three for mean 95); theta = 0.9 leaves
+    R = M - m_1 above one chunk.  Every lane layout of the redistribution
+    draws is compared with the oracle."""
+    init = W.init_poisson_iid(q, 5000, mean, 2, init_seed=int(mean) + 7 * q)
+    _run_both(ilg, oracle_lib, q, 5000, 2, omega, init, steps=6, seed=17, theta=theta)
+
+
 @pytest.mark.parametrize("q,omega,flip", [(3, 2.0, "auto"), (2, 2.0, "auto"), (3, 1.0, "on"),
                                           (3, 1.0, "off"), (2, 0.5, "auto"), (3, 0.3, "auto"),
                                           (3, 1.999, "auto"), (2, 0.01, "auto")])
