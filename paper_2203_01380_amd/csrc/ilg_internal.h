@@ -161,10 +161,7 @@ struct ServeSlot {
     uint32_t steps;        // steps in this quantum
     uint32_t realization, key0, key1;
     uint32_t flip, p_zero, cur0;
-};
-struct ServeTile {
-    uint32_t slot;
-    uint32_t x0;
+    uint32_t tile_begin, tile_end;  // the slot's tiles in the launch's tile list
 };
 constexpr int kServeGuideBits = 8;
 constexpr int kServeTile = 1024;  // nodes per tile (one workgroup pass)
@@ -178,8 +175,8 @@ inline size_t serve_table_set_bytes(int q)
 
 struct ServeArgs {
     void *arena;
-    const ServeSlot *slots;
-    const ServeTile *tiles;
+    const ServeSlot *slots;      // in tile order: slot s owns tiles [tile_begin, tile_end)
+    const uint32_t *tile_slot;   // slot of each tile
     uint32_t ntiles;
     uint32_t j;             // step index within the quantum
     const void *shared;     // half table then its guide

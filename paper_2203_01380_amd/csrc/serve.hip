@@ -1,8 +1,9 @@
 // Multi-slot lattice-gas step for the continuous-batching server.
 //
 // One launch advances every active request (slot) of one (q, count type) by
-// one step: the host lists the slots' tiles of 1024 nodes, slot by slot, and
-// each workgroup of a persistent grid walks a contiguous range of that list.
+// one step: the host lists the slots' tiles of 1024 nodes, slot by slot (each
+// slot's descriptor holds its tile range), and each workgroup of a persistent
+// grid walks a contiguous range of that list.
 // When the walk enters a new slot the workgroup stages the slot's removal and
 // rest tables with their guides in LDS (the half table is shared and staged
 // once).  Slots whose quantum is shorter than the current step index are
@@ -55,13 +56,21 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
 
     const uint32_t lo = (uint32_t)((uint64_t)a.ntiles * blockIdx.x / gridDim.x);
     const uint32_t hi = (uint32_t)((uint64_t)a.ntiles * (blockIdx.x + 1) / gridDim.x);
+    if (lo >= hi)
+        return;
+    // Only the slot index is carried from tile to tile: the descriptor is a
+    // scalar-cache read with no dependence on a per-tile lookup.  (Carrying
+    // the descriptor itself measured slower: the compiler keeps it in vector
+    // registers.)
+    uint32_t slot = a.tile_slot[lo];
     uint32_t staged = 0xFFFFFFFFu;
     for (uint32_t tile = lo; tile < hi; ++tile) {
-        const ServeTile tl = a.tiles[tile];
-        const ServeSlot sl = a.slots[tl.slot];
+        while (tile >= a.slots[slot].tile_end)
+            ++slot;
+        const ServeSlot sl = a.slots[slot];
         if (a.j >= sl.steps)
             continue;
-        if (tl.slot != staged) {
+        if (slot != staged) {
             // Barriers only where the walk enters a new slot: before the
             // restage (readers of the previous slot's tables are done) and
             // after it (the new tables are visible).
@@ -79,10 +88,10 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
                 for (int i = threadIdx.x; i < kG / 16; i += kBlock)
                     gdst[i] = gsrc[i];
             }
-            staged = tl.slot;
+            staged = slot;
             __syncthreads();
         }
-        const uint32_t x = tl.x0 + threadIdx.x;
+        const uint32_t x = (tile - sl.tile_begin) * (uint32_t)kBlock + threadIdx.x;
         const uint32_t L = sl.length;
         if (x >= L)
             continue;

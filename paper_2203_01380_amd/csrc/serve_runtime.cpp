@@ -80,7 +80,7 @@ public:
     uint32_t *err = nullptr;
     hipStream_t streams[4] = {nullptr, nullptr, nullptr, nullptr};  // (q, count type) groups
     ilg::ServeSlot *d_slots[4] = {nullptr, nullptr, nullptr, nullptr};
-    ilg::ServeTile *d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint32_t *d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};  // slot of each tile
     size_t cap_slots[4] = {0, 0, 0, 0}, cap_tiles[4] = {0, 0, 0, 0};
     hipStream_t io = nullptr;  // copies in and out
     int last_rc = ILG_OK;
@@ -150,14 +150,14 @@ public:
     // Host copies of the last launch's slot and tile lists (kept alive until
     // the copies from them have completed).
     std::vector<ilg::ServeSlot> h_slots[4];
-    std::vector<ilg::ServeTile> h_tiles[4];
+    std::vector<uint32_t> h_tiles[4];
     std::vector<Req *> launched;
     std::vector<uint32_t> launched_steps;
 
     int launch(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) override
     {
         std::vector<ilg::ServeSlot> *slots = h_slots;
-        std::vector<ilg::ServeTile> *tiles = h_tiles;
+        std::vector<uint32_t> *tiles = h_tiles;
         for (int g = 0; g < 4; ++g) {
             slots[g].clear();
             tiles[g].clear();
@@ -185,9 +185,11 @@ public:
             s.p_zero = p->fx.p == 0 ? 1u : 0u;
             s.cur0 = p->cur;
             const uint32_t idx = (uint32_t)slots[g].size();
+            const uint32_t nt = (uint32_t)((c.length + ilg::kServeTile - 1) / ilg::kServeTile);
+            s.tile_begin = (uint32_t)tiles[g].size();
+            s.tile_end = s.tile_begin + nt;
             slots[g].push_back(s);
-            for (uint64_t x0 = 0; x0 < c.length; x0 += ilg::kServeTile)
-                tiles[g].push_back(ilg::ServeTile{idx, (uint32_t)x0});
+            tiles[g].insert(tiles[g].end(), nt, idx);
             maxsteps[g] = std::max(maxsteps[g], steps[i]);
         }
         for (int g = 0; g < 4; ++g) {
@@ -198,12 +200,12 @@ public:
                 return rc;
             SHIP(hipMemcpyAsync(d_slots[g], slots[g].data(), slots[g].size() * sizeof(ilg::ServeSlot),
                                 hipMemcpyHostToDevice, streams[g]));
-            SHIP(hipMemcpyAsync(d_tiles[g], tiles[g].data(), tiles[g].size() * sizeof(ilg::ServeTile),
+            SHIP(hipMemcpyAsync(d_tiles[g], tiles[g].data(), tiles[g].size() * sizeof(uint32_t),
                                 hipMemcpyHostToDevice, streams[g]));
             ilg::ServeArgs a;
             a.arena = arena;
             a.slots = d_slots[g];
-            a.tiles = d_tiles[g];
+            a.tile_slot = d_tiles[g];
             a.ntiles = (uint32_t)tiles[g].size();
             a.shared = shared;
             a.err = err;
@@ -260,7 +262,7 @@ public:
         if (ntiles > cap_tiles[g]) {
             (void)hipFree(d_tiles[g]);
             cap_tiles[g] = std::max(ntiles, 2 * cap_tiles[g]);
-            SHIP(hipMalloc((void **)&d_tiles[g], cap_tiles[g] * sizeof(ilg::ServeTile)));
+            SHIP(hipMalloc((void **)&d_tiles[g], cap_tiles[g] * sizeof(uint32_t)));
         }
         return ILG_OK;
     }
