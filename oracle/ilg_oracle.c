@@ -35,6 +35,7 @@
  *
  * This code is written to be checked by eye, not to be fast.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -380,4 +381,141 @@ void oracle_binomial_samples(uint64_t n, const uint32_t *table, uint64_t seed, u
         stream_init(&st, seed, (uint32_t)s, 0, 0);
         out[s] = binomial(n, table, &st);
     }
+}
+
+/* ------------------------------------------------ Poisson sine initialisation
+ *
+ * The paper's initial state (Results, the sine density profile): occupation
+ * n_i(x) is a Poisson variate with expectation w_i times the density profile
+ * N [1 + sin(2 pi x / L)]; here with a general amplitude A,
+ *   mean_i(x) = w_i (N + A sin(2 pi x / L)).
+ * Reading (a specification of this build, "init v1"): so that two IEEE-754
+ * machines draw the same counts, every floating-point step below is one
+ * correctly rounded double operation (no fused multiply-add, no library
+ * transcendental):
+ *   sin(2 pi x / L): 8x = k L + rem with integers (octant k); for even k
+ *     t = rem / L, for odd k t = (L - rem) / L (the distance to the octant's
+ *     end, again from integers); a = t * (pi/4), a2 = a * a,
+ *     S = a * (1 + a2 (s1 + a2 (s2 + ... + a2 s8))),  s_j = (-1)^j / (2j+1)!
+ *     C = 1 + a2 (c1 + a2 (c2 + ... + a2 c9)),         c_j = (-1)^j / (2j)!
+ *     (Horner from the innermost coefficient); the value for k = 0..7 is
+ *     S, C, C, S, -S, -C, -C, -S;
+ *   e^-m for 0 <= m <= 256 (Cody-Waite reduction): n = (int)(m log2(e) + 0.5),
+ *     r = (m - n ln2_hi) - n ln2_lo, e^-r = sum_{j=0..17} (-r)^j / j! (Horner),
+ *     times 2^-n;
+ *   mean = w_i * (N + A * value); mean <= 0 gives 0;
+ *   parts P = max(1, ceil(mean / 256)), m = mean / P, and per part p a Philox
+ *   block with key = init seed, counter = (x, p, realization, 2^31); word i
+ *   is the part's draw u, U = (u + 1/2) 2^-32, and the part's count is the
+ *   least k with U <= F(k), F(0) = f(0) = e^-m, f(k) = (f(k-1) m) / k,
+ *   F(k) = F(k-1) + f(k) (the Poisson CDF by its recurrence), capped at 10^5;
+ *   n_i(x) = the sum over the parts (a sum of independent Poisson(m) is
+ *   Poisson(mean)).
+ * Coefficients 1/j! are 1.0 / j! with j! exact in double (j <= 18).  The
+ * counter's last word 2^31 keeps these blocks apart from the step's draw
+ * blocks (whose last word is a small block index). */
+
+static const double ORACLE_PI_4 = 0x1.921fb54442d18p-1;  /* pi / 4 */
+static const double ORACLE_LOG2E = 0x1.71547652b82fep+0; /* log2(e) */
+static const double ORACLE_LN2_HI = 0x1.62e42feep-1;     /* ln 2, upper bits */
+static const double ORACLE_LN2_LO = 0x1.a39ef35793c76p-33; /* ln 2 - ln2_hi */
+
+static double inv_factorial(int j)
+{
+    double f = 1.0;
+    for (int i = 2; i <= j; ++i)
+        f = f * (double)i;
+    return 1.0 / f;
+}
+
+/* sin(2 pi x / L) for integers 0 <= x < L */
+double oracle_sin2pi_frac(uint64_t x, uint64_t L)
+{
+    const uint64_t eight_x = 8 * x;
+    const uint64_t k = eight_x / L, rem = eight_x % L;
+    const double t = (double)(k % 2 == 0 ? rem : L - rem) / (double)L;
+    const double a = t * ORACLE_PI_4;
+    const double a2 = a * a;
+    double hs = (8 % 2 ? -1.0 : 1.0) * inv_factorial(17);   /* s8 = +1/17! */
+    for (int j = 7; j >= 1; --j)
+        hs = (j % 2 ? -1.0 : 1.0) * inv_factorial(2 * j + 1) + a2 * hs;
+    hs = 1.0 + a2 * hs;
+    const double S = a * hs;
+    double hc = (9 % 2 ? -1.0 : 1.0) * inv_factorial(18);   /* c9 = -1/18! */
+    for (int j = 8; j >= 1; --j)
+        hc = (j % 2 ? -1.0 : 1.0) * inv_factorial(2 * j) + a2 * hc;
+    const double C = 1.0 + a2 * hc;
+    switch (k) {
+    case 0: return S;
+    case 1: return C;
+    case 2: return C;
+    case 3: return S;
+    case 4: return -S;
+    case 5: return -C;
+    case 6: return -C;
+    default: return -S;
+    }
+}
+
+/* e^-m for 0 <= m <= 256 */
+double oracle_exp_neg(double m)
+{
+    const int n = (int)(m * ORACLE_LOG2E + 0.5);
+    const double r = (m - (double)n * ORACLE_LN2_HI) - (double)n * ORACLE_LN2_LO;
+    const double y = -r;
+    double h = inv_factorial(17);
+    for (int j = 16; j >= 0; --j)
+        h = inv_factorial(j) + y * h;
+    return ldexp(h, -n);
+}
+
+/* Poisson(m) by the inverse CDF, 0 < m <= 256, from one 32-bit draw */
+static uint64_t poisson_part(double m, uint32_t u)
+{
+    const double U = ((double)u + 0.5) * 0x1p-32;
+    double f = oracle_exp_neg(m);
+    double F = f;
+    uint64_t k = 0;
+    while (U > F && k < 100000) {
+        k += 1;
+        f = (f * m) / (double)k;
+        F = F + f;
+    }
+    return k;
+}
+
+/* Counts of nodes x0 .. x0+width-1 (taken mod L) into out[q][width] (count
+ * type count_bytes); weights w[0..q-1].  Returns 1 if a count exceeds the
+ * count type (the stored value is then truncated), else 0. */
+int oracle_init_poisson_sine(int q, int count_bytes, uint64_t length, uint64_t x0,
+                             uint64_t width, const double *w, double nave, double amp,
+                             uint64_t seed, uint32_t realization, void *out)
+{
+    const uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
+    const uint64_t maxv = count_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu;
+    int overflow = 0;
+    for (uint64_t k = 0; k < width; ++k) {
+        const uint64_t x = (x0 + k) % length;
+        const double s = oracle_sin2pi_frac(x, length);
+        const double rho = nave + amp * s;
+        for (int i = 0; i < q; ++i) {
+            const double mean = w[i] * rho;
+            uint64_t n = 0;
+            if (mean > 0.0) {
+                const double parts_d = ceil(mean / 256.0);
+                const uint32_t parts = parts_d < 1.0 ? 1u : (uint32_t)parts_d;
+                const double m = mean / (double)parts;
+                for (uint32_t p = 0; p < parts; ++p) {
+                    const uint32_t ctr[4] = {(uint32_t)x, p, realization, 0x80000000u};
+                    uint32_t blk[4];
+                    oracle_philox4x32_10(ctr, key, blk);
+                    n += poisson_part(m, blk[i]);
+                }
+            }
+            if (n > maxv)
+                overflow = 1;
+            store_count(out, count_bytes, (size_t)i * width + k, n);
+        }
+    }
+    return overflow;
 }

@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     os.makedirs(_BUILD_DIR, exist_ok=True)
     tmp = _LIB_PATH + ".tmp"
     subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-pthread",
-                    _SRC, "-o", tmp], check=True)
+                    _SRC, "-o", tmp, "-lm"], check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -75,6 +75,15 @@ def lib():
         L.oracle_binomial_samples.argtypes = [ctypes.c_uint64, vp, ctypes.c_uint64,
                                               ctypes.c_uint64, vp]
         L.oracle_binomial_samples.restype = None
+        L.oracle_sin2pi_frac.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.oracle_sin2pi_frac.restype = ctypes.c_double
+        L.oracle_exp_neg.argtypes = [ctypes.c_double]
+        L.oracle_exp_neg.restype = ctypes.c_double
+        L.oracle_init_poisson_sine.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                               ctypes.c_uint64, ctypes.c_uint64, vp,
+                                               ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                               ctypes.c_uint32, vp]
+        L.oracle_init_poisson_sine.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -168,3 +177,32 @@ def binomial_samples(n: int, table: Optional[np.ndarray], nsamples: int, seed: i
     out = np.zeros(nsamples, dtype=np.uint64)
     lib().oracle_binomial_samples(n, _ptr(table), seed, nsamples, _ptr(out))
     return out
+
+
+def init_weights(q: int, theta: float = 1.0 / 3.0) -> np.ndarray:
+    """Velocity weights of the initial means: D1Q2 (1/2, 1/2); D1Q3
+    (theta/2, 1 - theta, theta/2), each one double operation."""
+    if q == 2:
+        return np.array([0.5, 0.5])
+    return np.array([theta * 0.5, 1.0 - theta, theta * 0.5])
+
+
+def init_poisson_sine(q: int, count_bytes: int, length: int, nave: float, amp: float,
+                      seed: int, realization: int = 0, theta: float = 1.0 / 3.0, x0: int = 0,
+                      width: Optional[int] = None):
+    """Poisson sine initial state of nodes x0 .. x0+width-1 (mod L), as
+    [q][width] counts, and the overflow flag (init v1, see ilg_oracle.c)."""
+    width = length if width is None else width
+    w = np.ascontiguousarray(init_weights(q, theta), dtype=np.float64)
+    out = np.zeros((q, width), dtype=np.uint16 if count_bytes == 2 else np.uint32)
+    ov = lib().oracle_init_poisson_sine(q, count_bytes, length, x0, width, _ptr(w), float(nave),
+                                        float(amp), seed, realization, _ptr(out))
+    return out, bool(ov)
+
+
+def sin2pi_frac(x: int, length: int) -> float:
+    return float(lib().oracle_sin2pi_frac(x, length))
+
+
+def exp_neg(m: float) -> float:
+    return float(lib().oracle_exp_neg(m))
