@@ -120,7 +120,8 @@ uint64_t ilg_state_bytes(const ilg_config *cfg);
 uint64_t ilg_state_pitch(const ilg_config *cfg);
 
 /* Create a lattice; init_host is [q][L] counts (compact, count_bytes each),
- * copied before return.  Device buffers are owned by the handle. */
+ * copied before return, or NULL for an all-zero state (to be replaced by
+ * ilg_init_poisson_sine).  Device buffers are owned by the handle. */
 int ilg_create(const ilg_config *cfg, const void *init_host, void *stream, ilg_handle **out);
 
 /* Create a lattice on caller-owned device buffers of ilg_state_bytes(cfg)
@@ -142,7 +143,21 @@ int ilg_get_state(ilg_handle *h, void *host_out);
  * the next step to t (checkpoint restore).  Syncs. */
 int ilg_set_state(ilg_handle *h, const void *host_in, uint64_t t);
 
-/* Reductions of the current state (device kernels, then a small copy).
+/* Replace the state by the paper's Poisson sine initial condition drawn on
+ * the device (Results section, the sinusoidal initial density with integer
+ * occupations): n_i(x) ~ Poisson(w_i (nave + amp sin(2 pi x / L))), weights
+ * (1/2, 1/2) for q = 2 and (theta/2, 1 - theta, theta/2) for q = 3, drawn
+ * with Philox4x32-10 keyed by init_seed (independent of the step seed) and
+ * the configuration's realization.  The arithmetic is fixed ("init v1":
+ * correctly rounded double operations only, no library transcendental), so
+ * the counts are reproducible bit for bit on any IEEE-754 machine.
+ * Requires 0 <= nave <= 1e6 and |amp| <= nave (ILG_E_INVALID otherwise);
+ * ILG_E_OVERFLOW if a count exceeds the count type, the state then being
+ * left unchanged.  The step index is not changed; the sticky error word is
+ * cleared.  Syncs. */
+int ilg_init_poisson_sine(ilg_handle *h, double nave, double amp, uint64_t init_seed);
+
+/* Reductions of the current state (device kernels, then a small copy)./* Reductions of the current state (device kernels, then a small copy).
  * rho, j, e: optional host arrays of L int64 receiving the per-node raw
  * moments sum_i n_i, sum_i v_i n_i, sum_i v_i^2 n_i (NULL to skip).
  * nk <= ILG_MAX_K structure-factor modes are computed.  Syncs. */

@@ -99,6 +99,7 @@ def _load():
         "ilg_step": ([hp, u64], i32),
         "ilg_get_state": ([hp, vp], i32),
         "ilg_set_state": ([hp, vp, u64], i32),
+        "ilg_init_poisson_sine": ([hp, ctypes.c_double, ctypes.c_double, u64], i32),
         "ilg_moments": ([hp, vp, vp, vp, u32, ctypes.POINTER(IlgSummary)], i32),
         "ilg_state_hash": ([hp, ctypes.POINTER(u64)], i32),
         "ilg_current_step": ([hp], u64),
@@ -168,13 +169,16 @@ class Lattice:
     library allocates them itself (ilg_create)."""
 
     def __init__(self, q: int, length: int, count_bytes: int, omega: float, seed: int,
-                 init: np.ndarray, realization: int = 0, t0: int = 0, theta: float = 0.0,
-                 flip: str = "auto", use_torch: bool = True, stream=None):
+                 init: Optional[np.ndarray], realization: int = 0, t0: int = 0,
+                 theta: float = 0.0, flip: str = "auto", use_torch: bool = True, stream=None):
+        """init: [q][L] host counts, or None for an all-zero state (then call
+        init_poisson_sine to draw the initial state on the device)."""
         self.cfg = make_config(q, length, count_bytes, omega, seed, realization, t0, theta, flip)
         self.q, self.length, self.count_bytes = q, length, count_bytes
-        init = np.ascontiguousarray(init, dtype=_dtype(count_bytes))
-        if init.shape != (q, length):
-            raise ValueError(f"init must have shape {(q, length)}, got {init.shape}")
+        if init is not None:
+            init = np.ascontiguousarray(init, dtype=_dtype(count_bytes))
+            if init.shape != (q, length):
+                raise ValueError(f"init must have shape {(q, length)}, got {init.shape}")
         self._h = ctypes.c_void_p()
         self._bufs = None
         if use_torch:
@@ -184,13 +188,15 @@ class Lattice:
             self._stream = stream
             nbytes = int(lib.ilg_state_bytes(ctypes.byref(self.cfg)))
             pitch = int(lib.ilg_state_pitch(ctypes.byref(self.cfg)))
-            padded = np.zeros((q, pitch), dtype=init.dtype)
-            padded[:, :length] = init
-            host = torch.from_numpy(padded.view(np.uint8).reshape(-1))
             b0 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
             b1 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
             with torch.cuda.stream(stream):
-                b0.copy_(host)
+                if init is None:
+                    b0.zero_()
+                else:
+                    padded = np.zeros((q, pitch), dtype=init.dtype)
+                    padded[:, :length] = init
+                    b0.copy_(torch.from_numpy(padded.view(np.uint8).reshape(-1)))
             stream.synchronize()
             self._bufs = (b0, b1)
             check(lib.ilg_create_on(ctypes.byref(self.cfg), ctypes.c_void_p(b0.data_ptr()),
@@ -199,7 +205,8 @@ class Lattice:
         else:
             self._stream = None
             sp = None if stream is None else ctypes.c_void_p(int(stream))
-            check(lib.ilg_create(ctypes.byref(self.cfg), init.ctypes.data, sp,
+            check(lib.ilg_create(ctypes.byref(self.cfg),
+                                 None if init is None else init.ctypes.data, sp,
                                  ctypes.byref(self._h)))
 
     @property
@@ -221,6 +228,11 @@ class Lattice:
     def set_state(self, state: np.ndarray, t: int):
         s = np.ascontiguousarray(state, dtype=_dtype(self.count_bytes))
         check(lib.ilg_set_state(self._h, s.ctypes.data, t))
+
+    def init_poisson_sine(self, nave: float, amp: float, init_seed: int):
+        """Draw the Poisson sine initial state on the device (init v1):
+        n_i(x) ~ Poisson(w_i (nave + amp sin(2 pi x / L)))."""
+        check(lib.ilg_init_poisson_sine(self._h, float(nave), float(amp), int(init_seed)))
 
     def hash(self) -> int:
         out = ctypes.c_uint64()

@@ -75,6 +75,18 @@ struct StepArgs {
     uint32_t *err;         // sticky error word (bit 0: overflow)
 };
 
+// Poisson sine initial state (init v1): counts into out, [q][pitch].
+struct InitArgs {
+    void *out;
+    uint64_t pitch;
+    uint32_t length, q;
+    uint32_t realization, key0, key1;  // Philox key = init seed
+    double w[3];                       // velocity weights
+    double nave, amp;
+    uint32_t *err;                     // bit 0 set if a count exceeds the type
+};
+hipError_t launch_init(int count_bytes, const InitArgs &a, hipStream_t stream);
+
 // Launch one step of a q-velocity, count_bytes lattice on stream.
 hipError_t launch_step(int q, int count_bytes, const StepArgs &a, hipStream_t stream);
 

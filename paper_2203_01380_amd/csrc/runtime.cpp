@@ -276,10 +276,6 @@ int ilg_create(const ilg_config *cfg, const void *init_host, void *stream, ilg_h
     int rc = create_common(cfg, stream, out, &h);
     if (rc != ILG_OK)
         return rc;
-    if (!init_host) {
-        delete h;
-        return fail(ILG_E_INVALID, "null initial state");
-    }
     h->owns_state = true;
     hipError_t e1 = hipMalloc(&h->buf[0], h->bytes);
     hipError_t e2 = hipMalloc(&h->buf[1], h->bytes);
@@ -288,8 +284,14 @@ int ilg_create(const ilg_config *cfg, const void *init_host, void *stream, ilg_h
         return fail(ILG_E_NOMEM, "device allocation of the state failed");
     }
     rc = alloc_common(h);
-    if (rc == ILG_OK)
+    if (rc == ILG_OK && init_host) {
         rc = copy_state_in(h, init_host);
+    } else if (rc == ILG_OK) {
+        // no initial state: zero counts (for a device-side initialisation)
+        if (hipMemsetAsync(h->buf[0], 0, h->bytes, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess)
+            rc = fail(ILG_E_DEVICE, "zeroing the state failed");
+    }
     if (rc != ILG_OK) {
         std::string msg = g_last_error;
         release(h);
@@ -371,6 +373,50 @@ int ilg_set_state(ilg_handle *h, const void *host_in, uint64_t t)
     ILG_HIP(hipMemsetAsync(h->err, 0, sizeof(uint32_t), h->stream));
     ILG_HIP(hipStreamSynchronize(h->stream));
     h->t = t;
+    return ILG_OK;
+}
+
+int ilg_init_poisson_sine(ilg_handle *h, double nave, double amp, uint64_t init_seed)
+{
+    if (!h)
+        return fail(ILG_E_INVALID, "null handle");
+    if (!std::isfinite(nave) || !std::isfinite(amp) || nave < 0.0 || nave > 1.0e6 ||
+        std::fabs(amp) > nave)
+        return fail(ILG_E_INVALID, "need 0 <= nave <= 1e6 and |amp| <= nave");
+    const double theta = h->cfg.theta == 0.0 ? 1.0 / 3.0 : h->cfg.theta;
+    ilg::InitArgs a;
+    a.out = h->buf[h->cur ^ 1];
+    a.pitch = h->pitch;
+    a.length = (uint32_t)h->cfg.length;
+    a.q = h->cfg.q;
+    a.realization = h->cfg.realization;
+    a.key0 = (uint32_t)(init_seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(init_seed >> 32);
+    if (h->cfg.q == 2) {
+        a.w[0] = 0.5;
+        a.w[1] = 0.5;
+        a.w[2] = 0.0;
+    } else {
+        a.w[0] = theta * 0.5;
+        a.w[1] = 1.0 - theta;
+        a.w[2] = theta * 0.5;
+    }
+    a.nave = nave;
+    a.amp = amp;
+    a.err = h->err;
+    ILG_HIP(hipMemsetAsync(h->err, 0, sizeof(uint32_t), h->stream));
+    hipError_t e = ilg::launch_init((int)h->cfg.count_bytes, a, h->stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "init launch");
+    uint32_t err = 0;
+    ILG_HIP(hipMemcpyAsync(&err, h->err, sizeof(err), hipMemcpyDeviceToHost, h->stream));
+    ILG_HIP(hipStreamSynchronize(h->stream));
+    if (err & 1u) {
+        ILG_HIP(hipMemsetAsync(h->err, 0, sizeof(uint32_t), h->stream));
+        ILG_HIP(hipStreamSynchronize(h->stream));
+        return fail(ILG_E_OVERFLOW, "an initial count exceeds the count type (state unchanged)");
+    }
+    h->cur ^= 1;
     return ILG_OK;
 }
 
