@@ -275,6 +275,15 @@ int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server 
 int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_host,
                       uint64_t nsteps, uint64_t *id);
 
+/* Queue a request whose initial state is the paper's Poisson sine condition
+ * drawn on the device at admission (no host state is copied): as
+ * ilg_init_poisson_sine with nave, amp and init_seed, the configuration's
+ * realization and theta.  Same argument rules as ilg_init_poisson_sine; a
+ * drawn count above the count type is reported as ILG_E_OVERFLOW by a later
+ * poll, like an overflow during the steps. */
+int ilg_server_submit_poisson_sine(ilg_server *s, const ilg_config *cfg, double nave, double amp,
+                                   uint64_t init_seed, uint64_t nsteps, uint64_t *id);
+
 /* One scheduling round (admit, advance one quantum, retire).  Syncs. */
 int ilg_server_poll(ilg_server *s, ilg_poll_info *info);
 

@@ -117,6 +117,8 @@ def _load():
         "ilg_server_clock": ([], ctypes.c_double),
         "ilg_server_create": ([u64, u32, ctypes.POINTER(hp)], i32),
         "ilg_server_submit": ([hp, cfgp, vp, u64, ctypes.POINTER(u64)], i32),
+        "ilg_server_submit_poisson_sine": ([hp, cfgp, ctypes.c_double, ctypes.c_double, u64, u64,
+                                            ctypes.POINTER(u64)], i32),
         "ilg_server_poll": ([hp, ctypes.POINTER(IlgPollInfo)], i32),
         "ilg_server_info": ([hp, u64, ctypes.POINTER(IlgRequestInfo)], i32),
         "ilg_server_result": ([hp, u64, vp], i32),
@@ -385,6 +387,20 @@ class Server:
         rid = ctypes.c_uint64()
         check(lib.ilg_server_submit(self._h, ctypes.byref(cfg), a.ctypes.data, nsteps,
                                     ctypes.byref(rid)))
+        self._shapes[int(rid.value)] = (member["q"], member["length"], member["count_bytes"])
+        return int(rid.value)
+
+    def submit_poisson_sine(self, member: dict, nave: float, amp: float, init_seed: int,
+                            nsteps: int) -> int:
+        """Queue a request whose initial state is drawn on the device at
+        admission (Poisson sine condition, init v1)."""
+        cfg = make_config(member["q"], member["length"], member["count_bytes"], member["omega"],
+                          member["seed"], member.get("realization", 0), member.get("t0", 0),
+                          member.get("theta", 0.0), member.get("flip", "auto"))
+        rid = ctypes.c_uint64()
+        check(lib.ilg_server_submit_poisson_sine(self._h, ctypes.byref(cfg), float(nave),
+                                                 float(amp), int(init_seed), nsteps,
+                                                 ctypes.byref(rid)))
         self._shapes[int(rid.value)] = (member["q"], member["length"], member["count_bytes"])
         return int(rid.value)
 

@@ -7,6 +7,7 @@
 // overlaps), and copies finished states back to host memory.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -61,6 +62,10 @@ struct Payload {
     std::vector<unsigned char> host;  // initial state, later the final state ([q][L])
     uint64_t t = 0;                   // absolute index of the next step
     uint32_t cur = 0;                 // buffer holding the current state
+    // initial state drawn on the device at admission instead of copied in
+    bool device_init = false;
+    double nave = 0.0, amp = 0.0;
+    uint64_t init_seed = 0;
 };
 
 Payload *payload_of(Req &r)
@@ -102,8 +107,31 @@ public:
         const ilg_config &c = p->cfg;
         const size_t cb = c.count_bytes, pitch = pitch_of(c.length);
         unsigned char *base = static_cast<unsigned char *>(arena) + r.mem_off;
-        SHIP(hipMemcpy2DAsync(base, pitch * cb, p->host.data(), c.length * cb, c.length * cb, c.q,
-                              hipMemcpyHostToDevice, io));
+        if (p->device_init) {
+            // Poisson sine state drawn in place; a count above the type sets
+            // the sticky error word, reported by the next wait.
+            const double theta = c.theta == 0.0 ? 1.0 / 3.0 : c.theta;
+            ilg::InitArgs a;
+            a.out = base;
+            a.pitch = pitch;
+            a.length = (uint32_t)c.length;
+            a.q = c.q;
+            a.realization = c.realization;
+            a.key0 = (uint32_t)(p->init_seed & 0xFFFFFFFFu);
+            a.key1 = (uint32_t)(p->init_seed >> 32);
+            a.w[0] = c.q == 2 ? 0.5 : theta * 0.5;
+            a.w[1] = c.q == 2 ? 0.5 : 1.0 - theta;
+            a.w[2] = c.q == 2 ? 0.0 : theta * 0.5;
+            a.nave = p->nave;
+            a.amp = p->amp;
+            a.err = err;
+            hipError_t e = ilg::launch_init((int)cb, a, io);
+            if (e != hipSuccess)
+                return shfail(e, "init launch");
+        } else {
+            SHIP(hipMemcpy2DAsync(base, pitch * cb, p->host.data(), c.length * cb, c.length * cb,
+                                  c.q, hipMemcpyHostToDevice, io));
+        }
         // table set: removal table (+ rest table for q = 3) then their guides
         const int nt = c.q == 3 ? 2 : 1;
         std::vector<unsigned char> set(ilg::serve_table_set_bytes((int)c.q), 0);
@@ -246,6 +274,8 @@ public:
         const size_t cb = c.count_bytes, pitch = pitch_of(c.length);
         const unsigned char *src = static_cast<const unsigned char *>(arena) + r.mem_off +
                                    (size_t)p->cur * c.q * pitch * cb;
+        // a request drawn on the device has no host copy of its state yet
+        p->host.resize((size_t)c.q * c.length * cb);
         SHIP(hipMemcpy2DAsync(p->host.data(), c.length * cb, src, pitch * cb, c.length * cb, c.q,
                               hipMemcpyDeviceToHost, io));
         SHIP(hipStreamSynchronize(io));
@@ -356,6 +386,38 @@ int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_hos
     const size_t bytes = (size_t)cfg->q * cfg->length * cfg->count_bytes;
     p->host.assign(static_cast<const unsigned char *>(init_host),
                    static_cast<const unsigned char *>(init_host) + bytes);
+    std::unique_ptr<Req> r(new Req);
+    r->q = cfg->q;
+    r->total = nsteps;
+    r->payload = p;
+    if (!s->sched->submit(std::move(r), s->ex, id, steady_now()))
+        return sfail(ILG_E_BUSY, "request does not fit the server's memory budget");
+    return ILG_OK;
+}
+
+int ilg_server_submit_poisson_sine(ilg_server *s, const ilg_config *cfg, double nave, double amp,
+                                   uint64_t init_seed, uint64_t nsteps, uint64_t *id)
+{
+    if (!s || !id)
+        return sfail(ILG_E_INVALID, "null argument");
+    if (!std::isfinite(nave) || !std::isfinite(amp) || nave < 0.0 || nave > 1.0e6 ||
+        std::fabs(amp) > nave)
+        return sfail(ILG_E_INVALID, "need 0 <= nave <= 1e6 and |amp| <= nave");
+    ilg::Fixed fx;
+    int rc = ilg::check_config(cfg, &fx);
+    if (rc != ILG_OK)
+        return rc;
+    if (nsteps == 0)
+        return sfail(ILG_E_INVALID, "nsteps must be positive");
+    if (cfg->t0 + nsteps > (uint64_t(1) << 32))
+        return sfail(ILG_E_RANGE, "step index would pass 2^32 - 1");
+    auto p = std::make_shared<Payload>();
+    p->cfg = *cfg;
+    p->fx = fx;
+    p->device_init = true;
+    p->nave = nave;
+    p->amp = amp;
+    p->init_seed = init_seed;
     std::unique_ptr<Req> r(new Req);
     r->q = cfg->q;
     r->total = nsteps;

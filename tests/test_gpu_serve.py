@@ -148,3 +148,35 @@ def test_request_stream_replay(ilg):
             np.testing.assert_array_equal(
                 got, _alone(ilg, dict(m, t0=0), pool.init(i, m["q"], m["length"]), ns))
     srv.close()
+
+
+def test_device_drawn_initial_states(ilg, oracle_lib):
+    """Requests whose Poisson sine initial state is drawn on the device at
+    admission (no host state) end exactly where the oracle's draw of that
+    state, stepped by the oracle, ends; mixed with host-state requests."""
+    from oracle import oracle as O
+    cases = [dict(q=3, length=320, count_bytes=2, omega=1.6, seed=31, realization=4, t0=0),
+             dict(q=2, length=5000, count_bytes=4, omega=1.2, seed=32, realization=0, t0=9),
+             dict(q=3, length=1025, count_bytes=4, omega=0.8, seed=33, realization=7, t0=0)]
+    draws = [(100.0, 100.0, 5), (40.0, 15.0, 6), (300.0, 200.0, 7)]
+    steps = [120, 45, 77]
+    srv = ilg.Server(32 << 20, quantum_steps=25)
+    ids = []
+    for m, (nave, amp, s), ns in zip(cases, draws, steps):
+        ids.append(srv.submit_poisson_sine(m, nave, amp, s, ns))
+        m2 = dict(m, seed=m["seed"] + 100)
+        srv.submit(m2, W.init_poisson_iid(m["q"], m["length"], 30.0, m["count_bytes"], 3), ns)
+    for _ in range(1000):
+        st = srv.poll()
+        if st["active"] == 0 and st["queued"] == 0:
+            break
+    for rid, m, (nave, amp, s), ns in zip(ids, cases, draws, steps):
+        assert srv.info(rid)["state"] == "done"
+        got = srv.result(rid)
+        init, ov = O.init_poisson_sine(m["q"], m["count_bytes"], m["length"], nave, amp, s,
+                                       realization=m["realization"])
+        assert not ov
+        want, _, _ = oracle_lib.run(oracle_lib.Params(m["q"], m["omega"]), init, ns,
+                                    seed=m["seed"], realization=m["realization"], t0=m["t0"])
+        np.testing.assert_array_equal(got, want)
+    srv.close()
