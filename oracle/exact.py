@@ -34,12 +34,16 @@ TABLE_ENTRIES = CHUNK * (CHUNK + 1) // 2  # rows m = 1..64, m entries each
 # --------------------------------------------------------------- parameters
 
 def velocities(q: int) -> np.ndarray:
-    """Index order of the velocity sets: D1Q2 (-1, +1), D1Q3 (-1, 0, +1)."""
+    """Index order of the velocity sets: D1Q2 (-1, +1), D1Q3 (-1, 0, +1);
+    D2Q5 as rows (vx, vy): (-1,0), (0,-1), (0,0), (0,+1), (+1,0), so that the
+    mirror -v_i of index i is index q-1-i in every set."""
     if q == 2:
         return np.array([-1, 1], dtype=np.int64)
     if q == 3:
         return np.array([-1, 0, 1], dtype=np.int64)
-    raise ValueError("q must be 2 or 3")
+    if q == 5:
+        return np.array([[-1, 0], [0, -1], [0, 0], [0, 1], [1, 0]], dtype=np.int64)
+    raise ValueError("q must be 2, 3 or 5")
 
 
 def weights(q: int, theta: float = 1.0 / 3.0) -> np.ndarray:
@@ -49,22 +53,31 @@ def weights(q: int, theta: float = 1.0 / 3.0) -> np.ndarray:
     Eq. transform is orthonormal in the Hermite norm for any theta."""
     if q == 2:
         return np.array([0.5, 0.5])
+    if q == 5:
+        # D2Q5 (reading: the paper works the flip out in 1D; the 2D set takes
+        # the same isotropic second moment theta = sum_i w_i v_ix^2 = sum_i w_i v_iy^2)
+        return np.array([theta / 2.0, theta / 2.0, 1.0 - 2.0 * theta, theta / 2.0, theta / 2.0])
     return np.array([theta / 2.0, 1.0 - theta, theta / 2.0])
 
 
 def theta_of(q: int, theta: float = 1.0 / 3.0) -> float:
-    """theta = sum_i w_i v_i^2 (Eq. Thetadef)."""
-    return float(np.sum(weights(q, theta) * velocities(q) ** 2))
+    """theta = sum_i w_i v_i^2 (Eq. Thetadef); for D2Q5 the x component."""
+    v = velocities(q)
+    if v.ndim == 2:
+        v = v[:, 0]
+    return float(np.sum(weights(q, theta) * v ** 2))
 
 
-def fixed_point_params(omega: float, theta: float = 1.0 / 3.0, flip: str = "auto") -> Dict:
+def fixed_point_params(omega: float, theta: float = 1.0 / 3.0, flip: str = "auto",
+                       q: int = 3) -> Dict:
     """Collision parameters for a target relaxation rate omega (= omega^j).
 
     flip == "auto": the flip is applied iff omega > 1 (over-relaxation); then
     the collision fraction is omega* = 2 - omega (Eq. omegaj), otherwise
     omega* = omega (plain Seekins collision, omega <= 1).  "on"/"off" force it.
     P = round-half-even(omega* 2^32), the removal probability in 32-bit fixed
-    point; P_half = 2^31; P_rest = round-half-even((1 - theta) 2^32)."""
+    point; P_half = 2^31; P_rest = round-half-even(w_rest 2^32), the rest
+    weight: 1 - theta (D1Q3) or 1 - 2 theta (D2Q5, theta < 1/2)."""
     if not (0.0 < omega <= 2.0):
         raise ValueError("omega must lie in (0, 2]")
     if flip == "auto":
@@ -81,9 +94,14 @@ def fixed_point_params(omega: float, theta: float = 1.0 / 3.0, flip: str = "auto
         raise ValueError("flip must be auto, on or off")
     omega_star = (2.0 - omega) if do_flip else omega
     P = round(omega_star * float(TWO32))   # Python rounds floats half-to-even
-    if not (0.0 < theta < 1.0):
-        raise ValueError("theta must lie in (0, 1)")
-    P_rest = round((1.0 - theta) * float(TWO32))
+    if q == 5:
+        if not (0.0 < theta < 0.5):
+            raise ValueError("D2Q5 theta must lie in (0, 1/2)")
+        P_rest = round((1.0 - 2.0 * theta) * float(TWO32))
+    else:
+        if not (0.0 < theta < 1.0):
+            raise ValueError("theta must lie in (0, 1)")
+        P_rest = round((1.0 - theta) * float(TWO32))
     return dict(flip=do_flip, omega_star=omega_star, P=int(P), P_half=1 << 31, P_rest=int(P_rest))
 
 
@@ -324,6 +342,43 @@ def lb_run(f0: np.ndarray, q: int, omega_star: float, flip: bool, steps: int,
         snaps.append(f.copy())
         return f, snaps
     return f
+
+
+def lb_step_flip_2d(f: np.ndarray, omega_star: float, flip: bool,
+                    theta: float = 1.0 / 3.0) -> np.ndarray:
+    """D2Q5 Boltzmann average with flip, f of shape [5][Ly][Lx] (periodic):
+    a = F[f] (a_i = f_{4-i}), post = a + omega* (w_i rho - a), then
+    f_i(x + v_i) = post_i(x)."""
+    w = weights(5, theta)
+    a = f[::-1].copy() if flip else f.copy()
+    rho = a.sum(axis=0)
+    post = a + omega_star * (w[:, None, None] * rho[None] - a)
+    out = np.empty_like(post)
+    for i, (vx, vy) in enumerate(velocities(5)):
+        out[i] = np.roll(np.roll(post[i], int(vx), axis=1), int(vy), axis=0)
+    return out
+
+
+def lb_mode_matrix_2d(kx: float, ky: float, omega_star: float, flip: bool,
+                      theta: float = 1.0 / 3.0) -> np.ndarray:
+    """One D2Q5 step on a plane wave f_i(x) = g_i exp(i k.x): the collision
+    ((1 - omega*) I + omega* w 1^T) after the flip permutation, then streaming,
+    which multiplies component i by exp(-i k.v_i)."""
+    w = weights(5, theta)
+    Pm = np.eye(5)[::-1] if flip else np.eye(5)
+    C = (1.0 - omega_star) * np.eye(5) + omega_star * np.outer(w, np.ones(5))
+    v = velocities(5)
+    S = np.diag(np.exp(-1j * (kx * v[:, 0] + ky * v[:, 1])))
+    return S @ C @ Pm
+
+
+def lb_slow_rate_2d(kx: float, ky: float, omega_star: float, flip: bool,
+                    theta: float = 1.0 / 3.0) -> float:
+    """-log |lambda| of the eigenvalue of lb_mode_matrix_2d closest to 1 (the
+    density mode)."""
+    ev = np.linalg.eigvals(lb_mode_matrix_2d(kx, ky, omega_star, flip, theta))
+    lam = ev[np.argmin(np.abs(ev - 1.0))]
+    return float(-math.log(abs(lam)))
 
 
 def lb_operator(q: int, length: int, omega_star: float, flip: bool,

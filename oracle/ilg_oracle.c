@@ -27,6 +27,13 @@
  *   supplied by the caller (built with exact big integers in exact.py).
  *   p = 0 is passed as a NULL table: the result is 0 but the draws are still
  *   consumed, so draw alignment does not depend on p.
+ * D2Q5 (reading; the paper works the flip out in 1D and states that odd
+ * moments change sign and even moments do not): velocities (-1,0), (0,-1),
+ * (0,0), (0,+1), (+1,0), weights theta/2 for each mover and 1 - 2 theta at
+ * rest; the collided particles go to rest with probability 1 - 2 theta, the
+ * others to the x or the y pair with probability 1/2 and then to either
+ * direction of the pair with probability 1/2 (conditional binomials, drawn
+ * in that order).  Nodes are numbered x + Lx y.
  * Draws: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11), key = the 64-bit
  * seed split into two 32-bit words (low word first), counter =
  * (node x, step t, realization r, block b).  Draw number j of a node-step is
@@ -131,27 +138,29 @@ static uint64_t binomial(uint64_t n, const uint32_t *table, draw_stream *s)
 /* ------------------------------------------------------------ node update */
 
 typedef struct {
-    int q;                     /* 2: v = (-1,+1); 3: v = (-1,0,+1) */
+    int q;                     /* 2: v = (-1,+1); 3: v = (-1,0,+1);
+                                  5 (D2Q5): v = (-1,0), (0,-1), (0,0), (0,+1), (+1,0) */
     int flip;                  /* apply F before the collision */
     const uint32_t *tab_p;     /* removal fraction P (NULL: P = 0) */
     const uint32_t *tab_half;  /* P = 2^31 */
-    const uint32_t *tab_rest;  /* P = (1 - theta) 2^32, Q = 3 only */
+    const uint32_t *tab_rest;  /* rest weight: P = (1 - theta) 2^32 for q = 3,
+                                  (1 - 2 theta) 2^32 for q = 5 */
     uint64_t seed;
     uint32_t realization;
 } oracle_params;
 
 /* One node: flip, then removal binomials, then multinomial redistribution.
  * Returns the post-collision counts c_i = a_i - k_i + m_i (before streaming). */
-static void collide_node(const oracle_params *pp, const uint64_t n_in[3], uint32_t x, uint32_t t,
-                         uint64_t c_out[3])
+static void collide_node(const oracle_params *pp, const uint64_t n_in[5], uint32_t x, uint32_t t,
+                         uint64_t c_out[5])
 {
     const int q = pp->q;
-    uint64_t a[3] = {0, 0, 0}, k[3] = {0, 0, 0}, m[3] = {0, 0, 0};
+    uint64_t a[5] = {0, 0, 0, 0, 0}, k[5] = {0, 0, 0, 0, 0}, m[5] = {0, 0, 0, 0, 0};
     draw_stream s;
     stream_init(&s, pp->seed, x, t, pp->realization);
 
-    /* Flip, Eq. flip: a_i = n_{-i}; with index order (-1, [0,] +1) the mirror
-     * of index i is q-1-i. */
+    /* Flip, Eq. flip: a_i = n_{-i}; with the index orders above the mirror
+     * of index i is q-1-i (in 2D: -x <-> +x, -y <-> +y, rest fixed). */
     for (int i = 0; i < q; ++i)
         a[i] = pp->flip ? n_in[q - 1 - i] : n_in[i];
 
@@ -166,11 +175,23 @@ static void collide_node(const oracle_params *pp, const uint64_t n_in[3], uint32
     if (q == 2) {
         m[0] = binomial(M, pp->tab_half, &s);   /* w_- = 1/2 */
         m[1] = M - m[0];
-    } else {
+    } else if (q == 3) {
         m[1] = binomial(M, pp->tab_rest, &s);   /* w_0 = 1 - theta */
         uint64_t R = M - m[1];
         m[0] = binomial(R, pp->tab_half, &s);   /* w_- / (w_- + w_+) = 1/2 */
         m[2] = R - m[0];
+    } else {
+        /* D2Q5 weights: rest 1 - 2 theta, each mover theta / 2.  The movers
+         * split into the x pair and the y pair (1/2 each), each pair into its
+         * negative and positive direction (1/2 each). */
+        m[2] = binomial(M, pp->tab_rest, &s);   /* w_0 = 1 - 2 theta */
+        uint64_t R = M - m[2];
+        uint64_t mx = binomial(R, pp->tab_half, &s);
+        uint64_t my = R - mx;
+        m[0] = binomial(mx, pp->tab_half, &s);  /* -x */
+        m[4] = mx - m[0];                       /* +x */
+        m[1] = binomial(my, pp->tab_half, &s);  /* -y */
+        m[3] = my - m[1];                       /* +y */
     }
     for (int i = 0; i < q; ++i)
         c_out[i] = a[i] - k[i] + m[i];
@@ -213,7 +234,7 @@ static void *step_worker(void *arg)
     const int q = job->pp->q;
     const uint64_t maxval = job->count_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu;
     for (uint64_t w = job->w_begin; w < job->w_end; ++w) {
-        uint64_t n[3] = {0, 0, 0}, c[3];
+        uint64_t n[5] = {0, 0, 0, 0, 0}, c[5];
         for (int i = 0; i < q; ++i)
             n[i] = load_count(job->in, job->count_bytes, (size_t)i * job->width + w);
         uint32_t xg = (uint32_t)((job->x0 + w) % job->length);
@@ -272,6 +293,76 @@ int oracle_step(int q, int count_bytes, uint64_t length, uint64_t x0, uint64_t w
     return overflow;
 }
 
+/* ------------------------------------------------------- D2Q5 lattice step */
+
+/* One whole-lattice D2Q5 step on an Lx x Ly periodic lattice; state layout
+ * [5][Ly][Lx] (node index x + Lx y, which is also the Philox counter word 0).
+ * Velocity i moves to (x + vx_i mod Lx, y + vy_i mod Ly). */
+typedef struct {
+    const oracle_params *pp;
+    int count_bytes;
+    uint64_t lx, ly;
+    const void *in;
+    void *out;
+    uint32_t t;
+    uint64_t n_begin, n_end;
+    int overflow;
+} step2d_job;
+
+static void *step2d_worker(void *arg)
+{
+    step2d_job *job = (step2d_job *)arg;
+    static const int vx[5] = {-1, 0, 0, 0, 1}, vy[5] = {0, -1, 0, 1, 0};
+    const uint64_t nodes = job->lx * job->ly;
+    const uint64_t maxval = job->count_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu;
+    for (uint64_t id = job->n_begin; id < job->n_end; ++id) {
+        const uint64_t x = id % job->lx, y = id / job->lx;
+        uint64_t n[5], c[5];
+        for (int i = 0; i < 5; ++i)
+            n[i] = load_count(job->in, job->count_bytes, (size_t)i * nodes + id);
+        collide_node(job->pp, n, (uint32_t)id, job->t, c);
+        for (int i = 0; i < 5; ++i) {
+            const uint64_t xd = (x + job->lx + (uint64_t)(int64_t)vx[i]) % job->lx;
+            const uint64_t yd = (y + job->ly + (uint64_t)(int64_t)vy[i]) % job->ly;
+            if (c[i] > maxval)
+                job->overflow = 1;
+            store_count(job->out, job->count_bytes, (size_t)i * nodes + xd + job->lx * yd, c[i]);
+        }
+    }
+    return NULL;
+}
+
+int oracle_step2d(int count_bytes, uint64_t lx, uint64_t ly, int flip, const uint32_t *tab_p,
+                  const uint32_t *tab_half, const uint32_t *tab_rest, uint64_t seed,
+                  uint32_t realization, uint32_t t, const void *in, void *out, int nthreads)
+{
+    oracle_params pp = {5, flip, tab_p, tab_half, tab_rest, seed, realization};
+    const uint64_t nodes = lx * ly;
+    if (nthreads < 1)
+        nthreads = 1;
+    if ((uint64_t)nthreads > nodes)
+        nthreads = (int)nodes;
+    step2d_job *jobs = (step2d_job *)calloc((size_t)nthreads, sizeof(step2d_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    for (int k = 0; k < nthreads; ++k) {
+        step2d_job j = {&pp, count_bytes, lx, ly, in, out, t,
+                        nodes * (uint64_t)k / (uint64_t)nthreads,
+                        nodes * (uint64_t)(k + 1) / (uint64_t)nthreads, 0};
+        jobs[k] = j;
+    }
+    for (int k = 1; k < nthreads; ++k)
+        pthread_create(&th[k], NULL, step2d_worker, &jobs[k]);
+    step2d_worker(&jobs[0]);
+    for (int k = 1; k < nthreads; ++k)
+        pthread_join(th[k], NULL);
+    int overflow = 0;
+    for (int k = 0; k < nthreads; ++k)
+        overflow |= jobs[k].overflow;
+    free(jobs);
+    free(th);
+    return overflow;
+}
+
 /* ------------------------------------------------------------------ hash */
 
 static uint64_t splitmix64(uint64_t z)
@@ -318,6 +409,28 @@ int oracle_run(int q, int count_bytes, uint64_t length, int flip, const uint32_t
     return overflow;
 }
 
+/* nsteps whole-lattice D2Q5 steps from absolute step t0, `state` [5][Ly][Lx]
+ * updated in place; hashes[s] (if not NULL) is the hash after step s+1 (node
+ * index x + Lx y).  Returns 1 on count overflow. */
+int oracle_run2d(int count_bytes, uint64_t lx, uint64_t ly, int flip, const uint32_t *tab_p,
+                 const uint32_t *tab_half, const uint32_t *tab_rest, uint64_t seed,
+                 uint32_t realization, uint64_t t0, uint64_t nsteps, void *state,
+                 uint64_t *hashes, int nthreads)
+{
+    const size_t bytes = (size_t)5 * lx * ly * (size_t)count_bytes;
+    void *tmp = malloc(bytes);
+    int overflow = 0;
+    for (uint64_t s = 0; s < nsteps; ++s) {
+        overflow |= oracle_step2d(count_bytes, lx, ly, flip, tab_p, tab_half, tab_rest, seed,
+                                  realization, (uint32_t)(t0 + s), state, tmp, nthreads);
+        memcpy(state, tmp, bytes);
+        if (hashes)
+            hashes[s] = oracle_hash(5, count_bytes, lx * ly, state);
+    }
+    free(tmp);
+    return overflow;
+}
+
 /* Window run for light-cone sampling: `state` holds [q][width] counts of the
  * global nodes x0 .. x0+width-1 (mod length) at step t0; after nsteps steps the
  * nodes [nsteps, width-nsteps) hold the exact state of those global nodes. */
@@ -347,7 +460,7 @@ void oracle_collide_node(int q, int flip, const uint32_t *tab_p, const uint32_t 
                          uint32_t x, uint32_t t, const uint64_t *n_in, uint64_t *c_out)
 {
     oracle_params pp = {q, flip, tab_p, tab_half, tab_rest, seed, realization};
-    uint64_t n[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+    uint64_t n[5] = {0, 0, 0, 0, 0}, c[5] = {0, 0, 0, 0, 0};
     for (int i = 0; i < q; ++i)
         n[i] = n_in[i];
     collide_node(&pp, n, x, t, c);
@@ -361,11 +474,11 @@ void oracle_collide_samples(int q, int flip, const uint32_t *tab_p, const uint32
                             uint32_t t, const uint64_t *n_in, uint64_t nsamples, uint64_t *c_out)
 {
     oracle_params pp = {q, flip, tab_p, tab_half, tab_rest, seed, realization};
-    uint64_t n[3] = {0, 0, 0};
+    uint64_t n[5] = {0, 0, 0, 0, 0};
     for (int i = 0; i < q; ++i)
         n[i] = n_in[i];
     for (uint64_t s = 0; s < nsamples; ++s) {
-        uint64_t c[3] = {0, 0, 0};
+        uint64_t c[5] = {0, 0, 0, 0, 0};
         collide_node(&pp, n, (uint32_t)s, t, c);
         for (int i = 0; i < q; ++i)
             c_out[s * (uint64_t)q + (uint64_t)i] = c[i];

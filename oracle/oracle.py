@@ -75,6 +75,10 @@ def lib():
         L.oracle_binomial_samples.argtypes = [ctypes.c_uint64, vp, ctypes.c_uint64,
                                               ctypes.c_uint64, vp]
         L.oracle_binomial_samples.restype = None
+        L.oracle_run2d.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                   vp, vp, vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                   ctypes.c_uint64, vp, vp, ctypes.c_int]
+        L.oracle_run2d.restype = ctypes.c_int
         L.oracle_sin2pi_frac.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.oracle_sin2pi_frac.restype = ctypes.c_double
         L.oracle_exp_neg.argtypes = [ctypes.c_double]
@@ -102,13 +106,13 @@ class Params:
         self.q = q
         self.omega = omega
         self.theta = theta
-        fp = exact.fixed_point_params(omega, theta, flip)
+        fp = exact.fixed_point_params(omega, theta, flip, q=q)
         self.flip = fp["flip"]
         self.omega_star = fp["omega_star"]
         self.P, self.P_half, self.P_rest = fp["P"], fp["P_half"], fp["P_rest"]
         self.tab_p = exact.binomial_table(self.P)
         self.tab_half = _cached_table(self.P_half)
-        self.tab_rest = _cached_table(self.P_rest) if q == 3 else None
+        self.tab_rest = _cached_table(self.P_rest) if q in (3, 5) else None
 
 
 _table_cache = {}
@@ -131,9 +135,11 @@ def philox(ctr, key) -> np.ndarray:
 
 
 def state_hash(state: np.ndarray) -> int:
-    q, L = state.shape
+    """Hash of a [q][L] state, or of a D2Q5 [5][Ly][Lx] state with node
+    index x + Lx y."""
+    q = state.shape[0]
     s = np.ascontiguousarray(state)
-    return int(lib().oracle_hash(q, s.dtype.itemsize, L, _ptr(s)))
+    return int(lib().oracle_hash(q, s.dtype.itemsize, s.size // q, _ptr(s)))
 
 
 def run(params: Params, state: np.ndarray, nsteps: int, seed: int, realization: int = 0,
@@ -146,6 +152,20 @@ def run(params: Params, state: np.ndarray, nsteps: int, seed: int, realization: 
     ov = lib().oracle_run(q, s.dtype.itemsize, L, int(params.flip), _ptr(params.tab_p),
                           _ptr(params.tab_half), _ptr(params.tab_rest), seed, realization, t0,
                           nsteps, _ptr(s), _ptr(hs), nthreads or default_threads())
+    return s, (hs[:nsteps] if hashes else None), bool(ov)
+
+
+def run2d(params: Params, state: np.ndarray, nsteps: int, seed: int, realization: int = 0,
+          t0: int = 0, hashes: bool = False, nthreads: Optional[int] = None):
+    """Advance a periodic D2Q5 lattice, state [5][Ly][Lx]; returns
+    (new_state, hashes or None, overflow).  Node index x + Lx y."""
+    s = np.array(state, copy=True, order="C")
+    q, ly, lx = s.shape
+    assert q == 5 and params.q == 5
+    hs = np.zeros(max(nsteps, 1), dtype=np.uint64) if hashes else None
+    ov = lib().oracle_run2d(s.dtype.itemsize, lx, ly, int(params.flip), _ptr(params.tab_p),
+                            _ptr(params.tab_half), _ptr(params.tab_rest), seed, realization, t0,
+                            nsteps, _ptr(s), _ptr(hs), nthreads or default_threads())
     return s, (hs[:nsteps] if hashes else None), bool(ov)
 
 
@@ -164,7 +184,7 @@ def run_window(params: Params, window: np.ndarray, length: int, x0: int, nsteps:
 
 def collide_samples(params: Params, n_in, nsamples: int, seed: int, realization: int = 0,
                     t: int = 0) -> np.ndarray:
-    n = np.zeros(3, dtype=np.uint64)
+    n = np.zeros(5, dtype=np.uint64)
     n[:params.q] = n_in
     out = np.zeros((nsamples, params.q), dtype=np.uint64)
     lib().oracle_collide_samples(params.q, int(params.flip), _ptr(params.tab_p),
