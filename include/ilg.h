@@ -2,7 +2,9 @@
  * ilg.h -- C ABI of the MI355X (gfx950) diffusive integer lattice gas library.
  *
  * The library advances integer occupation numbers n_i(x, t) of a periodic 1D
- * lattice by the lattice-gas evolution with the flip operator of Strand &
+ * lattice (D1Q2, D1Q3) or 2D lattice (D2Q5, an extension by the paper's
+ * general rule that the flip changes the sign of odd velocity moments only)
+ * by the lattice-gas evolution with the flip operator of Strand &
  * Wagner, "Over-Relaxation in Diffusive Integer Lattice Gas":
  *   n_i(x + v_i, t + 1) = F_i(n) + Xi_i({F(n)})            (Eq. LGflip)
  * where F_i(n) = n_{-i} (Eq. flip) and Xi is the sampling collision of the
@@ -60,22 +62,29 @@ typedef enum ilg_status {
 #define ILG_FLIP_MASK 3u
 
 /* One lattice run.  Velocity index order is fixed: q = 2 -> v = (-1, +1),
- * q = 3 -> v = (-1, 0, +1).  Weights: (1/2, 1/2) and (theta/2, 1-theta,
- * theta/2); theta is the second velocity moment of the weights
- * (Eq. Thetadef) and D1Q3 uses the transformation matrix of Eq. transform. */
+ * q = 3 -> v = (-1, 0, +1), q = 5 -> v = (-1,0), (0,-1), (0,0), (0,+1),
+ * (+1,0); the mirror -v_i of index i is always index q-1-i.  Weights:
+ * (1/2, 1/2), (theta/2, 1-theta, theta/2) and (theta/2, theta/2, 1-2 theta,
+ * theta/2, theta/2); theta is the second velocity moment of the weights
+ * (Eq. Thetadef, per axis in 2D) and D1Q3 uses the transformation matrix of
+ * Eq. transform.  A D2Q5 lattice has length x height nodes numbered
+ * x + length y; the collided particles go to rest with probability
+ * 1 - 2 theta, else to the x or y pair (1/2 each), then to either direction
+ * (1/2 each). */
 typedef struct ilg_config {
     uint32_t abi_version; /* ILG_ABI_VERSION */
-    uint32_t q;           /* 2 or 3 */
+    uint32_t q;           /* 2, 3 or 5 */
     uint32_t count_bytes; /* 2 (uint16 counts) or 4 (uint32 counts) */
     uint32_t flags;       /* ILG_FLIP_* */
-    uint64_t length;      /* L, 1 <= L < 2^31, periodic */
+    uint64_t length;      /* L (1D) or Lx (D2Q5), periodic; nodes < 2^31 */
     double omega;         /* target rate omega^j in (0, 2]; with the flip the
                              collision fraction is omega* = 2 - omega, else
                              omega* = omega (Over-relaxation section) */
-    double theta;         /* q = 3 only, in (0, 1); 0 selects 1/3 */
+    double theta;         /* q = 3: in (0, 1); q = 5: in (0, 1/2); 0 selects
+                             1/3; ignored for q = 2 */
     uint64_t seed;        /* Philox key (low word, high word) */
     uint32_t realization; /* Philox counter word 2 */
-    uint32_t reserved;    /* must be 0 */
+    uint32_t height;      /* D2Q5: Ly >= 1 (periodic); must be 0 for q = 2, 3 */
     uint64_t t0;          /* absolute index of the first step to take */
 } ilg_config;
 
@@ -85,7 +94,8 @@ typedef struct ilg_fixed {
     uint32_t q;
     uint64_t p;        /* round-half-even(omega* 2^32), in [0, 2^32] */
     uint64_t p_half;   /* 2^31 */
-    uint64_t p_rest;   /* round-half-even((1 - theta) 2^32), q = 3 */
+    uint64_t p_rest;   /* round-half-even(w_rest 2^32): 1 - theta (q = 3),
+                          1 - 2 theta (q = 5) */
     double omega_star;
 } ilg_fixed;
 
@@ -94,10 +104,12 @@ typedef struct ilg_summary {
     uint64_t mass;      /* sum over x, i of n_i(x) (exact) */
     uint64_t step;      /* absolute step index of the state */
     uint64_t hash;      /* sum of splitmix64(((x q + i) << 32) ^ n_i(x)) mod 2^64 */
-    double amplitude;   /* A^LG = sum_x sin(2 pi x/L) N(x) / sum_x sin^2(2 pi x/L) */
+    double amplitude;   /* A^LG = sum_x sin(2 pi x/L) N(x) / sum_x sin^2(2 pi x/L);
+                           D2Q5: sums over all nodes with x the column */
     uint32_t nk;        /* number of S(k) values filled */
     uint32_t reserved;
-    double sk[ILG_MAX_K]; /* S(k) = |sum_x N(x) e^{-2 pi i k x/L}|^2 / sum_x N(x), k = 1..nk */
+    double sk[ILG_MAX_K]; /* S(k) = |sum_x N(x) e^{-2 pi i k x/L}|^2 / sum_x N(x), k = 1..nk
+                             (D2Q5: modes along x, sums over all nodes) */
 } ilg_summary;
 
 typedef struct ilg_handle ilg_handle; /* opaque; owned by the library */
@@ -114,12 +126,14 @@ int ilg_fixed_point(const ilg_config *cfg, ilg_fixed *out);
 int ilg_binomial_table(uint64_t p, uint32_t *out);
 
 /* Device layout of a lattice state: velocity-major [q][pitch] counts of
- * count_bytes each, pitch = L rounded up to a multiple of 64; entries
- * beyond L are padding and never read.  Returns the byte size. */
+ * count_bytes each over the nodes (L, or Lx Ly for D2Q5, node x + Lx y),
+ * pitch = the node count rounded up to a multiple of 64; entries beyond the
+ * last node are padding and never read.  Returns the byte size. */
 uint64_t ilg_state_bytes(const ilg_config *cfg);
 uint64_t ilg_state_pitch(const ilg_config *cfg);
 
-/* Create a lattice; init_host is [q][L] counts (compact, count_bytes each),
+/* Create a lattice; init_host is [q][nodes] counts (compact, count_bytes
+ * each; D2Q5 [5][Ly][Lx]),
  * copied before return, or NULL for an all-zero state (to be replaced by
  * ilg_init_poisson_sine).  Device buffers are owned by the handle. */
 int ilg_create(const ilg_config *cfg, const void *init_host, void *stream, ilg_handle **out);
@@ -139,14 +153,14 @@ int ilg_step(ilg_handle *h, uint64_t nsteps);
 /* Copy the current state to host [q][L] (compact).  Syncs. */
 int ilg_get_state(ilg_handle *h, void *host_out);
 
-/* Replace the state by host [q][L] counts and set the absolute step index of
+/* Replace the state by host [q][nodes] counts and set the absolute step index of
  * the next step to t (checkpoint restore).  Syncs. */
 int ilg_set_state(ilg_handle *h, const void *host_in, uint64_t t);
 
 /* Replace the state by the paper's Poisson sine initial condition drawn on
  * the device (Results section, the sinusoidal initial density with integer
- * occupations): n_i(x) ~ Poisson(w_i (nave + amp sin(2 pi x / L))), weights
- * (1/2, 1/2) for q = 2 and (theta/2, 1 - theta, theta/2) for q = 3, drawn
+ * occupations): n_i(x) ~ Poisson(w_i (nave + amp sin(2 pi x / L))) with the
+ * configuration's weights (D2Q5: the profile along x, x the column), drawn
  * with Philox4x32-10 keyed by init_seed (independent of the step seed) and
  * the configuration's realization.  The arithmetic is fixed ("init v1":
  * correctly rounded double operations only, no library transcendental), so
@@ -157,9 +171,10 @@ int ilg_set_state(ilg_handle *h, const void *host_in, uint64_t t);
  * cleared.  Syncs. */
 int ilg_init_poisson_sine(ilg_handle *h, double nave, double amp, uint64_t init_seed);
 
-/* Reductions of the current state (device kernels, then a small copy)./* Reductions of the current state (device kernels, then a small copy).
- * rho, j, e: optional host arrays of L int64 receiving the per-node raw
- * moments sum_i n_i, sum_i v_i n_i, sum_i v_i^2 n_i (NULL to skip).
+/* Reductions of the current state (device kernels, then a small copy).
+ * rho, j, e: optional host arrays of one int64 per node receiving the raw
+ * moments sum_i n_i, sum_i v_i n_i, sum_i v_i^2 n_i (D2Q5: the x component
+ * v_ix in j, |v_i|^2 in e) (NULL to skip).
  * nk <= ILG_MAX_K structure-factor modes are computed.  Syncs. */
 int ilg_moments(ilg_handle *h, int64_t *rho, int64_t *j, int64_t *e, uint32_t nk,
                 ilg_summary *out);
@@ -196,7 +211,8 @@ typedef struct ilg_batch_diag {
 } ilg_batch_diag;
 
 /* cfgs[nreal] and inits[nreal] (host [q][L_r] compact counts, copied before
- * return).  diag may be NULL (no diagnostics). */
+ * return).  diag may be NULL (no diagnostics).  q = 2 or 3 (D2Q5 runs in
+ * the plain form only: ILG_E_INVALID). */
 int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *inits,
                      const ilg_batch_diag *diag, void *stream, ilg_batch **out);
 
@@ -270,8 +286,8 @@ double ilg_server_clock(void);
  * requests by up to quantum_steps steps. */
 int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server **out);
 
-/* Queue a request: cfg, host [q][L] initial counts (copied), nsteps > 0.
- * ILG_E_BUSY if it can never fit the budget. */
+/* Queue a request: cfg (q = 2 or 3), host [q][L] initial counts (copied),
+ * nsteps > 0.  ILG_E_BUSY if it can never fit the budget. */
 int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_host,
                       uint64_t nsteps, uint64_t *id);
 

@@ -518,12 +518,15 @@ void oracle_binomial_samples(uint64_t n, const uint32_t *table, uint64_t seed, u
  *     times 2^-n;
  *   mean = w_i * (N + A * value); mean <= 0 gives 0;
  *   parts P = max(1, ceil(mean / 256)), m = mean / P, and per part p a Philox
- *   block with key = init seed, counter = (x, p, realization, 2^31); word i
- *   is the part's draw u, U = (u + 1/2) 2^-32, and the part's count is the
+ *   block with key = init seed, counter = (x, p, realization, 2^31 + i / 4);
+ *   word i mod 4 is the part's draw u, U = (u + 1/2) 2^-32, and the part's
+ *   count is the
  *   least k with U <= F(k), F(0) = f(0) = e^-m, f(k) = (f(k-1) m) / k,
  *   F(k) = F(k-1) + f(k) (the Poisson CDF by its recurrence), capped at 10^5;
  *   n_i(x) = the sum over the parts (a sum of independent Poisson(m) is
  *   Poisson(mean)).
+ * D2Q5: nodes x + Lx y; the profile runs along the column x = node mod Lx
+ * (sine of the column), the counter's word 0 is the node.
  * Coefficients 1/j! are 1.0 / j! with j! exact in double (j <= 18).  The
  * counter's last word 2^31 keeps these blocks apart from the step's draw
  * blocks (whose last word is a small block index). */
@@ -597,10 +600,11 @@ static uint64_t poisson_part(double m, uint32_t u)
     return k;
 }
 
-/* Counts of nodes x0 .. x0+width-1 (taken mod L) into out[q][width] (count
- * type count_bytes); weights w[0..q-1].  Returns 1 if a count exceeds the
- * count type (the stored value is then truncated), else 0. */
-int oracle_init_poisson_sine(int q, int count_bytes, uint64_t length, uint64_t x0,
+/* Counts of nodes x0 .. x0+width-1 (taken mod the node count `length`) into
+ * out[q][width] (count type count_bytes); weights w[0..q-1]; row length
+ * `row` (the profile's period: L in 1D, Lx for D2Q5).  Returns 1 if a count
+ * exceeds the count type (the stored value is then truncated), else 0. */
+int oracle_init_poisson_sine(int q, int count_bytes, uint64_t length, uint64_t row, uint64_t x0,
                              uint64_t width, const double *w, double nave, double amp,
                              uint64_t seed, uint32_t realization, void *out)
 {
@@ -609,7 +613,7 @@ int oracle_init_poisson_sine(int q, int count_bytes, uint64_t length, uint64_t x
     int overflow = 0;
     for (uint64_t k = 0; k < width; ++k) {
         const uint64_t x = (x0 + k) % length;
-        const double s = oracle_sin2pi_frac(x, length);
+        const double s = oracle_sin2pi_frac(x % row, row);
         const double rho = nave + amp * s;
         for (int i = 0; i < q; ++i) {
             const double mean = w[i] * rho;
@@ -619,10 +623,11 @@ int oracle_init_poisson_sine(int q, int count_bytes, uint64_t length, uint64_t x
                 const uint32_t parts = parts_d < 1.0 ? 1u : (uint32_t)parts_d;
                 const double m = mean / (double)parts;
                 for (uint32_t p = 0; p < parts; ++p) {
-                    const uint32_t ctr[4] = {(uint32_t)x, p, realization, 0x80000000u};
+                    const uint32_t ctr[4] = {(uint32_t)x, p, realization,
+                                             0x80000000u + (uint32_t)(i / 4)};
                     uint32_t blk[4];
                     oracle_philox4x32_10(ctr, key, blk);
-                    n += poisson_part(m, blk[i]);
+                    n += poisson_part(m, blk[i % 4]);
                 }
             }
             if (n > maxv)

@@ -84,7 +84,8 @@ def lib():
         L.oracle_exp_neg.argtypes = [ctypes.c_double]
         L.oracle_exp_neg.restype = ctypes.c_double
         L.oracle_init_poisson_sine.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
-                                               ctypes.c_uint64, ctypes.c_uint64, vp,
+                                               ctypes.c_uint64, ctypes.c_uint64,
+                                               ctypes.c_uint64, vp,
                                                ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                                                ctypes.c_uint32, vp]
         L.oracle_init_poisson_sine.restype = ctypes.c_int
@@ -201,22 +202,32 @@ def binomial_samples(n: int, table: Optional[np.ndarray], nsamples: int, seed: i
 
 def init_weights(q: int, theta: float = 1.0 / 3.0) -> np.ndarray:
     """Velocity weights of the initial means: D1Q2 (1/2, 1/2); D1Q3
-    (theta/2, 1 - theta, theta/2), each one double operation."""
+    (theta/2, 1 - theta, theta/2); D2Q5 (theta/2, theta/2, 1 - 2 theta,
+    theta/2, theta/2), each one double operation."""
     if q == 2:
         return np.array([0.5, 0.5])
+    if q == 5:
+        h = theta * 0.5
+        return np.array([h, h, 1.0 - 2.0 * theta, h, h])
     return np.array([theta * 0.5, 1.0 - theta, theta * 0.5])
 
 
 def init_poisson_sine(q: int, count_bytes: int, length: int, nave: float, amp: float,
                       seed: int, realization: int = 0, theta: float = 1.0 / 3.0, x0: int = 0,
-                      width: Optional[int] = None):
-    """Poisson sine initial state of nodes x0 .. x0+width-1 (mod L), as
-    [q][width] counts, and the overflow flag (init v1, see ilg_oracle.c)."""
-    width = length if width is None else width
+                      width: Optional[int] = None, height: int = 0):
+    """Poisson sine initial state of nodes x0 .. x0+width-1 (mod the node
+    count), as [q][width] counts, and the overflow flag (init v1, see
+    ilg_oracle.c).  D2Q5: length = Lx, height = Ly, nodes x + Lx y, profile
+    along x; with width None the result is the whole [5][Ly][Lx] state."""
+    nodes = length * (height if q == 5 else 1)
+    whole = width is None
+    width = nodes if whole else width
     w = np.ascontiguousarray(init_weights(q, theta), dtype=np.float64)
     out = np.zeros((q, width), dtype=np.uint16 if count_bytes == 2 else np.uint32)
-    ov = lib().oracle_init_poisson_sine(q, count_bytes, length, x0, width, _ptr(w), float(nave),
-                                        float(amp), seed, realization, _ptr(out))
+    ov = lib().oracle_init_poisson_sine(q, count_bytes, nodes, length, x0, width, _ptr(w),
+                                        float(nave), float(amp), seed, realization, _ptr(out))
+    if q == 5 and whole:
+        out = out.reshape(5, height, length)
     return out, bool(ov)
 
 

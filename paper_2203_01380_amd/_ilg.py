@@ -34,7 +34,7 @@ class IlgConfig(ctypes.Structure):
                 ("count_bytes", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("length", ctypes.c_uint64), ("omega", ctypes.c_double),
                 ("theta", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("realization", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("realization", ctypes.c_uint32), ("height", ctypes.c_uint32),
                 ("t0", ctypes.c_uint64)]
 
 
@@ -142,9 +142,10 @@ def check(rc: int):
 
 def make_config(q: int, length: int, count_bytes: int, omega: float, seed: int,
                 realization: int = 0, t0: int = 0, theta: float = 0.0,
-                flip: str = "auto") -> IlgConfig:
+                flip: str = "auto", height: int = 0) -> IlgConfig:
+    """height: rows Ly of a D2Q5 lattice (q = 5, length = Lx); 0 otherwise."""
     return IlgConfig(ABI_VERSION, q, count_bytes, FLIP_MODES[flip], length, omega, theta, seed,
-                     realization, 0, t0)
+                     realization, height, t0)
 
 
 def fixed_point(cfg: IlgConfig) -> IlgFixed:
@@ -172,15 +173,22 @@ class Lattice:
 
     def __init__(self, q: int, length: int, count_bytes: int, omega: float, seed: int,
                  init: Optional[np.ndarray], realization: int = 0, t0: int = 0,
-                 theta: float = 0.0, flip: str = "auto", use_torch: bool = True, stream=None):
-        """init: [q][L] host counts, or None for an all-zero state (then call
-        init_poisson_sine to draw the initial state on the device)."""
-        self.cfg = make_config(q, length, count_bytes, omega, seed, realization, t0, theta, flip)
+                 theta: float = 0.0, flip: str = "auto", use_torch: bool = True, stream=None,
+                 height: int = 0):
+        """init: [q][L] host counts (D2Q5: [5][height][length]), or None for an
+        all-zero state (then call init_poisson_sine to draw the initial state
+        on the device)."""
+        self.cfg = make_config(q, length, count_bytes, omega, seed, realization, t0, theta, flip,
+                               height)
         self.q, self.length, self.count_bytes = q, length, count_bytes
+        self.height = height
+        self.shape = (q, height, length) if q == 5 else (q, length)
+        nodes = length * (height if q == 5 else 1)
         if init is not None:
             init = np.ascontiguousarray(init, dtype=_dtype(count_bytes))
-            if init.shape != (q, length):
-                raise ValueError(f"init must have shape {(q, length)}, got {init.shape}")
+            if init.shape != self.shape:
+                raise ValueError(f"init must have shape {self.shape}, got {init.shape}")
+            init = init.reshape(q, nodes)
         self._h = ctypes.c_void_p()
         self._bufs = None
         if use_torch:
@@ -197,7 +205,7 @@ class Lattice:
                     b0.zero_()
                 else:
                     padded = np.zeros((q, pitch), dtype=init.dtype)
-                    padded[:, :length] = init
+                    padded[:, :nodes] = init
                     b0.copy_(torch.from_numpy(padded.view(np.uint8).reshape(-1)))
             stream.synchronize()
             self._bufs = (b0, b1)
@@ -223,12 +231,14 @@ class Lattice:
         return int(lib.ilg_current_step(self._h))
 
     def state(self) -> np.ndarray:
-        out = np.empty((self.q, self.length), dtype=_dtype(self.count_bytes))
+        out = np.empty(self.shape, dtype=_dtype(self.count_bytes))
         check(lib.ilg_get_state(self._h, out.ctypes.data))
         return out
 
     def set_state(self, state: np.ndarray, t: int):
         s = np.ascontiguousarray(state, dtype=_dtype(self.count_bytes))
+        if s.shape != self.shape:
+            raise ValueError(f"state must have shape {self.shape}, got {s.shape}")
         check(lib.ilg_set_state(self._h, s.ctypes.data, t))
 
     def init_poisson_sine(self, nave: float, amp: float, init_seed: int):
@@ -243,7 +253,8 @@ class Lattice:
 
     def moments(self, per_node: bool = False, nk: int = 0) -> dict:
         s = IlgSummary()
-        arrs = [np.empty(self.length, dtype=np.int64) for _ in range(3)] if per_node else None
+        arrs = ([np.empty(self.shape[1:], dtype=np.int64) for _ in range(3)] if per_node
+                else None)
         ptrs = [a.ctypes.data for a in arrs] if per_node else [None, None, None]
         check(lib.ilg_moments(self._h, *ptrs, nk, ctypes.byref(s)))
         out = dict(mass=int(s.mass), step=int(s.step), hash=int(s.hash),
@@ -290,7 +301,7 @@ class Batch:
         for r, (m, init) in enumerate(zip(members, inits)):
             cfgs[r] = make_config(m["q"], m["length"], m["count_bytes"], m["omega"], m["seed"],
                                   m.get("realization", 0), m.get("t0", 0), m.get("theta", 0.0),
-                                  m.get("flip", "auto"))
+                                  m.get("flip", "auto"), m.get("height", 0))
             a = np.ascontiguousarray(init, dtype=_dtype(m["count_bytes"]))
             if a.shape != (m["q"], m["length"]):
                 raise ValueError(f"member {r}: init shape {a.shape}")
@@ -380,7 +391,8 @@ class Server:
     def submit(self, member: dict, init: np.ndarray, nsteps: int) -> int:
         cfg = make_config(member["q"], member["length"], member["count_bytes"], member["omega"],
                           member["seed"], member.get("realization", 0), member.get("t0", 0),
-                          member.get("theta", 0.0), member.get("flip", "auto"))
+                          member.get("theta", 0.0), member.get("flip", "auto"),
+                          member.get("height", 0))
         a = np.ascontiguousarray(init, dtype=_dtype(member["count_bytes"]))
         if a.shape != (member["q"], member["length"]):
             raise ValueError(f"init shape {a.shape}")
@@ -396,7 +408,8 @@ class Server:
         admission (Poisson sine condition, init v1)."""
         cfg = make_config(member["q"], member["length"], member["count_bytes"], member["omega"],
                           member["seed"], member.get("realization", 0), member.get("t0", 0),
-                          member.get("theta", 0.0), member.get("flip", "auto"))
+                          member.get("theta", 0.0), member.get("flip", "auto"),
+                          member.get("height", 0))
         rid = ctypes.c_uint64()
         check(lib.ilg_server_submit_poisson_sine(self._h, ctypes.byref(cfg), float(nave),
                                                  float(amp), int(init_seed), nsteps,

@@ -4,7 +4,9 @@
 //   A^LG   = sum_x sin(2 pi x/L) N(x) / sum_x sin^2(2 pi x/L)     (Results section)
 //   S(k)   = |sum_x N(x) e^{-2 pi i k x/L}|^2 / sum_x N(x),  k = 1..nk      (FP64)
 // and optionally the per-node raw moments rho = sum n_i, J = sum v_i n_i,
-// E = sum v_i^2 n_i.  Angles are reduced exactly in integers,
+// E = sum v_i^2 n_i.  On a D2Q5 lattice x is the column (node mod Lx), the
+// sums run over all nodes, J is the x momentum and E sums |v_i|^2.  Angles
+// are reduced exactly in integers,
 // (k x) mod L, before sincospi, so every term is accurate to a few ulp; the
 // FP64 sums are deterministic (fixed grid, fixed tree).
 #include "ilg_internal.h"
@@ -54,7 +56,8 @@ __global__ __launch_bounds__(kDiagThreads) void diag_kernel(DiagArgs a)
     __shared__ double sd[kDiagThreads / 64];
     __shared__ uint64_t su[kDiagThreads / 64];
     const T *s = reinterpret_cast<const T *>(a.state);
-    const uint32_t L = a.length;
+    const uint32_t L = a.length;        // nodes
+    const uint32_t Lx = a.width;        // row length (angles along x)
     const int q = (int)a.q;
     uint64_t *part_u = reinterpret_cast<uint64_t *>(a.partials) + (size_t)blockIdx.x * kSlots;
     double *part_d = reinterpret_cast<double *>(part_u);
@@ -68,9 +71,13 @@ __global__ __launch_bounds__(kDiagThreads) void diag_kernel(DiagArgs a)
         for (int i = 0; i < q; ++i) {
             const uint64_t n = load_n(s, a.pitch, i, x);
             N += n;
-            const int v = (q == 2) ? (i == 0 ? -1 : 1) : i - 1;
+            // x component and squared speed of velocity i
+            const int v = (q == 2) ? (i == 0 ? -1 : 1)
+                          : (q == 3) ? i - 1
+                                     : (i == 0 ? -1 : (i == 4 ? 1 : 0));
+            const int v2 = (q == 5) ? (i == 2 ? 0 : 1) : v * v;
             J += (int64_t)v * (int64_t)n;
-            E += (int64_t)(v * v) * (int64_t)n;
+            E += (int64_t)v2 * (int64_t)n;
             hash += splitmix64((((uint64_t)x * (uint64_t)q + (uint64_t)i) << 32) ^ n);
         }
         mass += N;
@@ -79,7 +86,8 @@ __global__ __launch_bounds__(kDiagThreads) void diag_kernel(DiagArgs a)
             a.j[x] = J;
             a.e[x] = E;
         }
-        const double sv = sinpi(2.0 * (double)x / (double)L);
+        const uint32_t xc = Lx == L ? x : x % Lx;
+        const double sv = sinpi(2.0 * (double)xc / (double)Lx);
         sn += sv * (double)N;
         sdn += sv * sv;
     }
@@ -110,9 +118,9 @@ __global__ __launch_bounds__(kDiagThreads) void diag_kernel(DiagArgs a)
             for (int m = 0; m < kModesPerPass; ++m) {
                 const uint32_t k = k0 + m + 1;
                 if (k <= a.nk) {
-                    const uint64_t ang = ((uint64_t)k * x) % L;
+                    const uint64_t ang = ((uint64_t)k * (Lx == L ? x : x % Lx)) % Lx;
                     double sv, cv;
-                    sincospi(2.0 * (double)ang / (double)L, &sv, &cv);
+                    sincospi(2.0 * (double)ang / (double)Lx, &sv, &cv);
                     re[m] += Nd * cv;
                     im[m] -= Nd * sv;
                 }

@@ -65,7 +65,9 @@ struct StepArgs {
     const void *in;        // [q][pitch] counts at step t
     void *out;             // [q][pitch] counts at step t+1
     uint64_t pitch;
-    uint32_t length;
+    uint32_t length;       // nodes (L, or Lx Ly for D2Q5)
+    uint32_t width;        // row length Lx (= length in 1D)
+    uint32_t height;       // rows Ly (1 in 1D)
     uint32_t t;            // absolute step index being taken
     uint32_t realization;
     uint32_t key0, key1;   // Philox key
@@ -79,9 +81,10 @@ struct StepArgs {
 struct InitArgs {
     void *out;
     uint64_t pitch;
-    uint32_t length, q;
+    uint32_t length, q;                // nodes, velocities
+    uint32_t width;                    // row length: the profile is along x = node mod width
     uint32_t realization, key0, key1;  // Philox key = init seed
-    double w[3];                       // velocity weights
+    double w[5];                       // velocity weights
     double nave, amp;
     uint32_t *err;                     // bit 0 set if a count exceeds the type
 };
@@ -94,7 +97,8 @@ hipError_t launch_step(int q, int count_bytes, const StepArgs &a, hipStream_t st
 struct DiagArgs {
     const void *state;
     uint64_t pitch;
-    uint32_t length;
+    uint32_t length;       // nodes
+    uint32_t width;        // row length: sine and S(k) along x = node mod width
     uint32_t q;
     uint32_t count_bytes;
     uint32_t nk;

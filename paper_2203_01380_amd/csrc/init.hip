@@ -7,6 +7,8 @@
 // the same counts: every floating-point step is one correctly rounded double
 // operation (contraction into fused multiply-adds is switched off below, and
 // no library transcendental is called).
+//  * Nodes are x (1D) or x + Lx y (D2Q5), the profile runs along the column
+//    x = node mod Lx; the node index is the counter word 0.
 //  * sin(2 pi x / L): 8x = k L + rem in integers (octant k); t = rem / L for
 //    even k, (L - rem) / L for odd k; a = t (pi/4); Taylor polynomials
 //    S = a (1 + a^2 (s_1 + ... + a^2 s_8)), s_j = (-1)^j / (2j+1)!, and
@@ -19,8 +21,9 @@
 //    P = max(1, ceil(mean / 256)) equal parts m = mean / P (a sum of
 //    independent Poisson(m) is Poisson(mean)); part p draws word i of the
 //    Philox4x32-10 block with key = init seed and counter
-//    (x, p, realization, 2^31) (the last word keeps these blocks apart from
-//    the step's draws), U = (u + 1/2) 2^-32, and returns the least k with
+//    (x, p, realization, 2^31 + i / 4) (word i mod 4; the last counter word
+//    keeps these blocks apart from the step's draws), U = (u + 1/2) 2^-32,
+//    and returns the least k with
 //    U <= F(k), where F(0) = f(0) = e^-m, f(k) = (f(k-1) m) / k and
 //    F(k) = F(k-1) + f(k): the Poisson CDF by its recurrence (capped at 10^5).
 // Coefficients 1/j! are 1 / j! with j! exact in double (j <= 18).
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a)
     for (uint64_t xx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; xx < a.length;
          xx += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t x = (uint32_t)xx;
-        const double s = sin2pi_frac(x, a.length);
+        const double s = sin2pi_frac(x % a.width, a.width);
         const double rho = a.nave + a.amp * s;
         for (uint32_t i = 0; i < a.q; ++i) {
             const double mean = a.w[i] * rho;
@@ -142,8 +145,10 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a)
                 const uint32_t parts = pd < 1.0 ? 1u : (uint32_t)pd;
                 const double m = mean / (double)parts;
                 for (uint32_t p = 0; p < parts; ++p) {
-                    const uint4 b = philox4x32_10(x, p, a.realization, 0x80000000u, a.key0, a.key1);
-                    const uint32_t u = i == 0 ? b.x : (i == 1 ? b.y : b.z);
+                    const uint4 b = philox4x32_10(x, p, a.realization, 0x80000000u + (i >> 2),
+                                                  a.key0, a.key1);
+                    const uint32_t w = i & 3u;
+                    const uint32_t u = w == 0 ? b.x : (w == 1 ? b.y : (w == 2 ? b.z : b.w));
                     n += poisson_part(m, u);
                 }
             }

@@ -39,6 +39,12 @@ uint64_t pitch_of(uint64_t length)
     return (length + 63) / 64 * 64;
 }
 
+// Nodes of a configuration: L in 1D, Lx Ly for D2Q5 (node x + Lx y).
+uint64_t nodes_of(const ilg_config *cfg)
+{
+    return cfg->length * (cfg->q == 5 ? (uint64_t)cfg->height : 1u);
+}
+
 }  // namespace
 
 struct ilg_handle {
@@ -86,14 +92,18 @@ int check_config(const ilg_config *cfg, Fixed *fx)
         return fail(ILG_E_INVALID, "null config");
     if (cfg->abi_version != ILG_ABI_VERSION)
         return fail(ILG_E_INVALID, "abi_version mismatch");
-    if (cfg->q != 2 && cfg->q != 3)
-        return fail(ILG_E_INVALID, "q must be 2 or 3");
+    if (cfg->q != 2 && cfg->q != 3 && cfg->q != 5)
+        return fail(ILG_E_INVALID, "q must be 2, 3 or 5");
     if (cfg->count_bytes != 2 && cfg->count_bytes != 4)
         return fail(ILG_E_INVALID, "count_bytes must be 2 or 4");
     if (cfg->length < 1 || cfg->length >= (uint64_t(1) << 31))
         return fail(ILG_E_INVALID, "length must be in [1, 2^31)");
-    if (cfg->reserved != 0 || (cfg->flags & ~ILG_FLIP_MASK) != 0)
-        return fail(ILG_E_INVALID, "reserved bits set");
+    if (cfg->q == 5 ? cfg->height < 1 : cfg->height != 0)
+        return fail(ILG_E_INVALID, "height must be >= 1 for q = 5 and 0 otherwise");
+    if (nodes_of(cfg) >= (uint64_t(1) << 31))
+        return fail(ILG_E_INVALID, "the node count must be below 2^31");
+    if ((cfg->flags & ~ILG_FLIP_MASK) != 0)
+        return fail(ILG_E_INVALID, "reserved flag bits set");
     if (!(cfg->omega > 0.0 && cfg->omega <= 2.0))
         return fail(ILG_E_INVALID, "omega must lie in (0, 2]");
     if (cfg->t0 > 0xFFFFFFFFull)
@@ -101,6 +111,8 @@ int check_config(const ilg_config *cfg, Fixed *fx)
     double theta = cfg->theta == 0.0 ? 1.0 / 3.0 : cfg->theta;
     if (cfg->q == 3 && !(theta > 0.0 && theta < 1.0))
         return fail(ILG_E_INVALID, "theta must lie in (0, 1)");
+    if (cfg->q == 5 && !(theta > 0.0 && theta < 0.5))
+        return fail(ILG_E_INVALID, "D2Q5 theta must lie in (0, 1/2)");
     bool flip;
     switch (cfg->flags & ILG_FLIP_MASK) {
     case ILG_FLIP_AUTO:
@@ -128,7 +140,9 @@ int check_config(const ilg_config *cfg, Fixed *fx)
     fx->omega_star = omega_star;
     fx->p = (uint64_t)std::nearbyint(omega_star * two32);
     fx->p_half = uint64_t(1) << 31;
-    fx->p_rest = cfg->q == 3 ? (uint64_t)std::nearbyint((1.0 - theta) * two32) : 0;
+    fx->p_rest = cfg->q == 3   ? (uint64_t)std::nearbyint((1.0 - theta) * two32)
+                 : cfg->q == 5 ? (uint64_t)std::nearbyint((1.0 - 2.0 * theta) * two32)
+                               : 0;
     std::fesetround(saved);
     return ILG_OK;
 }
@@ -139,7 +153,9 @@ StepArgs step_args(const ilg_handle *h)
     a.in = h->buf[h->cur];
     a.out = h->buf[h->cur ^ 1];
     a.pitch = h->pitch;
-    a.length = (uint32_t)h->cfg.length;
+    a.length = (uint32_t)nodes_of(&h->cfg);
+    a.width = (uint32_t)h->cfg.length;
+    a.height = h->cfg.q == 5 ? h->cfg.height : 1u;
     a.t = (uint32_t)h->t;
     a.realization = h->cfg.realization;
     a.key0 = (uint32_t)(h->cfg.seed & 0xFFFFFFFFu);
@@ -196,8 +212,9 @@ int check_sticky(ilg_handle *h)
 int copy_state_in(ilg_handle *h, const void *host)
 {
     const size_t cb = h->cfg.count_bytes;
-    ILG_HIP(hipMemcpy2DAsync(h->buf[h->cur], h->pitch * cb, host, h->cfg.length * cb,
-                             h->cfg.length * cb, h->cfg.q, hipMemcpyHostToDevice, h->stream));
+    const size_t n = nodes_of(&h->cfg);
+    ILG_HIP(hipMemcpy2DAsync(h->buf[h->cur], h->pitch * cb, host, n * cb, n * cb, h->cfg.q,
+                             hipMemcpyHostToDevice, h->stream));
     ILG_HIP(hipStreamSynchronize(h->stream));
     return ILG_OK;
 }
@@ -238,12 +255,12 @@ int ilg_binomial_table(uint64_t p, uint32_t *out)
 
 uint64_t ilg_state_pitch(const ilg_config *cfg)
 {
-    return cfg ? pitch_of(cfg->length) : 0;
+    return cfg ? pitch_of(nodes_of(cfg)) : 0;
 }
 
 uint64_t ilg_state_bytes(const ilg_config *cfg)
 {
-    return cfg ? pitch_of(cfg->length) * cfg->q * cfg->count_bytes : 0;
+    return cfg ? pitch_of(nodes_of(cfg)) * cfg->q * cfg->count_bytes : 0;
 }
 
 static int create_common(const ilg_config *cfg, void *stream, ilg_handle **out, ilg_handle **hp)
@@ -263,7 +280,7 @@ static int create_common(const ilg_config *cfg, void *stream, ilg_handle **out, 
         h->cfg.theta = 1.0 / 3.0;
     h->fx = fx;
     h->stream = reinterpret_cast<hipStream_t>(stream);
-    h->pitch = pitch_of(cfg->length);
+    h->pitch = pitch_of(nodes_of(cfg));
     h->bytes = h->pitch * cfg->q * cfg->count_bytes;
     h->t = cfg->t0;
     *hp = h;
@@ -356,8 +373,9 @@ int ilg_get_state(ilg_handle *h, void *host_out)
     if (!h || !host_out)
         return fail(ILG_E_INVALID, "null argument");
     const size_t cb = h->cfg.count_bytes;
-    ILG_HIP(hipMemcpy2DAsync(host_out, h->cfg.length * cb, h->buf[h->cur], h->pitch * cb,
-                             h->cfg.length * cb, h->cfg.q, hipMemcpyDeviceToHost, h->stream));
+    const size_t n = nodes_of(&h->cfg);
+    ILG_HIP(hipMemcpy2DAsync(host_out, n * cb, h->buf[h->cur], h->pitch * cb, n * cb, h->cfg.q,
+                             hipMemcpyDeviceToHost, h->stream));
     return check_sticky(h);
 }
 
@@ -387,19 +405,27 @@ int ilg_init_poisson_sine(ilg_handle *h, double nave, double amp, uint64_t init_
     ilg::InitArgs a;
     a.out = h->buf[h->cur ^ 1];
     a.pitch = h->pitch;
-    a.length = (uint32_t)h->cfg.length;
+    a.length = (uint32_t)nodes_of(&h->cfg);
+    a.width = (uint32_t)h->cfg.length;
     a.q = h->cfg.q;
     a.realization = h->cfg.realization;
     a.key0 = (uint32_t)(init_seed & 0xFFFFFFFFu);
     a.key1 = (uint32_t)(init_seed >> 32);
+    for (int i = 0; i < 5; ++i)
+        a.w[i] = 0.0;
     if (h->cfg.q == 2) {
         a.w[0] = 0.5;
         a.w[1] = 0.5;
-        a.w[2] = 0.0;
-    } else {
+    } else if (h->cfg.q == 3) {
         a.w[0] = theta * 0.5;
         a.w[1] = 1.0 - theta;
         a.w[2] = theta * 0.5;
+    } else {
+        a.w[0] = theta * 0.5;
+        a.w[1] = theta * 0.5;
+        a.w[2] = 1.0 - 2.0 * theta;
+        a.w[3] = theta * 0.5;
+        a.w[4] = theta * 0.5;
     }
     a.nave = nave;
     a.amp = amp;
@@ -424,18 +450,20 @@ static int run_diag(ilg_handle *h, bool moments, uint32_t nk, ilg::DiagResult *r
 {
     ilg::DiagArgs a;
     a.state = h->buf[h->cur];
+    const uint64_t n = nodes_of(&h->cfg);
     a.pitch = h->pitch;
-    a.length = (uint32_t)h->cfg.length;
+    a.length = (uint32_t)n;
+    a.width = (uint32_t)h->cfg.length;
     a.q = h->cfg.q;
     a.count_bytes = h->cfg.count_bytes;
     a.nk = nk;
     a.rho = a.j = a.e = nullptr;
     if (moments) {
         if (!h->mom)
-            ILG_HIP(hipMalloc((void **)&h->mom, 3 * h->cfg.length * sizeof(int64_t)));
+            ILG_HIP(hipMalloc((void **)&h->mom, 3 * n * sizeof(int64_t)));
         a.rho = h->mom;
-        a.j = h->mom + h->cfg.length;
-        a.e = h->mom + 2 * h->cfg.length;
+        a.j = h->mom + n;
+        a.e = h->mom + 2 * n;
     }
     a.partials = h->diag_partials;
     a.result = h->diag_result;
@@ -458,7 +486,7 @@ int ilg_moments(ilg_handle *h, int64_t *rho, int64_t *j, int64_t *e, uint32_t nk
     int rc = run_diag(h, moments, nk, &res);
     if (rc != ILG_OK)
         return rc;
-    const uint64_t L = h->cfg.length;
+    const uint64_t L = nodes_of(&h->cfg);
     if (rho)
         ILG_HIP(hipMemcpyAsync(rho, h->mom, L * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
     if (j)

@@ -2,12 +2,14 @@
 // Philox draws of one node-step, the chunked fixed-point binomial, and the
 // node update (flip, removal binomials, multinomial redistribution).
 //
-// Per node x at step t (Eq. LGflip):
+// Per node x at step t (Eq. LGflip; D2Q5 nodes x + Lx y):
 //   a_i   = n_{q-1-i}(x) if the flip is on, else n_i(x)          (Eq. flip)
 //   k_i   = Bin(a_i, P)          removal: each particle collides w.p. P/2^32
 //   M     = sum_i k_i
 //   q = 2: m_0 = Bin(M, 2^31), m_1 = M - m_0
 //   q = 3: m_1 = Bin(M, P_rest), R = M - m_1, m_0 = Bin(R, 2^31), m_2 = R - m_0
+//   q = 5: m_2 = Bin(M, P_rest), R = M - m_2, m_x = Bin(R, 2^31), m_y = R - m_x,
+//          m_0 = Bin(m_x, 2^31), m_4 = m_x - m_0, m_1 = Bin(m_y, 2^31), m_3 = m_y - m_1
 //   c_i   = a_i - k_i + m_i   (streamed afterwards to x + v_i)
 // Bin(n, p) takes ceil(n/64) 32-bit draws (full chunks of 64 first, then the
 // remainder); a chunk of m trials with draw U yields #{j < m : T[m][j] <= U}.
@@ -98,6 +100,7 @@ __device__ __forceinline__ uint32_t draw_word(const Draws<NB> &d, uint32_t j)
     uint32_t r;
     if (!wave_any(j != j0) && j0 < kEager) {
         // wave-uniform index: scalar branches pick the register
+        static_assert(kEager <= 12, "at most three eager Philox blocks");
         switch (j0) {
         case 0: r = d.w[0]; break;
         case 1: r = d.w[1]; break;
@@ -106,16 +109,25 @@ __device__ __forceinline__ uint32_t draw_word(const Draws<NB> &d, uint32_t j)
         case 4: r = d.w[4 % kEager]; break;
         case 5: r = d.w[5 % kEager]; break;
         case 6: r = d.w[6 % kEager]; break;
+        case 7: r = d.w[7 % kEager]; break;
+        case 8: r = d.w[8 % kEager]; break;
+        case 9: r = d.w[9 % kEager]; break;
+        case 10: r = d.w[10 % kEager]; break;
         default: r = d.w[kEager - 1]; break;
         }
     } else {
         const uint32_t jc = j < kEager ? j : kEager - 1;
         if constexpr (NB == 1) {
             r = pick4(d.w[0], d.w[1], d.w[2], d.w[3], jc);
-        } else {
+        } else if constexpr (NB == 2) {
             const uint32_t lo = pick4(d.w[0], d.w[1], d.w[2], d.w[3], jc & 3u);
             const uint32_t hi = pick4(d.w[4], d.w[5], d.w[6], d.w[7], jc & 3u);
             r = (jc & 4u) ? hi : lo;
+        } else {
+            const uint32_t b0 = pick4(d.w[0], d.w[1], d.w[2], d.w[3], jc & 3u);
+            const uint32_t b1 = pick4(d.w[4], d.w[5], d.w[6], d.w[7], jc & 3u);
+            const uint32_t b2 = pick4(d.w[8], d.w[9], d.w[10], d.w[11], jc & 3u);
+            r = (jc >= 8u) ? b2 : ((jc >= 4u) ? b1 : b0);
         }
         if (wave_any(j >= kEager)) {
             if (j >= kEager) {
@@ -373,6 +385,45 @@ __device__ __forceinline__ W or_all(const W (&c)[Q])
     return any;
 }
 
+// D2Q5 node update when the whole wave shares the common draw layout: every
+// removal binomial has 1..64 trials (draws 0..4) and the redistribution fits
+// one chunk per binomial (M <= 64): rest Bin(M, 1 - 2 theta) at draw 5, the
+// x/y split Bin(R, 1/2) at draw 6, then Bin(m_x, 1/2) for -x at draw 7 and
+// Bin(m_y, 1/2) for -y at the next draw, which is 8 if the -x split took one
+// (m_x > 0), else 7.  Earlier zero counts make the later words irrelevant
+// (M = 0 or R = 0 leaves nothing to split).  Returns false (nothing
+// written) if some lane has M > 64.
+template <typename W, int NB, int GB>
+__device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Draws<NB> &d,
+                                           const uint32_t *tab_p, const uint8_t *g_p,
+                                           const uint32_t *tab_half, const uint8_t *g_half,
+                                           const uint32_t *tab_rest, const uint8_t *g_rest,
+                                           bool p_zero)
+{
+    static_assert(NB >= 3, "draws 0..8 must be computed up front");
+    W kv[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        kv[i] = p_zero ? (W)0 : (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[i], d.w[i]);
+    const W M = kv[0] + kv[1] + kv[2] + kv[3] + kv[4];
+    if (wave_any(M > (W)kChunk))
+        return false;
+    W mv[5];
+    mv[2] = (W)chunk_or_zero<GB>(tab_rest, g_rest, (uint32_t)M, d.w[5]);
+    const W R = M - mv[2];
+    const W mx = (W)chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, d.w[6]);
+    const W my = R - mx;
+    mv[0] = (W)chunk_or_zero<GB>(tab_half, g_half, (uint32_t)mx, d.w[7]);
+    mv[4] = mx - mv[0];
+    const uint32_t uy = pick3(mx > 0, false, d.w[7], d.w[8], 0u);
+    mv[1] = (W)chunk_or_zero<GB>(tab_half, g_half, (uint32_t)my, uy);
+    mv[3] = my - mv[1];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        c[i] = av[i] - kv[i] + mv[i];
+    return true;
+}
+
 template <typename T> struct Wide;
 template <> struct Wide<uint16_t> { using type = uint32_t; };
 template <> struct Wide<uint32_t> { using type = uint64_t; };
@@ -394,6 +445,10 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
     bool ok = true, two = false, three = false;
     if constexpr (Q == 2) {
         ok = av[0] >= 1 && av[0] <= (W)kChunk && av[1] >= 1 && av[1] <= (W)kChunk;
+    } else if constexpr (Q == 5) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            ok = ok && av[i] >= 1 && av[i] <= (W)kChunk;
     } else {
         ok = av[0] >= 1 && av[0] <= (W)kChunk && av[2] >= 1 && av[2] <= (W)kChunk &&
              av[1] >= 1 && av[1] <= (W)(3 * kChunk);
@@ -402,7 +457,10 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
     }
     bool done = false;
     if (!wave_any(!ok)) {
-        if (!wave_any(two))
+        if constexpr (Q == 5)
+            done = node_fast5<W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
+                                         g_rest, p_zero);
+        else if (!wave_any(two))
             done = node_fast<Q, 1, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
                                               g_rest, p_zero);
         else if constexpr (Q == 3) {
@@ -425,6 +483,16 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
         if constexpr (Q == 2) {
             mv[0] = binomial<W, NB, GB>(M, j, tab_half, g_half, false, d);
             mv[1] = M - mv[0];
+        } else if constexpr (Q == 5) {
+            // rest, then the x/y pair split, then -x within x, -y within y
+            mv[2] = binomial<W, NB, GB>(M, j, tab_rest, g_rest, false, d);
+            const W R = M - mv[2];
+            const W mx = binomial<W, NB, GB>(R, j, tab_half, g_half, false, d);
+            const W my = R - mx;
+            mv[0] = binomial<W, NB, GB>(mx, j, tab_half, g_half, false, d);
+            mv[4] = mx - mv[0];
+            mv[1] = binomial<W, NB, GB>(my, j, tab_half, g_half, false, d);
+            mv[3] = my - mv[1];
         } else {
             mv[1] = binomial<W, NB, GB>(M, j, tab_rest, g_rest, false, d);
             const W R = M - mv[1];

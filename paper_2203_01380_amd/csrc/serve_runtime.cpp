@@ -115,6 +115,7 @@ public:
             a.out = base;
             a.pitch = pitch;
             a.length = (uint32_t)c.length;
+            a.width = (uint32_t)c.length;
             a.q = c.q;
             a.realization = c.realization;
             a.key0 = (uint32_t)(p->init_seed & 0xFFFFFFFFu);
@@ -122,6 +123,7 @@ public:
             a.w[0] = c.q == 2 ? 0.5 : theta * 0.5;
             a.w[1] = c.q == 2 ? 0.5 : 1.0 - theta;
             a.w[2] = c.q == 2 ? 0.0 : theta * 0.5;
+            a.w[3] = a.w[4] = 0.0;
             a.nave = p->nave;
             a.amp = p->amp;
             a.err = err;
@@ -376,6 +378,8 @@ int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_hos
     int rc = ilg::check_config(cfg, &fx);
     if (rc != ILG_OK)
         return rc;
+    if (cfg->q == 5)
+        return sfail(ILG_E_INVALID, "D2Q5 lattices run in the plain form only");
     if (nsteps == 0)
         return sfail(ILG_E_INVALID, "nsteps must be positive");
     if (cfg->t0 + nsteps > (uint64_t(1) << 32))
@@ -407,6 +411,8 @@ int ilg_server_submit_poisson_sine(ilg_server *s, const ilg_config *cfg, double 
     int rc = ilg::check_config(cfg, &fx);
     if (rc != ILG_OK)
         return rc;
+    if (cfg->q == 5)
+        return sfail(ILG_E_INVALID, "D2Q5 lattices run in the plain form only");
     if (nsteps == 0)
         return sfail(ILG_E_INVALID, "nsteps must be positive");
     if (cfg->t0 + nsteps > (uint64_t(1) << 32))

@@ -32,7 +32,7 @@ template <int Q, typename T, int NB, int GB, int BLOCK, bool FLIP, bool PZ>
 __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 {
     using W = typename Wide<T>::type;
-    constexpr int kTabs = (Q == 3) ? 3 : 2;
+    constexpr int kTabs = (Q == 2) ? 2 : 3;
     constexpr int kRowGuide = 1 << GB;
     // Tables first, guides after them: every guide then sits at a nonzero
     // LDS address, which lets the row-and-bucket index fold into the
@@ -106,6 +106,29 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         sampler::node_update<Q, W, NB, GB>(av, cn, x, a.t, a.realization, a.key0, a.key1, tab_p,
                                            g_p, tab_half, g_half, tab_rest, g_rest, PZ);
         ovf |= sampler::or_all<Q, W>(cn);
+        if constexpr (Q == 5) {
+            // D2Q5 streaming on the node index x + Lx y (periodic in both):
+            // -x, -y, rest, +y, +x.  The column and row of the node come from
+            // the tile's first node (one scalar division per tile).
+            const uint32_t tile0 = tile * kTile;
+            const uint32_t row0 = tile0 / a.width;
+            uint32_t cx = tile0 - row0 * a.width + threadIdx.x, cy = row0;
+            if (cx >= a.width) {
+                const uint32_t k = cx / a.width;
+                cx -= k * a.width;
+                cy += k;
+            }
+            const uint32_t dxm = cx == 0 ? x + a.width - 1 : x - 1;
+            const uint32_t dxp = cx + 1 == a.width ? x + 1 - a.width : x + 1;
+            const uint32_t dym = cy == 0 ? x + (L - a.width) : x - a.width;
+            const uint32_t dyp = cy + 1 == a.height ? x - (L - a.width) : x + a.width;
+            out[dxm] = (T)cn[0];
+            out[pitch + dym] = (T)cn[1];
+            out[2 * pitch + x] = (T)cn[2];
+            out[3 * pitch + dyp] = (T)cn[3];
+            out[4 * pitch + dxp] = (T)cn[4];
+            continue;
+        }
         // Streaming: velocity -1 to x-1, 0 in place, +1 to x+1 (periodic).
         const uint32_t xm = (x == 0) ? L - 1 : x - 1;
         const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
@@ -162,6 +185,10 @@ hipError_t launch_step(int q, int count_bytes, const StepArgs &a, hipStream_t st
         return launch_q<3, uint16_t, 2>(a, stream);
     if (q == 3 && count_bytes == 4)
         return launch_q<3, uint32_t, 2>(a, stream);
+    if (q == 5 && count_bytes == 2)
+        return launch_q<5, uint16_t, 3>(a, stream);
+    if (q == 5 && count_bytes == 4)
+        return launch_q<5, uint32_t, 3>(a, stream);
     return hipErrorInvalidValue;
 }
 

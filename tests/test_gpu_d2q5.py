@@ -1,0 +1,135 @@
+"""GPU parity of the D2Q5 lattice gas with the flip (the paper's flip on a
+two-dimensional five-velocity set) against the oracle: every compared step
+bit-exact over lattice shapes whose 1024-node tiles wrap rows, both count
+types, special rates, multi-chunk counts, per-step hashes, moments, the
+device-drawn initial state, a 2048 x 2048 lattice, and the rejection of
+D2Q5 by the batched and serving forms."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ilg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2203_01380_amd as ilg
+    return ilg
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run_both(ilg, lx, ly, cb, omega, init, steps, seed=1, r=0, t0=0, flip="auto", theta=0.0,
+              use_torch=True, check_every=1):
+    _say(f"[d2q5] {lx}x{ly} cb={cb} omega={omega} steps={steps} flip={flip} theta={theta}")
+    p = O.Params(5, omega, theta=theta or 1.0 / 3.0, flip=flip)
+    lat = ilg.Lattice(5, lx, cb, omega, seed, init, realization=r, t0=t0, theta=theta, flip=flip,
+                      use_torch=use_torch, height=ly)
+    cur = init.copy()
+    done = 0
+    while done < steps:
+        n = min(check_every, steps - done)
+        lat.step(n)
+        cur, hs, ov = O.run2d(p, cur, n, seed=seed, realization=r, t0=t0 + done, hashes=True)
+        assert not ov
+        done += n
+        got = lat.state()
+        if not np.array_equal(got, cur):
+            bad = np.argwhere(got != cur)
+            raise AssertionError(f"state mismatch after {done} steps at {bad[:5].tolist()}")
+        assert lat.hash() == int(hs[-1])
+    lat.close()
+    return cur
+
+
+@pytest.mark.parametrize("lx,ly", [(1, 1), (1, 7), (7, 1), (3, 5), (64, 64), (1023, 3),
+                                   (1000, 33), (2049, 2), (31, 257)])
+@pytest.mark.parametrize("cb", [2, 4])
+def test_shapes_and_types(ilg, lx, ly, cb):
+    rng = np.random.default_rng(lx * 1000 + ly + cb)
+    dt = np.uint16 if cb == 2 else np.uint32
+    init = rng.poisson(25.0, size=(5, ly, lx)).astype(dt)
+    _run_both(ilg, lx, ly, cb, 1.6, init, steps=5, seed=3 + lx, r=2)
+
+
+@pytest.mark.parametrize("omega,flip,theta", [(2.0, "auto", 0.0), (1.0, "off", 0.0),
+                                              (1.0, "on", 0.0), (0.3, "auto", 0.0),
+                                              (1.9, "auto", 0.2), (0.7, "auto", 0.45),
+                                              (1.05, "auto", 0.0)])
+def test_special_rates(ilg, omega, flip, theta):
+    rng = np.random.default_rng(17)
+    init = rng.poisson(30.0, size=(5, 40, 50)).astype(np.uint32)
+    _run_both(ilg, 50, 40, 4, omega, init, steps=6, seed=9, flip=flip, theta=theta)
+
+
+def test_multi_chunk_counts(ilg):
+    """Counts above 64 (several chunks, draws past the eager blocks)."""
+    rng = np.random.default_rng(4)
+    init = rng.poisson(150.0, size=(5, 30, 70)).astype(np.uint16)
+    init[:, :3, :5] = 900
+    _run_both(ilg, 70, 30, 2, 1.3, init, steps=6, seed=11, check_every=2)
+    _run_both(ilg, 70, 30, 2, 1.0, init, steps=3, seed=12, use_torch=False)
+
+
+def test_moments_d2q5(ilg):
+    rng = np.random.default_rng(5)
+    init = rng.poisson(20.0, size=(5, 12, 33)).astype(np.uint16)
+    lat = ilg.Lattice(5, 33, 2, 1.4, 1, init, height=12)
+    lat.step(3)
+    st = lat.state().astype(np.int64)
+    m = lat.moments(per_node=True)
+    lat.close()
+    assert m["mass"] == int(init.astype(np.int64).sum())
+    np.testing.assert_array_equal(m["rho"], st.sum(axis=0))
+    np.testing.assert_array_equal(m["j"], st[4] - st[0])
+    np.testing.assert_array_equal(m["e"], st.sum(axis=0) - st[2])
+
+
+def test_device_init_d2q5(ilg):
+    lx, ly = 97, 41
+    lat = ilg.Lattice(5, lx, 2, 1.7, 6, None, realization=3, height=ly)
+    lat.init_poisson_sine(120.0, 80.0, 44)
+    got = lat.state()
+    want, ov = O.init_poisson_sine(5, 2, lx, 120.0, 80.0, 44, realization=3, height=ly)
+    assert not ov
+    np.testing.assert_array_equal(got, want)
+    lat.step(4)
+    after = lat.state()
+    lat.close()
+    ref, _, _ = O.run2d(O.Params(5, 1.7), want, 4, seed=6, realization=3)
+    np.testing.assert_array_equal(after, ref)
+
+
+def test_full_size_2048(ilg):
+    """2048 x 2048 nodes, uint16: one whole-lattice step against the oracle,
+    then 20 more steps conserve the mass."""
+    lx = ly = 2048
+    _say("[d2q5] 2048 x 2048")
+    lat = ilg.Lattice(5, lx, 2, 1.8, 1, None, height=ly)
+    lat.init_poisson_sine(150.0, 0.0, 2)
+    init = lat.state()
+    lat.step(1)
+    ref, _, _ = O.run2d(O.Params(5, 1.8), init, 1, seed=1)
+    np.testing.assert_array_equal(lat.state(), ref)
+    lat.step(20)
+    assert lat.moments()["mass"] == int(init.astype(np.int64).sum())
+    lat.close()
+
+
+def test_batch_and_server_reject_d2q5(ilg):
+    m = dict(q=5, length=8, count_bytes=2, omega=1.5, seed=1, height=4)
+    init = np.zeros((5, 8 * 4), dtype=np.uint16)
+    with pytest.raises((ilg.IlgError, ValueError)):
+        ilg.Batch([m], [init.reshape(5, 32)])
+    srv = ilg.Server(1 << 20, 10)
+    with pytest.raises(ilg.IlgError):
+        srv.submit_poisson_sine(m, 10.0, 0.0, 1, 5)
+    srv.close()

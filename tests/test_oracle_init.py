@@ -149,3 +149,23 @@ def test_seed_changes_draws():
     a, _ = O.init_poisson_sine(2, 2, 5000, 40.0, 10.0, seed=1)
     b, _ = O.init_poisson_sine(2, 2, 5000, 40.0, 10.0, seed=2)
     assert (a != b).mean() > 0.8
+
+
+def test_d2q5_profile_and_weights():
+    """D2Q5: means w_i (N + A sin(2 pi x / Lx)) with weights (theta/2, theta/2,
+    1 - 2 theta, theta/2, theta/2), constant along y; the fifth velocity takes
+    its word from a second Philox block and is independent of the first."""
+    lx, ly, N, A, R = 16, 3, 60.0, 40.0, 2500
+    acc = np.zeros((5, ly, lx))
+    for r in range(R):
+        out, _ = O.init_poisson_sine(5, 2, lx, N, A, seed=13, realization=r, height=ly)
+        acc += out
+    mean = acc / R
+    w = np.array([1 / 6, 1 / 6, 1 / 3, 1 / 6, 1 / 6])
+    prof = N + A * np.sin(2 * np.pi * np.arange(lx) / lx)
+    expect = w[:, None, None] * prof[None, None, :] * np.ones((1, ly, 1))
+    z = (mean - expect) / np.sqrt(expect / R)
+    assert np.abs(z).max() < 4.5
+    big, _ = O.init_poisson_sine(5, 2, 400, 90.0, 0.0, seed=2, height=500)
+    flat = big.reshape(5, -1).astype(np.float64)
+    assert abs(np.corrcoef(flat[0], flat[4])[0, 1]) < 4.5 / math.sqrt(flat.shape[1])
