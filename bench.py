@@ -6,7 +6,9 @@ omega* = 0.2), Philox seed 1.  A "step" is one full lattice time step; the
 state is resident in HBM before timing; timing uses HIP events on the stream
 the kernels run on.
 
-Also reported (extra JSON objects): the batched ensemble form on the ragged
+Also reported (extra JSON objects): the same step on a 2^26-node lattice
+(state larger than the MALL), the D2Q5 extension on 4096 x 4096 nodes, the
+batched ensemble form on the ragged
 D1Q2 ensemble (4096 members, L log-uniform in [64, 8192], 5000 steps, S(k)
 every 10 steps) against the plain per-realization loop on a sample of the same
 members, the batched D1Q3 decay sweep (6 x 1024 members, L = 4096, uint32,
@@ -121,6 +123,28 @@ def bench_plain_mall_free(ilg, W, stream, warmup: int, steps: int = 500):
             "steps": steps, "ms_per_step": ms, "node_updates_per_s": spec.length / (ms / 1e3),
             "alg_gbs": alg_bytes / (ms / 1e3) / 1e9,
             "traffic": counter_traffic(spec.length)}
+
+
+def bench_d2q5(ilg, stream, warmup: int, steps: int = 500):
+    """The D2Q5 extension: 4096 x 4096 periodic nodes, uint16, Poisson
+    occupations drawn on the device (means 25, 25, 50, 25, 25), omega = 1.8."""
+    lx = ly = 4096
+    lat = ilg.Lattice(5, lx, 2, 1.8, 1, None, height=ly)
+    lat.init_poisson_sine(150.0, 0.0, 2)
+    mass0 = lat.moments()["mass"]
+    lat.step(warmup)
+    sec = timed(stream, lambda: lat.step(steps))
+    if lat.moments()["mass"] != mass0:
+        raise SystemExit("D2Q5: mass not conserved")
+    lat.close()
+    ms = sec * 1e3 / steps
+    nodes = lx * ly
+    alg_bytes = 2 * 5 * 2 * nodes
+    return {"workload": "D2Q5 with flip, 4096 x 4096 periodic, uint16, Poisson means "
+                        "(25, 25, 50, 25, 25) drawn on the device, omega=1.8",
+            "steps": steps, "ms_per_step": ms, "node_updates_per_s": nodes / (ms / 1e3),
+            "alg_bytes_per_node_update": 20, "alg_gbs": alg_bytes / (ms / 1e3) / 1e9,
+            "hbm_frac": alg_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 
 def bench_batched_ragged(ilg, W, stream, steps: int, loop_members: int):
@@ -264,8 +288,8 @@ def main():
     ap.add_argument("--length", type=int, default=1 << 24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,mallfree,batched,decay,serving",
-                    help="comma list of plain (always), mallfree, batched, decay, serving")
+    ap.add_argument("--forms", default="plain,mallfree,d2q5,batched,decay,serving",
+                    help="comma list of plain (always), mallfree, d2q5, batched, decay, serving")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
@@ -344,6 +368,9 @@ def main():
     if "mallfree" in forms and spec.length != MALL_FREE_LENGTH:
         say("plain step at 2^26 nodes")
         out["plain_l2p26"] = bench_plain_mall_free(ilg, W, stream, args.warmup)
+    if "d2q5" in forms:
+        say("D2Q5 4096 x 4096")
+        out["d2q5"] = bench_d2q5(ilg, stream, args.warmup)
     if "batched" in forms:
         say("batched ragged ensemble")
         out["batched"] = bench_batched_ragged(ilg, W, stream, args.batched_steps,

@@ -385,14 +385,15 @@ __device__ __forceinline__ W or_all(const W (&c)[Q])
     return any;
 }
 
-// D2Q5 node update when the whole wave shares the common draw layout: every
-// removal binomial has 1..64 trials (draws 0..4) and the redistribution fits
-// one chunk per binomial (M <= 64): rest Bin(M, 1 - 2 theta) at draw 5, the
-// x/y split Bin(R, 1/2) at draw 6, then Bin(m_x, 1/2) for -x at draw 7 and
-// Bin(m_y, 1/2) for -y at the next draw, which is 8 if the -x split took one
-// (m_x > 0), else 7.  Earlier zero counts make the later words irrelevant
-// (M = 0 or R = 0 leaves nothing to split).  Returns false (nothing
-// written) if some lane has M > 64.
+// D2Q5 node update when every lane has the movers' counts in 1..64 and the
+// rest count in 1..128 (one or two chunks: D = 1 or 2 by lane) and the
+// redistribution fits one chunk per binomial (M <= 64).  Draws: movers -x
+// and -y at 0 and 1, the rest at 2 (and 3 for a second chunk), then, shifted
+// by D - 1 per lane, +y at 3, +x at 4, the rest redistribution Bin(M, 1 - 2
+// theta) at 5, the x/y split Bin(R, 1/2) at 6, Bin(m_x, 1/2) for -x at 7 and
+// Bin(m_y, 1/2) for -y at the next draw (8 if the -x split took one, else 7).
+// Earlier zero counts make the later words irrelevant (M = 0 or R = 0 leaves
+// nothing to split).  Returns false (nothing written) if some lane has M > 64.
 template <typename W, int NB, int GB>
 __device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Draws<NB> &d,
                                            const uint32_t *tab_p, const uint8_t *g_p,
@@ -400,22 +401,41 @@ __device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Dr
                                            const uint32_t *tab_rest, const uint8_t *g_rest,
                                            bool p_zero)
 {
-    static_assert(NB >= 3, "draws 0..8 must be computed up front");
+    static_assert(NB >= 3, "draws 0..9 must be computed up front");
+    const uint32_t a2 = (uint32_t)av[2];
+    const bool two = a2 > (uint32_t)kChunk;
+    // word k of the layout after the rest binomial, shifted by one if it took two chunks
+    auto wk = [&](auto kc) -> uint32_t {
+        constexpr int k = decltype(kc)::value;
+        return two ? d.w[k + 1] : d.w[k];
+    };
     W kv[5];
+    if (p_zero) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i)
-        kv[i] = p_zero ? (W)0 : (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[i], d.w[i]);
+        for (int i = 0; i < 5; ++i)
+            kv[i] = 0;
+    } else {
+        kv[0] = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[0], d.w[0]);
+        kv[1] = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[1], d.w[1]);
+        uint32_t k2 = chunk_count<GB>(tab_p, g_p, two ? (uint32_t)kChunk : a2, d.w[2]);
+        if (wave_any(two))
+            k2 += chunk_or_zero<GB>(tab_p, g_p, two ? a2 - kChunk : 0u, d.w[3]);
+        kv[2] = (W)k2;
+        kv[3] = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[3], wk(std::integral_constant<int, 3>{}));
+        kv[4] = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[4], wk(std::integral_constant<int, 4>{}));
+    }
     const W M = kv[0] + kv[1] + kv[2] + kv[3] + kv[4];
     if (wave_any(M > (W)kChunk))
         return false;
     W mv[5];
-    mv[2] = (W)chunk_or_zero<GB>(tab_rest, g_rest, (uint32_t)M, d.w[5]);
+    mv[2] = (W)chunk_or_zero<GB>(tab_rest, g_rest, (uint32_t)M, wk(std::integral_constant<int, 5>{}));
     const W R = M - mv[2];
-    const W mx = (W)chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, d.w[6]);
+    const W mx = (W)chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, wk(std::integral_constant<int, 6>{}));
     const W my = R - mx;
-    mv[0] = (W)chunk_or_zero<GB>(tab_half, g_half, (uint32_t)mx, d.w[7]);
+    const uint32_t u7 = wk(std::integral_constant<int, 7>{});
+    mv[0] = (W)chunk_or_zero<GB>(tab_half, g_half, (uint32_t)mx, u7);
     mv[4] = mx - mv[0];
-    const uint32_t uy = pick3(mx > 0, false, d.w[7], d.w[8], 0u);
+    const uint32_t uy = mx > 0 ? wk(std::integral_constant<int, 8>{}) : u7;
     mv[1] = (W)chunk_or_zero<GB>(tab_half, g_half, (uint32_t)my, uy);
     mv[3] = my - mv[1];
 #pragma unroll
@@ -448,7 +468,7 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
     } else if constexpr (Q == 5) {
 #pragma unroll
         for (int i = 0; i < 5; ++i)
-            ok = ok && av[i] >= 1 && av[i] <= (W)kChunk;
+            ok = ok && av[i] >= 1 && av[i] <= (W)(i == 2 ? 2 * kChunk : kChunk);
     } else {
         ok = av[0] >= 1 && av[0] <= (W)kChunk && av[2] >= 1 && av[2] <= (W)kChunk &&
              av[1] >= 1 && av[1] <= (W)(3 * kChunk);

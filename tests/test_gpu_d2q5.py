@@ -133,3 +133,16 @@ def test_batch_and_server_reject_d2q5(ilg):
     with pytest.raises(ilg.IlgError):
         srv.submit_poisson_sine(m, 10.0, 0.0, 1, 5)
     srv.close()
+
+
+def test_rest_count_chunk_layouts(ilg):
+    """Rest counts around one and two chunks (64/65, 128/129) mixed within
+    wavefronts, movers 1..40: the straight-line path with a per-lane shift
+    of the later draws, and the generic path past 128."""
+    rng = np.random.default_rng(23)
+    lx, ly = 256, 24
+    init = rng.integers(1, 41, size=(5, ly, lx)).astype(np.uint16)
+    init[2] = rng.choice([1, 40, 64, 65, 100, 128, 129, 150], size=(ly, lx))
+    init[2, :8] = rng.integers(60, 129, size=(8, lx))      # rows inside the fast path
+    _run_both(ilg, lx, ly, 2, 1.8, init, steps=6, seed=29)
+    _run_both(ilg, lx, ly, 2, 1.2, init, steps=4, seed=30)
