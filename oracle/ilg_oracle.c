@@ -34,7 +34,8 @@
  * others to the x or the y pair with probability 1/2 and then to either
  * direction of the pair with probability 1/2 (conditional binomials, drawn
  * in that order).  Nodes are numbered x + Lx y.
- * Draws: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11), key = the 64-bit
+ * Draws (specification v1): Philox4x32-10 (Salmon, Moraes, Dror & Shaw,
+ * SC'11); v2 uses the same generator with 7 rounds.  Key = the 64-bit
  * seed split into two 32-bit words (low word first), counter =
  * (node x, step t, realization r, block b).  Draw number j of a node-step is
  * word (j mod 4) of block j / 4.  Draw order within a node-step: removal
@@ -58,13 +59,14 @@
  *   out0 = hi(M1*c2) ^ c1 ^ k0,  out1 = lo(M1*c2),
  *   out2 = hi(M0*c0) ^ c3 ^ k1,  out3 = lo(M0*c0);
  * the key is advanced by the two Weyl constants between rounds. */
-void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+void oracle_philox4x32(const uint32_t ctr_in[4], const uint32_t key_in[2], int rounds,
+                       uint32_t out[4])
 {
     const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
     const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
     uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
     uint32_t k0 = key_in[0], k1 = key_in[1];
-    for (int round = 0; round < 10; ++round) {
+    for (int round = 0; round < rounds; ++round) {
         if (round > 0) {
             k0 += W0;
             k1 += W1;
@@ -80,16 +82,24 @@ void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], ui
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    oracle_philox4x32(ctr_in, key_in, 10, out);
+}
+
 /* The stream of 32-bit draws of one node-step. */
 typedef struct {
     uint32_t key[2];
     uint32_t ctr[4];   /* x, t, r, block */
     uint32_t block[4];
     uint64_t used;     /* number of draws consumed so far */
+    int rounds;        /* Philox rounds: 10 (specification v1) or 7 (v2) */
 } draw_stream;
 
-static void stream_init(draw_stream *s, uint64_t seed, uint32_t x, uint32_t t, uint32_t r)
+static void stream_init(draw_stream *s, uint64_t seed, uint32_t x, uint32_t t, uint32_t r,
+                        int rounds)
 {
+    s->rounds = rounds;
     s->key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
     s->key[1] = (uint32_t)(seed >> 32);
     s->ctr[0] = x;
@@ -104,7 +114,7 @@ static uint32_t next_draw(draw_stream *s)
     uint64_t j = s->used;
     if (j % 4 == 0) {
         s->ctr[3] = (uint32_t)(j / 4);
-        oracle_philox4x32_10(s->ctr, s->key, s->block);
+        oracle_philox4x32(s->ctr, s->key, s->rounds, s->block);
     }
     s->used = j + 1;
     return s->block[j % 4];
@@ -147,7 +157,21 @@ typedef struct {
                                   (1 - 2 theta) 2^32 for q = 5 */
     uint64_t seed;
     uint32_t realization;
+    int rounds;                /* Philox rounds of the step draws */
 } oracle_params;
+
+/* The `flip` word of the entry points: bit 0 applies the flip; bits 8..15
+ * give the Philox round count of the step draws (0 means 10, the draw
+ * specification v1; 7 selects v2). */
+static oracle_params make_params(int q, int flipword, const uint32_t *tab_p,
+                                 const uint32_t *tab_half, const uint32_t *tab_rest,
+                                 uint64_t seed, uint32_t realization)
+{
+    const int rounds = (flipword >> 8) & 0xFF;
+    oracle_params pp = {q, flipword & 1, tab_p, tab_half, tab_rest, seed, realization,
+                        rounds ? rounds : 10};
+    return pp;
+}
 
 /* One node: flip, then removal binomials, then multinomial redistribution.
  * Returns the post-collision counts c_i = a_i - k_i + m_i (before streaming). */
@@ -157,7 +181,7 @@ static void collide_node(const oracle_params *pp, const uint64_t n_in[5], uint32
     const int q = pp->q;
     uint64_t a[5] = {0, 0, 0, 0, 0}, k[5] = {0, 0, 0, 0, 0}, m[5] = {0, 0, 0, 0, 0};
     draw_stream s;
-    stream_init(&s, pp->seed, x, t, pp->realization);
+    stream_init(&s, pp->seed, x, t, pp->realization, pp->rounds);
 
     /* Flip, Eq. flip: a_i = n_{-i}; with the index orders above the mirror
      * of index i is q-1-i (in 2D: -x <-> +x, -y <-> +y, rest fixed). */
@@ -265,7 +289,7 @@ int oracle_step(int q, int count_bytes, uint64_t length, uint64_t x0, uint64_t w
                 uint64_t seed, uint32_t realization, uint32_t t, const void *in, void *out,
                 int nthreads)
 {
-    oracle_params pp = {q, flip, tab_p, tab_half, tab_rest, seed, realization};
+    oracle_params pp = make_params(q, flip, tab_p, tab_half, tab_rest, seed, realization);
     if (!periodic)
         memset(out, 0, (size_t)q * width * (size_t)count_bytes);
     if (nthreads < 1)
@@ -336,7 +360,7 @@ int oracle_step2d(int count_bytes, uint64_t lx, uint64_t ly, int flip, const uin
                   const uint32_t *tab_half, const uint32_t *tab_rest, uint64_t seed,
                   uint32_t realization, uint32_t t, const void *in, void *out, int nthreads)
 {
-    oracle_params pp = {5, flip, tab_p, tab_half, tab_rest, seed, realization};
+    oracle_params pp = make_params(5, flip, tab_p, tab_half, tab_rest, seed, realization);
     const uint64_t nodes = lx * ly;
     if (nthreads < 1)
         nthreads = 1;
@@ -459,7 +483,7 @@ void oracle_collide_node(int q, int flip, const uint32_t *tab_p, const uint32_t 
                          const uint32_t *tab_rest, uint64_t seed, uint32_t realization,
                          uint32_t x, uint32_t t, const uint64_t *n_in, uint64_t *c_out)
 {
-    oracle_params pp = {q, flip, tab_p, tab_half, tab_rest, seed, realization};
+    oracle_params pp = make_params(q, flip, tab_p, tab_half, tab_rest, seed, realization);
     uint64_t n[5] = {0, 0, 0, 0, 0}, c[5] = {0, 0, 0, 0, 0};
     for (int i = 0; i < q; ++i)
         n[i] = n_in[i];
@@ -473,7 +497,7 @@ void oracle_collide_samples(int q, int flip, const uint32_t *tab_p, const uint32
                             const uint32_t *tab_rest, uint64_t seed, uint32_t realization,
                             uint32_t t, const uint64_t *n_in, uint64_t nsamples, uint64_t *c_out)
 {
-    oracle_params pp = {q, flip, tab_p, tab_half, tab_rest, seed, realization};
+    oracle_params pp = make_params(q, flip, tab_p, tab_half, tab_rest, seed, realization);
     uint64_t n[5] = {0, 0, 0, 0, 0};
     for (int i = 0; i < q; ++i)
         n[i] = n_in[i];
@@ -491,7 +515,7 @@ void oracle_binomial_samples(uint64_t n, const uint32_t *table, uint64_t seed, u
 {
     for (uint64_t s = 0; s < nsamples; ++s) {
         draw_stream st;
-        stream_init(&st, seed, (uint32_t)s, 0, 0);
+        stream_init(&st, seed, (uint32_t)s, 0, 0, 10);
         out[s] = binomial(n, table, &st);
     }
 }

@@ -48,6 +48,8 @@ def lib():
         vp = ctypes.c_void_p
         L.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.oracle_philox4x32_10.restype = None
+        L.oracle_philox4x32.argtypes = [u32p, u32p, ctypes.c_int, u32p]
+        L.oracle_philox4x32.restype = None
         L.oracle_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
                                   ctypes.c_uint64, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                   ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, vp, vp,
@@ -103,8 +105,14 @@ def _ptr(a: Optional[np.ndarray]):
 class Params:
     """Fixed-point collision parameters and their exact tables."""
 
-    def __init__(self, q: int, omega: float, theta: float = 1.0 / 3.0, flip: str = "auto"):
+    def __init__(self, q: int, omega: float, theta: float = 1.0 / 3.0, flip: str = "auto",
+                 rounds: int = 10):
+        """rounds: Philox rounds of the step draws, 10 (draw specification
+        v1) or 7 (v2)."""
+        if rounds not in (7, 10):
+            raise ValueError("rounds must be 10 or 7")
         self.q = q
+        self.rounds = rounds
         self.omega = omega
         self.theta = theta
         fp = exact.fixed_point_params(omega, theta, flip, q=q)
@@ -114,6 +122,12 @@ class Params:
         self.tab_p = exact.binomial_table(self.P)
         self.tab_half = _cached_table(self.P_half)
         self.tab_rest = _cached_table(self.P_rest) if q in (3, 5) else None
+
+    @property
+    def flipword(self) -> int:
+        """The C entry points' flip argument: bit 0 the flip, bits 8..15 the
+        Philox round count (0 for 10)."""
+        return int(self.flip) | (0 if self.rounds == 10 else self.rounds << 8)
 
 
 _table_cache = {}
@@ -125,13 +139,13 @@ def _cached_table(P: int):
     return _table_cache[P]
 
 
-def philox(ctr, key) -> np.ndarray:
+def philox(ctr, key, rounds: int = 10) -> np.ndarray:
     c = np.ascontiguousarray(ctr, dtype=np.uint32)
     k = np.ascontiguousarray(key, dtype=np.uint32)
     out = np.zeros(4, dtype=np.uint32)
     u32p = ctypes.POINTER(ctypes.c_uint32)
-    lib().oracle_philox4x32_10(c.ctypes.data_as(u32p), k.ctypes.data_as(u32p),
-                               out.ctypes.data_as(u32p))
+    lib().oracle_philox4x32(c.ctypes.data_as(u32p), k.ctypes.data_as(u32p), rounds,
+                            out.ctypes.data_as(u32p))
     return out
 
 
@@ -150,7 +164,7 @@ def run(params: Params, state: np.ndarray, nsteps: int, seed: int, realization: 
     q, L = s.shape
     assert q == params.q
     hs = np.zeros(max(nsteps, 1), dtype=np.uint64) if hashes else None
-    ov = lib().oracle_run(q, s.dtype.itemsize, L, int(params.flip), _ptr(params.tab_p),
+    ov = lib().oracle_run(q, s.dtype.itemsize, L, params.flipword, _ptr(params.tab_p),
                           _ptr(params.tab_half), _ptr(params.tab_rest), seed, realization, t0,
                           nsteps, _ptr(s), _ptr(hs), nthreads or default_threads())
     return s, (hs[:nsteps] if hashes else None), bool(ov)
@@ -164,7 +178,7 @@ def run2d(params: Params, state: np.ndarray, nsteps: int, seed: int, realization
     q, ly, lx = s.shape
     assert q == 5 and params.q == 5
     hs = np.zeros(max(nsteps, 1), dtype=np.uint64) if hashes else None
-    ov = lib().oracle_run2d(s.dtype.itemsize, lx, ly, int(params.flip), _ptr(params.tab_p),
+    ov = lib().oracle_run2d(s.dtype.itemsize, lx, ly, params.flipword, _ptr(params.tab_p),
                             _ptr(params.tab_half), _ptr(params.tab_rest), seed, realization, t0,
                             nsteps, _ptr(s), _ptr(hs), nthreads or default_threads())
     return s, (hs[:nsteps] if hashes else None), bool(ov)
@@ -176,7 +190,7 @@ def run_window(params: Params, window: np.ndarray, length: int, x0: int, nsteps:
     returns the window after nsteps, valid on [nsteps, W - nsteps)."""
     s = np.array(window, copy=True, order="C")
     q, W = s.shape
-    ov = lib().oracle_run_window(q, s.dtype.itemsize, length, x0, W, int(params.flip),
+    ov = lib().oracle_run_window(q, s.dtype.itemsize, length, x0, W, params.flipword,
                                  _ptr(params.tab_p), _ptr(params.tab_half), _ptr(params.tab_rest),
                                  seed, realization, t0, nsteps, _ptr(s),
                                  nthreads or default_threads())
@@ -188,7 +202,7 @@ def collide_samples(params: Params, n_in, nsamples: int, seed: int, realization:
     n = np.zeros(5, dtype=np.uint64)
     n[:params.q] = n_in
     out = np.zeros((nsamples, params.q), dtype=np.uint64)
-    lib().oracle_collide_samples(params.q, int(params.flip), _ptr(params.tab_p),
+    lib().oracle_collide_samples(params.q, params.flipword, _ptr(params.tab_p),
                                  _ptr(params.tab_half), _ptr(params.tab_rest), seed, realization,
                                  t, _ptr(n), nsamples, _ptr(out))
     return out
