@@ -125,6 +125,26 @@ def bench_plain_mall_free(ilg, W, stream, warmup: int, steps: int = 500):
             "traffic": counter_traffic(spec.length)}
 
 
+def bench_philox7(ilg, W, stream, warmup: int, steps: int = 1000):
+    """Draw specification v2 (7-round Philox) on the headline lattice: the
+    same step with a different, equally valid random stream."""
+    spec, init = W.workload_d1q3_big(steps=steps)
+    lat = ilg.Lattice(spec.q, spec.length, spec.count_bytes, spec.omega, spec.seed, init,
+                      rounds=7)
+    mass0 = int(init.astype(np.int64).sum())
+    lat.step(warmup)
+    sec = timed(stream, lambda: lat.step(steps))
+    if lat.moments()["mass"] != mass0:
+        raise SystemExit("Philox-7: mass not conserved")
+    lat.close()
+    ms = sec * 1e3 / steps
+    alg_bytes = 2 * spec.q * spec.count_bytes * spec.length
+    return {"workload": "same step with 7-round Philox draws (draw specification v2), D1Q3 "
+                        "L=2^24 periodic, uint16, Poisson(50), omega=1.8",
+            "steps": steps, "ms_per_step": ms, "node_updates_per_s": spec.length / (ms / 1e3),
+            "alg_gbs": alg_bytes / (ms / 1e3) / 1e9}
+
+
 def bench_d2q5(ilg, stream, warmup: int, steps: int = 500):
     """The D2Q5 extension: 4096 x 4096 periodic nodes, uint16, Poisson
     occupations drawn on the device (means 25, 25, 50, 25, 25), omega = 1.8."""
@@ -288,8 +308,9 @@ def main():
     ap.add_argument("--length", type=int, default=1 << 24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,mallfree,d2q5,batched,decay,serving",
-                    help="comma list of plain (always), mallfree, d2q5, batched, decay, serving")
+    ap.add_argument("--forms", default="plain,mallfree,philox7,d2q5,batched,decay,serving",
+                    help="comma list of plain (always), mallfree, philox7, d2q5, batched, decay, "
+                         "serving")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
@@ -368,6 +389,9 @@ def main():
     if "mallfree" in forms and spec.length != MALL_FREE_LENGTH:
         say("plain step at 2^26 nodes")
         out["plain_l2p26"] = bench_plain_mall_free(ilg, W, stream, args.warmup)
+    if "philox7" in forms:
+        say("plain step with 7-round draws")
+        out["philox7"] = bench_philox7(ilg, W, stream, args.warmup)
     if "d2q5" in forms:
         say("D2Q5 4096 x 4096")
         out["d2q5"] = bench_d2q5(ilg, stream, args.warmup)

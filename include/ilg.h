@@ -60,6 +60,16 @@ typedef enum ilg_status {
 #define ILG_FLIP_OFF 1u   /* never flip; needs omega <= 1 */
 #define ILG_FLIP_ON 2u    /* always flip; needs omega >= 1 */
 #define ILG_FLIP_MASK 3u
+/* Draw specification v2: the step draws come from Philox4x32 with 7 rounds
+ * instead of 10 (same counters, key and word order); the generator's authors
+ * report that seven rounds pass their statistical test batteries.  A
+ * different but equally valid random stream (the collision law of the
+ * Integer Lattice Gas section is unchanged), with 30% fewer Philox rounds
+ * per node.  Plain form
+ * (ilg_create) only: the batched and serving forms reject it
+ * (ILG_E_INVALID).  Device-drawn initial states keep the 10-round
+ * generator. */
+#define ILG_DRAWS_PHILOX7 4u
 
 /* One lattice run.  Velocity index order is fixed: q = 2 -> v = (-1, +1),
  * q = 3 -> v = (-1, 0, +1), q = 5 -> v = (-1,0), (0,-1), (0,0), (0,+1),
@@ -75,7 +85,7 @@ typedef struct ilg_config {
     uint32_t abi_version; /* ILG_ABI_VERSION */
     uint32_t q;           /* 2, 3 or 5 */
     uint32_t count_bytes; /* 2 (uint16 counts) or 4 (uint32 counts) */
-    uint32_t flags;       /* ILG_FLIP_* */
+    uint32_t flags;       /* one ILG_FLIP_* mode, optionally | ILG_DRAWS_PHILOX7 */
     uint64_t length;      /* L (1D) or Lx (D2Q5), periodic; nodes < 2^31 */
     double omega;         /* target rate omega^j in (0, 2]; with the flip the
                              collision fraction is omega* = 2 - omega, else

@@ -56,6 +56,7 @@ void build_table_set(uint64_t p, uint64_t p_rest, void *host_set);
 
 struct Fixed {
     int flip;
+    int rounds;  // Philox rounds of the step draws: 10 (v1) or 7 (v2)
     uint64_t p, p_half, p_rest;
     double omega_star;
 };
@@ -73,6 +74,7 @@ struct StepArgs {
     uint32_t key0, key1;   // Philox key
     uint32_t flip;
     uint32_t p_zero;       // collision fraction is exactly 0
+    uint32_t rounds;       // Philox rounds of the draws: 10 or 7
     const void *tables;    // device table set
     uint32_t *err;         // sticky error word (bit 0: overflow)
 };

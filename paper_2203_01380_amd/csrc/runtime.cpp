@@ -102,7 +102,7 @@ int check_config(const ilg_config *cfg, Fixed *fx)
         return fail(ILG_E_INVALID, "height must be >= 1 for q = 5 and 0 otherwise");
     if (nodes_of(cfg) >= (uint64_t(1) << 31))
         return fail(ILG_E_INVALID, "the node count must be below 2^31");
-    if ((cfg->flags & ~ILG_FLIP_MASK) != 0)
+    if ((cfg->flags & ~(ILG_FLIP_MASK | ILG_DRAWS_PHILOX7)) != 0)
         return fail(ILG_E_INVALID, "reserved flag bits set");
     if (!(cfg->omega > 0.0 && cfg->omega <= 2.0))
         return fail(ILG_E_INVALID, "omega must lie in (0, 2]");
@@ -137,6 +137,7 @@ int check_config(const ilg_config *cfg, Fixed *fx)
     std::fesetround(FE_TONEAREST);
     const double two32 = 4294967296.0;
     fx->flip = flip ? 1 : 0;
+    fx->rounds = (cfg->flags & ILG_DRAWS_PHILOX7) ? 7 : 10;
     fx->omega_star = omega_star;
     fx->p = (uint64_t)std::nearbyint(omega_star * two32);
     fx->p_half = uint64_t(1) << 31;
@@ -162,6 +163,7 @@ StepArgs step_args(const ilg_handle *h)
     a.key1 = (uint32_t)(h->cfg.seed >> 32);
     a.flip = (uint32_t)h->fx.flip;
     a.p_zero = h->fx.p == 0 ? 1u : 0u;
+    a.rounds = (uint32_t)h->fx.rounds;
     a.tables = h->tables;
     a.err = h->err;
     return a;

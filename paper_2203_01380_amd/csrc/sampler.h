@@ -13,8 +13,9 @@
 //   c_i   = a_i - k_i + m_i   (streamed afterwards to x + v_i)
 // Bin(n, p) takes ceil(n/64) 32-bit draws (full chunks of 64 first, then the
 // remainder); a chunk of m trials with draw U yields #{j < m : T[m][j] <= U}.
-// Draw j of a node-step is word j%4 of Philox4x32-10 block j/4 with counter
-// (x, t, realization, j/4).
+// Draw j of a node-step is word j%4 of Philox4x32 block j/4 with counter
+// (x, t, realization, j/4), the generator taking NR rounds (10: draw
+// specification v1; 7: v2).
 //
 // gfx950 notes.  The work is integer VALU bound (Philox rounds and the
 // inverse-CDF searches):
@@ -58,7 +59,7 @@ __device__ __forceinline__ bool wave_any(bool p)
     return __builtin_amdgcn_ballot_w64(p) != 0ull;
 }
 
-template <int NB>
+template <int NB, int NR>
 struct Draws {
     uint32_t w[4 * NB];
     uint32_t x, t, r, k0, k1;
@@ -69,7 +70,7 @@ struct Draws {
         x = x_; t = t_; r = r_; k0 = k0_; k1 = k1_;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const uint4 o = philox4x32_10(x, t, r, (uint32_t)b, k0, k1);
+            const uint4 o = philox4x32<NR>(x, t, r, (uint32_t)b, k0, k1);
             w[4 * b + 0] = o.x; w[4 * b + 1] = o.y; w[4 * b + 2] = o.z; w[4 * b + 3] = o.w;
         }
     }
@@ -92,8 +93,8 @@ __device__ __forceinline__ uint32_t pick3(bool c2, bool c3, uint32_t a, uint32_t
 }
 
 // Word j of the lane's draw stream (lanes may ask for different j).
-template <int NB>
-__device__ __forceinline__ uint32_t draw_word(const Draws<NB> &d, uint32_t j)
+template <int NB, int NR>
+__device__ __forceinline__ uint32_t draw_word(const Draws<NB, NR> &d, uint32_t j)
 {
     constexpr uint32_t kEager = 4 * NB;
     const uint32_t j0 = __builtin_amdgcn_readfirstlane(j);
@@ -131,7 +132,7 @@ __device__ __forceinline__ uint32_t draw_word(const Draws<NB> &d, uint32_t j)
         }
         if (wave_any(j >= kEager)) {
             if (j >= kEager) {
-                const uint4 o = philox4x32_10(d.x, d.t, d.r, j >> 2, d.k0, d.k1);
+                const uint4 o = philox4x32<NR>(d.x, d.t, d.r, j >> 2, d.k0, d.k1);
                 r = pick4(o.x, o.y, o.z, o.w, j & 3u);
             }
         }
@@ -167,14 +168,14 @@ __device__ __forceinline__ uint32_t chunk_count(const uint32_t *tab, const uint8
 
 // Bin(n, table) with the chunked rule, consuming draws from index j on.
 // p_zero: the probability is 0 (draws are still consumed).
-template <typename W, int NB, int GB>
+template <typename W, int NB, int GB, int NR>
 __device__ __forceinline__ W binomial(W n, uint32_t &j, const uint32_t *tab, const uint8_t *guide,
-                                      bool p_zero, const Draws<NB> &d)
+                                      bool p_zero, const Draws<NB, NR> &d)
 {
     if (!wave_any(n > (W)kChunk)) {
         // at most one chunk per lane
         const bool has = n != 0;
-        const uint32_t u = draw_word<NB>(d, j);
+        const uint32_t u = draw_word(d, j);
         j += has ? 1u : 0u;
         if (p_zero)
             return 0;
@@ -185,7 +186,7 @@ __device__ __forceinline__ W binomial(W n, uint32_t &j, const uint32_t *tab, con
     W total = 0;
     while (n > 0) {
         const uint32_t m = n >= (W)kChunk ? (uint32_t)kChunk : (uint32_t)n;
-        const uint32_t u = draw_word<NB>(d, j);
+        const uint32_t u = draw_word(d, j);
         ++j;
         if (!p_zero)
             total += chunk_count<GB>(tab, guide, m, u);
@@ -255,8 +256,8 @@ __device__ __forceinline__ bool redistribute3(W M, const uint32_t (&u)[4], W (&m
 // extra chunks masked per lane.  Returns false (nothing written) if the
 // redistribution needs more, or m_0 of q = 3 more than one chunk; the caller
 // then takes the generic path from scratch.
-template <int Q, int D1, typename W, int NB, int GB>
-__device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Draws<NB> &d,
+template <int Q, int D1, typename W, int NB, int GB, int NR>
+__device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Draws<NB, NR> &d,
                                           const uint32_t *tab_p, const uint8_t *g_p,
                                           const uint32_t *tab_half, const uint8_t *g_half,
                                           const uint32_t *tab_rest, const uint8_t *g_rest,
@@ -326,8 +327,8 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
 // the later binomials (draws 1 + D1 on) are selected per lane.  The
 // redistribution is as in node_fast.  Returns false (nothing written) where
 // node_fast would, or if a needed word lies beyond the eight computed.
-template <typename W, int NB, int GB>
-__device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Draws<NB> &d,
+template <typename W, int NB, int GB, int NR>
+__device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Draws<NB, NR> &d,
                                           const uint32_t *tab_p, const uint8_t *g_p,
                                           const uint32_t *tab_half, const uint8_t *g_half,
                                           const uint32_t *tab_rest, const uint8_t *g_rest,
@@ -394,8 +395,8 @@ __device__ __forceinline__ W or_all(const W (&c)[Q])
 // Bin(m_y, 1/2) for -y at the next draw (8 if the -x split took one, else 7).
 // Earlier zero counts make the later words irrelevant (M = 0 or R = 0 leaves
 // nothing to split).  Returns false (nothing written) if some lane has M > 64.
-template <typename W, int NB, int GB>
-__device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Draws<NB> &d,
+template <typename W, int NB, int GB, int NR>
+__device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Draws<NB, NR> &d,
                                            const uint32_t *tab_p, const uint8_t *g_p,
                                            const uint32_t *tab_half, const uint8_t *g_half,
                                            const uint32_t *tab_rest, const uint8_t *g_rest,
@@ -449,8 +450,9 @@ template <> struct Wide<uint16_t> { using type = uint32_t; };
 template <> struct Wide<uint32_t> { using type = uint64_t; };
 
 // Full node update: av holds the (already flipped) occupations; cn receives
-// the post-collision counts.  Table pointers are LDS addresses.
-template <int Q, typename W, int NB, int GB>
+// the post-collision counts.  Table pointers are LDS addresses.  NR: Philox
+// rounds of the draws (10 or 7).
+template <int Q, typename W, int NB, int GB, int NR = 10>
 __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32_t x, uint32_t t,
                                             uint32_t r, uint32_t key0, uint32_t key1,
                                             const uint32_t *tab_p, const uint8_t *g_p,
@@ -459,7 +461,7 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
                                             bool p_zero)
 {
     W kv[Q], mv[Q];
-    Draws<NB> d;
+    Draws<NB, NR> d;
     d.init(x, t, r, key0, key1);
     // Common draw layout, decided once per wave for this node slot.
     bool ok = true, two = false, three = false;

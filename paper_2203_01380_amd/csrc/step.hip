@@ -28,7 +28,7 @@ constexpr int kBlock = 1024;
 constexpr int kWgPerCu = 2;
 using sampler::Wide;
 
-template <int Q, typename T, int NB, int GB, int BLOCK, bool FLIP, bool PZ>
+template <int Q, typename T, int NB, int GB, int BLOCK, bool FLIP, bool PZ, int NR>
 __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 {
     using W = typename Wide<T>::type;
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             av[i] = FLIP ? n[Q - 1 - i] : n[i];
-        sampler::node_update<Q, W, NB, GB>(av, cn, x, a.t, a.realization, a.key0, a.key1, tab_p,
+        sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, a.t, a.realization, a.key0, a.key1, tab_p,
                                            g_p, tab_half, g_half, tab_rest, g_rest, PZ);
         ovf |= sampler::or_all<Q, W>(cn);
         if constexpr (Q == 5) {
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         atomicOr(a.err, 1u);
 }
 
-template <int Q, typename T, int NB, bool FLIP, bool PZ>
+template <int Q, typename T, int NB, bool FLIP, bool PZ, int NR>
 hipError_t launch_mode(const StepArgs &a, hipStream_t stream)
 {
     constexpr uint32_t kTile = (uint32_t)kBlock;
@@ -156,21 +156,26 @@ hipError_t launch_mode(const StepArgs &a, hipStream_t stream)
         grid -= grid % kNumXcd;
     if (grid == 0)
         grid = 1;
-    hipLaunchKernelGGL((step_kernel<Q, T, NB, kGuideBits, kBlock, FLIP, PZ>), dim3(grid),
+    hipLaunchKernelGGL((step_kernel<Q, T, NB, kGuideBits, kBlock, FLIP, PZ, NR>), dim3(grid),
                        dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
-// The flip and a zero collision fraction are per-lattice constants, so each
-// combination has its own kernel (no per-node tests for them).
+// The flip, a zero collision fraction and the Philox round count are
+// per-lattice constants, so each combination has its own kernel (no per-node
+// tests for them).  With a zero collision fraction no particle moves whatever
+// the draws are, so that kernel serves both round counts.
 template <int Q, typename T, int NB>
 hipError_t launch_q(const StepArgs &a, hipStream_t stream)
 {
     if (a.p_zero)
-        return a.flip ? launch_mode<Q, T, NB, true, true>(a, stream)
-                      : launch_mode<Q, T, NB, false, true>(a, stream);
-    return a.flip ? launch_mode<Q, T, NB, true, false>(a, stream)
-                  : launch_mode<Q, T, NB, false, false>(a, stream);
+        return a.flip ? launch_mode<Q, T, NB, true, true, 10>(a, stream)
+                      : launch_mode<Q, T, NB, false, true, 10>(a, stream);
+    if (a.rounds == 7)
+        return a.flip ? launch_mode<Q, T, NB, true, false, 7>(a, stream)
+                      : launch_mode<Q, T, NB, false, false, 7>(a, stream);
+    return a.flip ? launch_mode<Q, T, NB, true, false, 10>(a, stream)
+                  : launch_mode<Q, T, NB, false, false, 10>(a, stream);
 }
 
 }  // namespace
