@@ -187,7 +187,10 @@ void batch_kernel(BatchArgs a)
         if (threadIdx.x == 0)
             s_next = atomicAdd(a.queue, 1u);
         __syncthreads();
-        const uint32_t idx = s_next;
+        // Uniform across the workgroup: reading it into a scalar register
+        // makes the member's descriptor (key, step, rates) scalar loads, and
+        // keeps the Philox key schedule out of vector registers.
+        const uint32_t idx = __builtin_amdgcn_readfirstlane(s_next);
         if (idx >= a.nreal)
             break;
         const uint32_t r = a.order[idx];

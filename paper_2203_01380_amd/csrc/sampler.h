@@ -153,12 +153,7 @@ __device__ __forceinline__ uint32_t chunk_count(const uint32_t *tab, const uint8
 {
     const uint32_t *row = tab + dev_row_offset(m);
     const uint32_t g = guide[((m - 1u) << GB) + (u >> (32 - GB))];
-    // Byte offset of entry g: 4 dev_row_offset(m) = 2m^2 + 6m - 8, one
-    // 24-bit multiply-add, then one shift-add for g.
-    const uint32_t rowb = __umul24(m, 2u * m + 6u) - 8u;
-    const uint32_t *pg = reinterpret_cast<const uint32_t *>(
-        reinterpret_cast<const uint8_t *>(tab) + (rowb + (g << 2)));
-    const uint32_t t0 = pg[0], t1 = pg[1];
+    const uint32_t t0 = row[g], t1 = row[g + 1u];
     const bool s1 = t1 <= u;
     uint32_t c = g + (t0 <= u ? 1u : 0u) + (s1 ? 1u : 0u);
     if (wave_any(s1)) {

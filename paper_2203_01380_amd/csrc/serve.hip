@@ -103,9 +103,13 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             av[i] = (W)in[(uint64_t)(sl.flip ? Q - 1 - i : i) * pitch + x];
-        sampler::node_update<Q, W, NB, GB>(av, cn, x, sl.t0 + a.j, sl.realization, sl.key0,
-                                           sl.key1, tab_p, g_p, tab_half, g_half, tab_rest,
-                                           g_rest, sl.p_zero != 0);
+        // The key words are uniform; saying so keeps their round schedule in
+        // scalar registers (as operands of the Philox xors).
+        const uint32_t key0 = __builtin_amdgcn_readfirstlane(sl.key0);
+        const uint32_t key1 = __builtin_amdgcn_readfirstlane(sl.key1);
+        sampler::node_update<Q, W, NB, GB>(av, cn, x, sl.t0 + a.j, sl.realization, key0, key1,
+                                           tab_p, g_p, tab_half, g_half, tab_rest, g_rest,
+                                           sl.p_zero != 0);
         ovf |= sampler::or_all<Q, W>(cn);
         const uint32_t xm = (x == 0) ? L - 1 : x - 1;
         const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
