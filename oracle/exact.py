@@ -102,7 +102,11 @@ def fixed_point_params(omega: float, theta: float = 1.0 / 3.0, flip: str = "auto
         if not (0.0 < theta < 1.0):
             raise ValueError("theta must lie in (0, 1)")
         P_rest = round((1.0 - theta) * float(TWO32))
-    return dict(flip=do_flip, omega_star=omega_star, P=int(P), P_half=1 << 31, P_rest=int(P_rest))
+    # D1Q2 exchange form: crossing probability omega*/2, i.e.
+    # round-half-even(omega* 2^31) in the same fixed point.
+    P_x = round(omega_star * float(1 << 31))
+    return dict(flip=do_flip, omega_star=omega_star, P=int(P), P_half=1 << 31, P_rest=int(P_rest),
+                P_x=int(P_x))
 
 
 # ------------------------------------------------------ fixed-point tables
@@ -232,6 +236,22 @@ def collision_law_particles(n_in: Sequence[int], q: int, P: int, P_rest: int,
                 kk = tuple(x + y for x, y in zip(k1, k2))
                 nxt[kk] = nxt.get(kk, Fraction(0)) + p1 * p2
         law = nxt
+    return law
+
+
+def collision_law_exchange(n_in: Sequence[int], P_x: int, flip: bool) -> Dict[tuple, Fraction]:
+    """Exact law of the D1Q2 post-collision counts when every particle
+    crosses to the opposite velocity with probability P_x / 2^32, independently
+    (the flip applied first)."""
+    a = list(reversed(n_in)) if flip else list(n_in)
+    px = Fraction(P_x, TWO32)
+    bx = ideal_binomial_pmf(a[0], px)
+    by = ideal_binomial_pmf(a[1], px)
+    law: Dict[tuple, Fraction] = {}
+    for X, pX in enumerate(bx):
+        for Y, pY in enumerate(by):
+            c = (a[0] - X + Y, a[1] - Y + X)
+            law[c] = law.get(c, Fraction(0)) + pX * pY
     return law
 
 

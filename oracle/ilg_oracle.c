@@ -34,6 +34,14 @@
  * others to the x or the y pair with probability 1/2 and then to either
  * direction of the pair with probability 1/2 (conditional binomials, drawn
  * in that order).  Nodes are numbered x + Lx y.
+ * D1Q2 exchange form (draw specification v3, a reformulation of the same
+ * collision): a particle of either velocity is removed with probability p
+ * and then sent to each velocity with probability 1/2, so it ends on the
+ * opposite velocity with probability p/2, independently of the others.  The
+ * exchange form draws that directly: X = Bin(a_-, p_x) particles cross from
+ * -1 to +1, then Y = Bin(a_+, p_x) from +1 to -1, with p_x the fixed-point
+ * crossing probability round(omega* 2^31) / 2^32 (two binomials per node
+ * instead of three); c_- = a_- - X + Y, c_+ = a_+ - Y + X.
  * Draws (specification v1): Philox4x32-10 (Salmon, Moraes, Dror & Shaw,
  * SC'11); v2 uses the same generator with 7 rounds.  Key = the 64-bit
  * seed split into two 32-bit words (low word first), counter =
@@ -158,18 +166,20 @@ typedef struct {
     uint64_t seed;
     uint32_t realization;
     int rounds;                /* Philox rounds of the step draws */
+    int exchange;              /* D1Q2 exchange form; tab_p is then the table
+                                  of the crossing probability p_x */
 } oracle_params;
 
-/* The `flip` word of the entry points: bit 0 applies the flip; bits 8..15
- * give the Philox round count of the step draws (0 means 10, the draw
- * specification v1; 7 selects v2). */
+/* The `flip` word of the entry points: bit 0 applies the flip; bit 1 selects
+ * the D1Q2 exchange form; bits 8..15 give the Philox round count of the step
+ * draws (0 means 10, the draw specification v1; 7 selects v2). */
 static oracle_params make_params(int q, int flipword, const uint32_t *tab_p,
                                  const uint32_t *tab_half, const uint32_t *tab_rest,
                                  uint64_t seed, uint32_t realization)
 {
     const int rounds = (flipword >> 8) & 0xFF;
     oracle_params pp = {q, flipword & 1, tab_p, tab_half, tab_rest, seed, realization,
-                        rounds ? rounds : 10};
+                        rounds ? rounds : 10, q == 2 && ((flipword >> 1) & 1)};
     return pp;
 }
 
@@ -187,6 +197,16 @@ static void collide_node(const oracle_params *pp, const uint64_t n_in[5], uint32
      * of index i is q-1-i (in 2D: -x <-> +x, -y <-> +y, rest fixed). */
     for (int i = 0; i < q; ++i)
         a[i] = pp->flip ? n_in[q - 1 - i] : n_in[i];
+
+    if (pp->exchange) {
+        /* D1Q2 exchange form: X particles cross from -1 to +1, Y from +1 to
+         * -1, each particle independently with probability p_x. */
+        const uint64_t X = binomial(a[0], pp->tab_p, &s);
+        const uint64_t Y = binomial(a[1], pp->tab_p, &s);
+        c_out[0] = a[0] - X + Y;
+        c_out[1] = a[1] - Y + X;
+        return;
+    }
 
     /* Each particle of velocity i collides with probability p. */
     uint64_t M = 0;

@@ -106,28 +106,35 @@ class Params:
     """Fixed-point collision parameters and their exact tables."""
 
     def __init__(self, q: int, omega: float, theta: float = 1.0 / 3.0, flip: str = "auto",
-                 rounds: int = 10):
+                 rounds: int = 10, exchange: bool = False):
         """rounds: Philox rounds of the step draws, 10 (draw specification
-        v1) or 7 (v2)."""
+        v1) or 7 (v2).  exchange: the D1Q2 exchange form (specification v3):
+        two crossing binomials with probability P_x = round(omega* 2^31),
+        whose table replaces tab_p."""
         if rounds not in (7, 10):
             raise ValueError("rounds must be 10 or 7")
+        if exchange and q != 2:
+            raise ValueError("the exchange form is defined for D1Q2")
         self.q = q
         self.rounds = rounds
+        self.exchange = exchange
         self.omega = omega
         self.theta = theta
         fp = exact.fixed_point_params(omega, theta, flip, q=q)
         self.flip = fp["flip"]
         self.omega_star = fp["omega_star"]
         self.P, self.P_half, self.P_rest = fp["P"], fp["P_half"], fp["P_rest"]
-        self.tab_p = exact.binomial_table(self.P)
+        self.P_x = fp["P_x"]
+        self.tab_p = exact.binomial_table(self.P_x if exchange else self.P)
         self.tab_half = _cached_table(self.P_half)
         self.tab_rest = _cached_table(self.P_rest) if q in (3, 5) else None
 
     @property
     def flipword(self) -> int:
-        """The C entry points' flip argument: bit 0 the flip, bits 8..15 the
-        Philox round count (0 for 10)."""
-        return int(self.flip) | (0 if self.rounds == 10 else self.rounds << 8)
+        """The C entry points' flip argument: bit 0 the flip, bit 1 the
+        exchange form, bits 8..15 the Philox round count (0 for 10)."""
+        return (int(self.flip) | (2 if self.exchange else 0)
+                | (0 if self.rounds == 10 else self.rounds << 8))
 
 
 _table_cache = {}
