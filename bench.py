@@ -7,7 +7,9 @@ state is resident in HBM before timing; timing uses HIP events on the stream
 the kernels run on.
 
 Also reported (extra JSON objects): the same step on a 2^26-node lattice
-(state larger than the MALL), the D2Q5 extension on 4096 x 4096 nodes, the
+(state larger than the MALL), the same step with 7-round Philox draws, D1Q2
+on 2^24 nodes with three binomials and in the exchange form, the D2Q5
+extension on 4096 x 4096 nodes, the
 batched ensemble form on the ragged
 D1Q2 ensemble (4096 members, L log-uniform in [64, 8192], 5000 steps, S(k)
 every 10 steps) against the plain per-realization loop on a sample of the same
@@ -143,6 +145,28 @@ def bench_philox7(ilg, W, stream, warmup: int, steps: int = 1000):
                         "L=2^24 periodic, uint16, Poisson(50), omega=1.8",
             "steps": steps, "ms_per_step": ms, "node_updates_per_s": spec.length / (ms / 1e3),
             "alg_gbs": alg_bytes / (ms / 1e3) / 1e9}
+
+
+def bench_exchange(ilg, W, stream, warmup: int, steps: int = 1000):
+    """D1Q2, L = 2^24, uint16, Poisson(40), omega = 1.5: the three-binomial
+    collision against the exchange form (draw specification v3, two
+    crossing binomials per node)."""
+    L = 1 << 24
+    init = W.init_poisson_iid(2, L, 40.0, 2, init_seed=7)
+    mass0 = int(init.astype(np.int64).sum())
+    out = {"workload": "D1Q2 with flip, L=2^24 periodic, uint16, Poisson(40), omega=1.5",
+           "steps": steps}
+    for name, ex in (("three_binomials", False), ("exchange", True)):
+        lat = ilg.Lattice(2, L, 2, 1.5, 1, init, exchange=ex)
+        lat.step(warmup)
+        sec = timed(stream, lambda: lat.step(steps))
+        if lat.moments()["mass"] != mass0:
+            raise SystemExit("D1Q2: mass not conserved")
+        lat.close()
+        ms = sec * 1e3 / steps
+        out[name] = {"ms_per_step": ms, "node_updates_per_s": L / (ms / 1e3),
+                     "alg_gbs": 2 * 2 * 2 * L / (ms / 1e3) / 1e9}
+    return out
 
 
 def bench_d2q5(ilg, stream, warmup: int, steps: int = 500):
@@ -308,9 +332,9 @@ def main():
     ap.add_argument("--length", type=int, default=1 << 24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,mallfree,philox7,d2q5,batched,decay,serving",
-                    help="comma list of plain (always), mallfree, philox7, d2q5, batched, decay, "
-                         "serving")
+    ap.add_argument("--forms", default="plain,mallfree,philox7,exchange,d2q5,batched,decay,serving",
+                    help="comma list of plain (always), mallfree, philox7, exchange, d2q5, "
+                         "batched, decay, serving")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
@@ -392,6 +416,9 @@ def main():
     if "philox7" in forms:
         say("plain step with 7-round draws")
         out["philox7"] = bench_philox7(ilg, W, stream, args.warmup)
+    if "exchange" in forms:
+        say("D1Q2: three binomials against the exchange form")
+        out["d1q2_exchange"] = bench_exchange(ilg, W, stream, args.warmup)
     if "d2q5" in forms:
         say("D2Q5 4096 x 4096")
         out["d2q5"] = bench_d2q5(ilg, stream, args.warmup)

@@ -70,6 +70,16 @@ typedef enum ilg_status {
  * (ILG_E_INVALID).  Device-drawn initial states keep the 10-round
  * generator. */
 #define ILG_DRAWS_PHILOX7 4u
+/* Draw specification v3, D1Q2 only: the exchange form of the same collision.
+ * A particle removed with probability omega* and sent to either velocity with
+ * probability 1/2 ends on the opposite velocity with probability omega* / 2;
+ * the step draws the crossing counts directly, X = Bin(a_-, p_x) from -1 to
+ * +1 and then Y = Bin(a_+, p_x) from +1 to -1 (chunked as every binomial),
+ * with p_x = round-half-even(omega* 2^31) / 2^32, and sets c_- = a_- - X + Y,
+ * c_+ = a_+ - Y + X: two binomials per node instead of three.  Combines with
+ * ILG_DRAWS_PHILOX7.  Plain form (ilg_create) only; other q and the batched
+ * and serving forms reject it (ILG_E_INVALID). */
+#define ILG_DRAWS_EXCHANGE 8u
 
 /* One lattice run.  Velocity index order is fixed: q = 2 -> v = (-1, +1),
  * q = 3 -> v = (-1, 0, +1), q = 5 -> v = (-1,0), (0,-1), (0,0), (0,+1),
@@ -85,7 +95,8 @@ typedef struct ilg_config {
     uint32_t abi_version; /* ILG_ABI_VERSION */
     uint32_t q;           /* 2, 3 or 5 */
     uint32_t count_bytes; /* 2 (uint16 counts) or 4 (uint32 counts) */
-    uint32_t flags;       /* one ILG_FLIP_* mode, optionally | ILG_DRAWS_PHILOX7 */
+    uint32_t flags;       /* one ILG_FLIP_* mode, optionally | ILG_DRAWS_PHILOX7
+                             | ILG_DRAWS_EXCHANGE */
     uint64_t length;      /* L (1D) or Lx (D2Q5), periodic; nodes < 2^31 */
     double omega;         /* target rate omega^j in (0, 2]; with the flip the
                              collision fraction is omega* = 2 - omega, else
@@ -102,7 +113,9 @@ typedef struct ilg_config {
 typedef struct ilg_fixed {
     uint32_t flip;     /* 1 if the flip is applied */
     uint32_t q;
-    uint64_t p;        /* round-half-even(omega* 2^32), in [0, 2^32] */
+    uint64_t p;        /* round-half-even(omega* 2^32), in [0, 2^32]; with
+                          ILG_DRAWS_EXCHANGE the crossing probability
+                          round-half-even(omega* 2^31) */
     uint64_t p_half;   /* 2^31 */
     uint64_t p_rest;   /* round-half-even(w_rest 2^32): 1 - theta (q = 3),
                           1 - 2 theta (q = 5) */

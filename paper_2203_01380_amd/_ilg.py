@@ -20,6 +20,7 @@ MAX_K = 64
 TABLE_ENTRIES = 2080
 FLIP_MODES = {"auto": 0, "off": 1, "on": 2}
 DRAWS_PHILOX7 = 4  # draw specification v2 (7-round Philox), plain form only
+DRAWS_EXCHANGE = 8  # draw specification v3 (D1Q2 exchange form), plain form only
 STATUS = {0: "ILG_OK", -1: "ILG_E_INVALID", -2: "ILG_E_NOMEM", -3: "ILG_E_DEVICE",
           -4: "ILG_E_OVERFLOW", -5: "ILG_E_RANGE", -6: "ILG_E_BUSY"}
 
@@ -143,13 +144,15 @@ def check(rc: int):
 
 def make_config(q: int, length: int, count_bytes: int, omega: float, seed: int,
                 realization: int = 0, t0: int = 0, theta: float = 0.0,
-                flip: str = "auto", height: int = 0, rounds: int = 10) -> IlgConfig:
+                flip: str = "auto", height: int = 0, rounds: int = 10,
+                exchange: bool = False) -> IlgConfig:
     """height: rows Ly of a D2Q5 lattice (q = 5, length = Lx); 0 otherwise.
     rounds: Philox rounds of the step draws, 10 (draw specification v1) or 7
-    (v2)."""
+    (v2).  exchange: the D1Q2 exchange form (v3)."""
     if rounds not in (7, 10):
         raise ValueError("rounds must be 10 or 7")
-    flags = FLIP_MODES[flip] | (DRAWS_PHILOX7 if rounds == 7 else 0)
+    flags = (FLIP_MODES[flip] | (DRAWS_PHILOX7 if rounds == 7 else 0)
+             | (DRAWS_EXCHANGE if exchange else 0))
     return IlgConfig(ABI_VERSION, q, count_bytes, flags, length, omega, theta, seed,
                      realization, height, t0)
 
@@ -180,12 +183,13 @@ class Lattice:
     def __init__(self, q: int, length: int, count_bytes: int, omega: float, seed: int,
                  init: Optional[np.ndarray], realization: int = 0, t0: int = 0,
                  theta: float = 0.0, flip: str = "auto", use_torch: bool = True, stream=None,
-                 height: int = 0, rounds: int = 10):
+                 height: int = 0, rounds: int = 10, exchange: bool = False):
         """init: [q][L] host counts (D2Q5: [5][height][length]), or None for an
         all-zero state (then call init_poisson_sine to draw the initial state
-        on the device).  rounds: 10 or 7 Philox rounds for the step draws."""
+        on the device).  rounds: 10 or 7 Philox rounds for the step draws;
+        exchange: the D1Q2 exchange form."""
         self.cfg = make_config(q, length, count_bytes, omega, seed, realization, t0, theta, flip,
-                               height, rounds)
+                               height, rounds, exchange)
         self.q, self.length, self.count_bytes = q, length, count_bytes
         self.height = height
         self.shape = (q, height, length) if q == 5 else (q, length)
@@ -308,7 +312,7 @@ class Batch:
             cfgs[r] = make_config(m["q"], m["length"], m["count_bytes"], m["omega"], m["seed"],
                                   m.get("realization", 0), m.get("t0", 0), m.get("theta", 0.0),
                                   m.get("flip", "auto"), m.get("height", 0),
-                                  m.get("rounds", 10))
+                                  m.get("rounds", 10), m.get("exchange", False))
             a = np.ascontiguousarray(init, dtype=_dtype(m["count_bytes"]))
             if a.shape != (m["q"], m["length"]):
                 raise ValueError(f"member {r}: init shape {a.shape}")
@@ -399,7 +403,8 @@ class Server:
         cfg = make_config(member["q"], member["length"], member["count_bytes"], member["omega"],
                           member["seed"], member.get("realization", 0), member.get("t0", 0),
                           member.get("theta", 0.0), member.get("flip", "auto"),
-                          member.get("height", 0), member.get("rounds", 10))
+                          member.get("height", 0), member.get("rounds", 10),
+                          member.get("exchange", False))
         a = np.ascontiguousarray(init, dtype=_dtype(member["count_bytes"]))
         if a.shape != (member["q"], member["length"]):
             raise ValueError(f"init shape {a.shape}")
@@ -416,7 +421,8 @@ class Server:
         cfg = make_config(member["q"], member["length"], member["count_bytes"], member["omega"],
                           member["seed"], member.get("realization", 0), member.get("t0", 0),
                           member.get("theta", 0.0), member.get("flip", "auto"),
-                          member.get("height", 0), member.get("rounds", 10))
+                          member.get("height", 0), member.get("rounds", 10),
+                          member.get("exchange", False))
         rid = ctypes.c_uint64()
         check(lib.ilg_server_submit_poisson_sine(self._h, ctypes.byref(cfg), float(nave),
                                                  float(amp), int(init_seed), nsteps,

@@ -138,6 +138,8 @@ int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *
             return bfail(ILG_E_INVALID, "D2Q5 lattices run in the plain form only");
         if (fx[r].rounds != 10)
             return bfail(ILG_E_INVALID, "7-round draws run in the plain form only");
+        if (fx[r].exchange)
+            return bfail(ILG_E_INVALID, "the exchange form runs in the plain form only");
         if (!inits[r])
             return bfail(ILG_E_INVALID, "null initial state");
         if (cfgs[r].q != cfgs[0].q || cfgs[r].count_bytes != cfgs[0].count_bytes ||

@@ -56,7 +56,8 @@ void build_table_set(uint64_t p, uint64_t p_rest, void *host_set);
 
 struct Fixed {
     int flip;
-    int rounds;  // Philox rounds of the step draws: 10 (v1) or 7 (v2)
+    int rounds;    // Philox rounds of the step draws: 10 (v1) or 7 (v2)
+    int exchange;  // D1Q2 exchange form (v3): p is the crossing probability
     uint64_t p, p_half, p_rest;
     double omega_star;
 };
@@ -75,6 +76,7 @@ struct StepArgs {
     uint32_t flip;
     uint32_t p_zero;       // collision fraction is exactly 0
     uint32_t rounds;       // Philox rounds of the draws: 10 or 7
+    uint32_t exchange;     // D1Q2 exchange form: two crossing binomials
     const void *tables;    // device table set
     uint32_t *err;         // sticky error word (bit 0: overflow)
 };

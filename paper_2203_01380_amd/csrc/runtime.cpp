@@ -102,8 +102,10 @@ int check_config(const ilg_config *cfg, Fixed *fx)
         return fail(ILG_E_INVALID, "height must be >= 1 for q = 5 and 0 otherwise");
     if (nodes_of(cfg) >= (uint64_t(1) << 31))
         return fail(ILG_E_INVALID, "the node count must be below 2^31");
-    if ((cfg->flags & ~(ILG_FLIP_MASK | ILG_DRAWS_PHILOX7)) != 0)
+    if ((cfg->flags & ~(ILG_FLIP_MASK | ILG_DRAWS_PHILOX7 | ILG_DRAWS_EXCHANGE)) != 0)
         return fail(ILG_E_INVALID, "reserved flag bits set");
+    if ((cfg->flags & ILG_DRAWS_EXCHANGE) && cfg->q != 2)
+        return fail(ILG_E_INVALID, "the exchange form is defined for q = 2");
     if (!(cfg->omega > 0.0 && cfg->omega <= 2.0))
         return fail(ILG_E_INVALID, "omega must lie in (0, 2]");
     if (cfg->t0 > 0xFFFFFFFFull)
@@ -139,7 +141,9 @@ int check_config(const ilg_config *cfg, Fixed *fx)
     fx->flip = flip ? 1 : 0;
     fx->rounds = (cfg->flags & ILG_DRAWS_PHILOX7) ? 7 : 10;
     fx->omega_star = omega_star;
-    fx->p = (uint64_t)std::nearbyint(omega_star * two32);
+    fx->exchange = (cfg->flags & ILG_DRAWS_EXCHANGE) ? 1 : 0;
+    // exchange form: the crossing probability omega* / 2 (omega* 2^31 is exact)
+    fx->p = (uint64_t)std::nearbyint(omega_star * (fx->exchange ? two32 / 2.0 : two32));
     fx->p_half = uint64_t(1) << 31;
     fx->p_rest = cfg->q == 3   ? (uint64_t)std::nearbyint((1.0 - theta) * two32)
                  : cfg->q == 5 ? (uint64_t)std::nearbyint((1.0 - 2.0 * theta) * two32)
@@ -164,6 +168,7 @@ StepArgs step_args(const ilg_handle *h)
     a.flip = (uint32_t)h->fx.flip;
     a.p_zero = h->fx.p == 0 ? 1u : 0u;
     a.rounds = (uint32_t)h->fx.rounds;
+    a.exchange = (uint32_t)h->fx.exchange;
     a.tables = h->tables;
     a.err = h->err;
     return a;

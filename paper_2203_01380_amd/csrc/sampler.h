@@ -527,5 +527,36 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
     }
 }
 
+// D1Q2 exchange form (draw specification v3): av holds the (flipped)
+// occupations a_-, a_+; X = Bin(a_-, p_x) particles cross to +1, then
+// Y = Bin(a_+, p_x) cross to -1 (tab_p/g_p are the crossing probability's
+// table and guide).  When every lane has both counts in 1..64 the two draws
+// are words 0 and 1; otherwise the generic chunked binomials.
+template <typename W, int NB, int GB, int NR = 10>
+__device__ __forceinline__ void node_exchange(const W (&av)[2], W (&cn)[2], uint32_t x, uint32_t t,
+                                              uint32_t r, uint32_t key0, uint32_t key1,
+                                              const uint32_t *tab_p, const uint8_t *g_p,
+                                              bool p_zero)
+{
+    Draws<NB, NR> d;
+    d.init(x, t, r, key0, key1);
+    const bool ok = av[0] >= 1 && av[0] <= (W)kChunk && av[1] >= 1 && av[1] <= (W)kChunk;
+    W X, Y;
+    if (!wave_any(!ok)) {
+        if (p_zero) {
+            X = Y = 0;
+        } else {
+            X = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[0], d.w[0]);
+            Y = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[1], d.w[1]);
+        }
+    } else {
+        uint32_t j = 0;
+        X = binomial<W, NB, GB>(av[0], j, tab_p, g_p, p_zero, d);
+        Y = binomial<W, NB, GB>(av[1], j, tab_p, g_p, p_zero, d);
+    }
+    cn[0] = av[0] - X + Y;
+    cn[1] = av[1] - Y + X;
+}
+
 }  // namespace sampler
 }  // namespace ilg

@@ -382,6 +382,8 @@ int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_hos
         return sfail(ILG_E_INVALID, "D2Q5 lattices run in the plain form only");
     if (fx.rounds != 10)
         return sfail(ILG_E_INVALID, "7-round draws run in the plain form only");
+    if (fx.exchange)
+        return sfail(ILG_E_INVALID, "the exchange form runs in the plain form only");
     if (nsteps == 0)
         return sfail(ILG_E_INVALID, "nsteps must be positive");
     if (cfg->t0 + nsteps > (uint64_t(1) << 32))
@@ -417,6 +419,8 @@ int ilg_server_submit_poisson_sine(ilg_server *s, const ilg_config *cfg, double 
         return sfail(ILG_E_INVALID, "D2Q5 lattices run in the plain form only");
     if (fx.rounds != 10)
         return sfail(ILG_E_INVALID, "7-round draws run in the plain form only");
+    if (fx.exchange)
+        return sfail(ILG_E_INVALID, "the exchange form runs in the plain form only");
     if (nsteps == 0)
         return sfail(ILG_E_INVALID, "nsteps must be positive");
     if (cfg->t0 + nsteps > (uint64_t(1) << 32))

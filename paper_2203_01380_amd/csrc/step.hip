@@ -28,7 +28,8 @@ constexpr int kBlock = 1024;
 constexpr int kWgPerCu = 2;
 using sampler::Wide;
 
-template <int Q, typename T, int NB, int GB, int BLOCK, bool FLIP, bool PZ, int NR>
+// EX: the D1Q2 exchange form (Q = 2 only).
+template <int Q, typename T, int NB, int GB, int BLOCK, bool FLIP, bool PZ, int NR, bool EX>
 __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 {
     using W = typename Wide<T>::type;
@@ -103,8 +104,15 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             av[i] = FLIP ? n[Q - 1 - i] : n[i];
-        sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, a.t, a.realization, a.key0, a.key1, tab_p,
-                                           g_p, tab_half, g_half, tab_rest, g_rest, PZ);
+        if constexpr (EX) {
+            static_assert(Q == 2, "the exchange form is defined for D1Q2");
+            sampler::node_exchange<W, NB, GB, NR>(av, cn, x, a.t, a.realization, a.key0, a.key1,
+                                                  tab_p, g_p, PZ);
+        } else {
+            sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, a.t, a.realization, a.key0, a.key1,
+                                                   tab_p, g_p, tab_half, g_half, tab_rest, g_rest,
+                                                   PZ);
+        }
         ovf |= sampler::or_all<Q, W>(cn);
         if constexpr (Q == 5) {
             // D2Q5 streaming on the node index x + Lx y (periodic in both):
@@ -141,7 +149,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         atomicOr(a.err, 1u);
 }
 
-template <int Q, typename T, int NB, bool FLIP, bool PZ, int NR>
+template <int Q, typename T, int NB, bool FLIP, bool PZ, int NR, bool EX = false>
 hipError_t launch_mode(const StepArgs &a, hipStream_t stream)
 {
     constexpr uint32_t kTile = (uint32_t)kBlock;
@@ -156,15 +164,26 @@ hipError_t launch_mode(const StepArgs &a, hipStream_t stream)
         grid -= grid % kNumXcd;
     if (grid == 0)
         grid = 1;
-    hipLaunchKernelGGL((step_kernel<Q, T, NB, kGuideBits, kBlock, FLIP, PZ, NR>), dim3(grid),
+    hipLaunchKernelGGL((step_kernel<Q, T, NB, kGuideBits, kBlock, FLIP, PZ, NR, EX>), dim3(grid),
                        dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
-// The flip, a zero collision fraction and the Philox round count are
-// per-lattice constants, so each combination has its own kernel (no per-node
-// tests for them).  With a zero collision fraction no particle moves whatever
-// the draws are, so that kernel serves both round counts.
+// The flip, a zero collision fraction, the Philox round count and the D1Q2
+// exchange form are per-lattice constants, so each combination has its own
+// kernel (no per-node tests for them).  With a zero collision fraction no
+// particle moves whatever the draws are, so that kernel serves every round
+// count and both D1Q2 forms.
+template <int Q, typename T, int NB, bool FLIP, int NR>
+hipError_t launch_ex(const StepArgs &a, hipStream_t stream)
+{
+    if constexpr (Q == 2) {
+        if (a.exchange)
+            return launch_mode<Q, T, NB, FLIP, false, NR, true>(a, stream);
+    }
+    return launch_mode<Q, T, NB, FLIP, false, NR>(a, stream);
+}
+
 template <int Q, typename T, int NB>
 hipError_t launch_q(const StepArgs &a, hipStream_t stream)
 {
@@ -172,10 +191,10 @@ hipError_t launch_q(const StepArgs &a, hipStream_t stream)
         return a.flip ? launch_mode<Q, T, NB, true, true, 10>(a, stream)
                       : launch_mode<Q, T, NB, false, true, 10>(a, stream);
     if (a.rounds == 7)
-        return a.flip ? launch_mode<Q, T, NB, true, false, 7>(a, stream)
-                      : launch_mode<Q, T, NB, false, false, 7>(a, stream);
-    return a.flip ? launch_mode<Q, T, NB, true, false, 10>(a, stream)
-                  : launch_mode<Q, T, NB, false, false, 10>(a, stream);
+        return a.flip ? launch_ex<Q, T, NB, true, 7>(a, stream)
+                      : launch_ex<Q, T, NB, false, 7>(a, stream);
+    return a.flip ? launch_ex<Q, T, NB, true, 10>(a, stream)
+                  : launch_ex<Q, T, NB, false, 10>(a, stream);
 }
 
 }  // namespace
