@@ -169,6 +169,7 @@ void batch_kernel(BatchArgs a)
     __shared__ double s_red[kWaves];
     __shared__ unsigned long long s_redu[kWaves];
 
+    sampler::stage_row_offsets();
     // Shared tables (P = 2^31 and, for q = 3, P_rest) and their guides, once.
     for (int i = threadIdx.x; i < (kTabs - 1) * kDevTableEntries; i += BLOCK)
         s_tab[kDevTableEntries + i] = a.tabs_shared[i];

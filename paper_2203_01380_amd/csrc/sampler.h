@@ -147,13 +147,27 @@ __device__ __forceinline__ uint32_t draw_word(const Draws<NB, NR> &d, uint32_t j
 // (past the row they are all-ones sentinels), so the two probes need no bound
 // test, and entry g + 1 <= u implies entry g <= u.  A sentinel compares <= u
 // only for u = 2^32 - 1, where the final clamp to m gives the right count.
+// Byte offset of row m in a padded device table, 4 dev_row_offset(m), for
+// m = 1..64 (entry 0 unused): one LDS word read in place of the multiply
+// and shifts, issued alongside the guide read.  Every kernel that runs the
+// sampler fills it with stage_row_offsets() before its first barrier.
+static __shared__ uint32_t s_row_bytes[kChunk + 1];
+
+__device__ __forceinline__ void stage_row_offsets()
+{
+    for (uint32_t m = threadIdx.x; m <= (uint32_t)kChunk; m += blockDim.x)
+        s_row_bytes[m] = m == 0 ? 0u : dev_row_offset(m) * 4u;
+}
+
 template <int GB>
 __device__ __forceinline__ uint32_t chunk_count(const uint32_t *tab, const uint8_t *guide,
                                                 uint32_t m, uint32_t u)
 {
     const uint32_t *row = tab + dev_row_offset(m);
     const uint32_t g = guide[((m - 1u) << GB) + (u >> (32 - GB))];
-    const uint32_t t0 = row[g], t1 = row[g + 1u];
+    const uint32_t *pg = reinterpret_cast<const uint32_t *>(
+        reinterpret_cast<const uint8_t *>(tab) + (s_row_bytes[m] + (g << 2)));
+    const uint32_t t0 = pg[0], t1 = pg[1];
     const bool s1 = t1 <= u;
     uint32_t c = g + (t0 <= u ? 1u : 0u) + (s1 ? 1u : 0u);
     if (wave_any(s1)) {

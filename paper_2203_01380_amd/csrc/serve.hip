@@ -34,6 +34,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     uint32_t *s_tab = reinterpret_cast<uint32_t *>(s_lds);
     uint8_t *s_guide = s_lds + kTabBytes;
 
+    sampler::stage_row_offsets();
     // shared half table (slot 1 in LDS) and its guide
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.shared);

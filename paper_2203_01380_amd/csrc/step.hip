@@ -44,6 +44,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     uint8_t *s_guide = s_lds + kTabBytes;
 
     // Stage tables (16-byte copies) and the 2^GB-bucket view of the guides.
+    sampler::stage_row_offsets();
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.tables);
         uint4 *dst = reinterpret_cast<uint4 *>(s_tab);
