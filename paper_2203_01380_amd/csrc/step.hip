@@ -29,6 +29,21 @@ constexpr int kWgPerCu = 2;
 using sampler::Wide;
 
 // EX: the D1Q2 exchange form (Q = 2 only).
+// Element x of the velocity row starting at base + row.  For 16-bit counts
+// the byte offset 2x fits in 32 bits (fewer than 2^31 nodes), so the address
+// is a wave-uniform 64-bit row pointer plus a 32-bit lane offset, which the
+// global load and store instructions take directly (no 64-bit add per lane).
+template <typename P>
+__device__ __forceinline__ P *row_elem(P *row, uint32_t x)
+{
+    if constexpr (sizeof(P) == 2) {
+        using B = typename std::conditional<std::is_const<P>::value, const uint8_t, uint8_t>::type;
+        return reinterpret_cast<P *>(reinterpret_cast<B *>(row) + (uint32_t)(x * 2u));
+    } else {
+        return row + x;
+    }
+}
+
 template <int Q, typename T, int NB, int GB, int BLOCK, bool FLIP, bool PZ, int NR, bool EX>
 __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 {
@@ -93,6 +108,14 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         stride = gridDim.x;
     }
 
+    const T *in_row[Q];
+    T *out_row[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        in_row[i] = in + (uint64_t)i * pitch;
+        out_row[i] = out + (uint64_t)i * pitch;
+    }
+
     W ovf = 0;
     for (uint32_t tile = first; tile < end; tile += stride) {
         const uint32_t x = tile * kTile + threadIdx.x;
@@ -101,7 +124,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         W n[Q], av[Q], cn[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            n[i] = (W)in[i * pitch + x];
+            n[i] = (W)*row_elem(in_row[i], x);
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             av[i] = FLIP ? n[Q - 1 - i] : n[i];
@@ -141,10 +164,10 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         // Streaming: velocity -1 to x-1, 0 in place, +1 to x+1 (periodic).
         const uint32_t xm = (x == 0) ? L - 1 : x - 1;
         const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-        out[xm] = (T)cn[0];
-        out[(uint64_t)(Q - 1) * pitch + xp] = (T)cn[Q - 1];
+        *row_elem(out_row[0], xm) = (T)cn[0];
+        *row_elem(out_row[Q - 1], xp) = (T)cn[Q - 1];
         if constexpr (Q == 3)
-            out[pitch + x] = (T)cn[1];
+            *row_elem(out_row[1], x) = (T)cn[1];
     }
     if (ovf > kMax)
         atomicOr(a.err, 1u);
