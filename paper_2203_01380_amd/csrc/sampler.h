@@ -477,30 +477,35 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
     W kv[Q], mv[Q];
     Draws<NB, NR> d;
     d.init(x, t, r, key0, key1);
-    // Common draw layout, decided once per wave for this node slot.
-    bool ok = true, two = false, three = false;
+    // Common draw layout, decided once per wave for this node slot.  The
+    // per-lane tests are combined bitwise (no short-circuit branches) and
+    // read as lane masks: a count a lies in 1..n exactly when a - 1 < n as
+    // an unsigned number.
+    auto in_1_to = [](W a, uint32_t n) { return (uint32_t)(a - (W)1) < n; };
+    bool ok, two = false, three = false;
     if constexpr (Q == 2) {
-        ok = av[0] >= 1 && av[0] <= (W)kChunk && av[1] >= 1 && av[1] <= (W)kChunk;
+        ok = in_1_to(av[0], kChunk) & in_1_to(av[1], kChunk);
     } else if constexpr (Q == 5) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i)
-            ok = ok && av[i] >= 1 && av[i] <= (W)(i == 2 ? 2 * kChunk : kChunk);
+        ok = in_1_to(av[0], kChunk) & in_1_to(av[1], kChunk) & in_1_to(av[2], 2 * kChunk) &
+             in_1_to(av[3], kChunk) & in_1_to(av[4], kChunk);
     } else {
-        ok = av[0] >= 1 && av[0] <= (W)kChunk && av[2] >= 1 && av[2] <= (W)kChunk &&
-             av[1] >= 1 && av[1] <= (W)(3 * kChunk);
+        ok = in_1_to(av[0], kChunk) & in_1_to(av[2], kChunk) & in_1_to(av[1], 3 * kChunk);
         two = av[1] > (W)kChunk;
         three = av[1] > (W)(2 * kChunk);
     }
+    const uint64_t lanes = __builtin_amdgcn_ballot_w64(true);
+    const uint64_t ok_mask = __builtin_amdgcn_ballot_w64(ok);
+    const uint64_t two_mask = __builtin_amdgcn_ballot_w64(two);
     bool done = false;
-    if (!wave_any(!ok)) {
+    if (ok_mask == lanes) {
         if constexpr (Q == 5)
             done = node_fast5<W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
                                          g_rest, p_zero);
-        else if (!wave_any(two))
+        else if (two_mask == 0ull)
             done = node_fast<Q, 1, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
                                               g_rest, p_zero);
         else if constexpr (Q == 3) {
-            if (!wave_any(!two) && !wave_any(three))
+            if (two_mask == lanes && __builtin_amdgcn_ballot_w64(three) == 0ull)
                 done = node_fast<Q, 2, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half,
                                                   tab_rest, g_rest, p_zero);
             else

@@ -154,11 +154,11 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
             const uint32_t dxp = cx + 1 == a.width ? x + 1 - a.width : x + 1;
             const uint32_t dym = cy == 0 ? x + (L - a.width) : x - a.width;
             const uint32_t dyp = cy + 1 == a.height ? x - (L - a.width) : x + a.width;
-            out[dxm] = (T)cn[0];
-            out[pitch + dym] = (T)cn[1];
-            out[2 * pitch + x] = (T)cn[2];
-            out[3 * pitch + dyp] = (T)cn[3];
-            out[4 * pitch + dxp] = (T)cn[4];
+            *row_elem(out_row[0], dxm) = (T)cn[0];
+            *row_elem(out_row[1], dym) = (T)cn[1];
+            *row_elem(out_row[2], x) = (T)cn[2];
+            *row_elem(out_row[3], dyp) = (T)cn[3];
+            *row_elem(out_row[4], dxp) = (T)cn[4];
             continue;
         }
         // Streaming: velocity -1 to x-1, 0 in place, +1 to x+1 (periodic).
