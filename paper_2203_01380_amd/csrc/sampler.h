@@ -140,13 +140,6 @@ __device__ __forceinline__ uint32_t draw_word(const Draws<NB, NR> &d, uint32_t j
     return r;
 }
 
-// Inverse-CDF count of one chunk of m >= 1 trials: #{j < m : row[j] <= u}.
-// The guide gives the count g <= m at the lower edge of u's bucket; rows are
-// nondecreasing, so counting continues from there to the first entry above u.
-// Tables are in the padded device layout: entries g and g + 1 always exist
-// (past the row they are all-ones sentinels), so the two probes need no bound
-// test, and entry g + 1 <= u implies entry g <= u.  A sentinel compares <= u
-// only for u = 2^32 - 1, where the final clamp to m gives the right count.
 // Byte offset of row m in a padded device table, 4 dev_row_offset(m), for
 // m = 1..64 (entry 0 unused): one LDS word read in place of the multiply
 // and shifts, issued alongside the guide read.  Every kernel that runs the
@@ -159,9 +152,18 @@ __device__ __forceinline__ void stage_row_offsets()
         s_row_bytes[m] = m == 0 ? 0u : dev_row_offset(m) * 4u;
 }
 
+// Inverse-CDF count of one chunk of m >= 1 trials, #{j < m : row[j] <= u},
+// before its final clamp to m.  The guide gives the count g <= m at the
+// lower edge of u's bucket; rows are nondecreasing, so counting continues
+// from there to the first entry above u.  Tables are in the padded device
+// layout: entries g and g + 1 always exist (past the row they are all-ones
+// sentinels), so the two probes need no bound test, and entry g + 1 <= u
+// implies entry g <= u.  A sentinel compares <= u only for u = 2^32 - 1,
+// where the result may exceed m; the callers' clamp then gives the count.
 template <int GB>
-__device__ __forceinline__ uint32_t chunk_count(const uint32_t *tab, const uint8_t *guide,
-                                                uint32_t m, uint32_t u)
+__device__ __forceinline__ uint32_t chunk_count_unclamped(const uint32_t *tab,
+                                                          const uint8_t *guide, uint32_t m,
+                                                          uint32_t u)
 {
     const uint32_t *row = tab + dev_row_offset(m);
     const uint32_t g = guide[((m - 1u) << GB) + (u >> (32 - GB))];
@@ -177,6 +179,15 @@ __device__ __forceinline__ uint32_t chunk_count(const uint32_t *tab, const uint8
             c += go ? 1u : 0u;
         }
     }
+    return c;
+}
+
+// #{j < m : row[j] <= u} for a chunk of m >= 1 trials.
+template <int GB>
+__device__ __forceinline__ uint32_t chunk_count(const uint32_t *tab, const uint8_t *guide,
+                                                uint32_t m, uint32_t u)
+{
+    const uint32_t c = chunk_count_unclamped<GB>(tab, guide, m, u);
     return c < m ? c : m;
 }
 
@@ -209,13 +220,14 @@ __device__ __forceinline__ W binomial(W n, uint32_t &j, const uint32_t *tab, con
     return total;
 }
 
-// One chunk whose draw word is known: m in [0, 64] trials (m = 0 gives 0).
+// One chunk whose draw word is known: m in [0, 64] trials.  m = 0 searches
+// row 1 and the clamp to m = 0 gives 0.
 template <int GB>
 __device__ __forceinline__ uint32_t chunk_or_zero(const uint32_t *tab, const uint8_t *guide,
                                                   uint32_t m, uint32_t u)
 {
-    const uint32_t c = chunk_count<GB>(tab, guide, m != 0 ? m : 1u, u);
-    return m != 0 ? c : 0u;
+    const uint32_t c = chunk_count_unclamped<GB>(tab, guide, m != 0 ? m : 1u, u);
+    return c < m ? c : m;
 }
 
 // Bin(n, table) for 0 <= n <= 64 K with the chunked rule when the words of
