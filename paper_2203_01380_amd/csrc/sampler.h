@@ -172,12 +172,12 @@ __device__ __forceinline__ uint32_t chunk_count_unclamped(const uint32_t *tab,
     const uint32_t t0 = pg[0], t1 = pg[1];
     const bool s1 = t1 <= u;
     uint32_t c = g + (t0 <= u ? 1u : 0u) + (s1 ? 1u : 0u);
-    if (wave_any(s1)) {
-        bool go = s1;
-        while (go) {
-            go = (c < m) && (row[c] <= u);
-            c += go ? 1u : 0u;
-        }
+    // Lanes past both probes continue the scan (the loop runs under their
+    // lane mask, so a wave without such lanes skips it).
+    bool go = s1;
+    while (go) {
+        go = (c < m) && (row[c] <= u);
+        c += go ? 1u : 0u;
     }
     return c;
 }
