@@ -508,6 +508,7 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
     const uint64_t lanes = __builtin_amdgcn_ballot_w64(true);
     const uint64_t ok_mask = __builtin_amdgcn_ballot_w64(ok);
     const uint64_t two_mask = __builtin_amdgcn_ballot_w64(two);
+    const uint64_t three_mask = __builtin_amdgcn_ballot_w64(three);
     bool done = false;
     if (ok_mask == lanes) {
         if constexpr (Q == 5)
@@ -517,7 +518,7 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
             done = node_fast<Q, 1, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
                                               g_rest, p_zero);
         else if constexpr (Q == 3) {
-            if (two_mask == lanes && __builtin_amdgcn_ballot_w64(three) == 0ull)
+            if (two_mask == lanes && three_mask == 0ull)
                 done = node_fast<Q, 2, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half,
                                                   tab_rest, g_rest, p_zero);
             else
