@@ -194,8 +194,11 @@ void batch_kernel(BatchArgs a)
         const uint32_t idx = __builtin_amdgcn_readfirstlane(s_next);
         if (idx >= a.nreal)
             break;
-        const uint32_t r = a.order[idx];
-        const BatchMeta m = a.meta[r];
+        // Member index and descriptor are uniform: scalar registers.  (The
+        // descriptor is rewritten only after the member's steps, by thread 0.)
+        const uint32_t r = __builtin_amdgcn_readfirstlane(a.order[idx]);
+        using ConstMeta = const __attribute__((address_space(4))) BatchMeta;
+        const BatchMeta m = ((ConstMeta *)a.meta)[r];
         const bool p_zero = m.p_zero != 0;
         const bool flip = m.flip != 0;
         if (!p_zero) {
@@ -216,21 +219,25 @@ void batch_kernel(BatchArgs a)
             const T *in = base + cur * qp;
             T *out = base + (cur ^ 1u) * qp;
             const uint32_t t = m.t + s;
+            // flipped loads by swapping the outer row pointers (uniform)
+            const uint64_t outer = (uint64_t)(Q - 1) * pitch;
+            const T *row_lo = in + (flip ? outer : 0), *row_hi = in + (flip ? 0 : outer);
             for (uint32_t x = threadIdx.x; x < L; x += BLOCK) {
                 W av[Q], cn[Q];
-#pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    av[i] = (W)in[(uint64_t)(flip ? Q - 1 - i : i) * pitch + x];
+                av[0] = (W)*sampler::row_elem(row_lo, x);
+                av[Q - 1] = (W)*sampler::row_elem(row_hi, x);
+                if constexpr (Q == 3)
+                    av[1] = (W)*sampler::row_elem(in + pitch, x);
                 sampler::node_update<Q, W, NB, GB>(av, cn, x, t, m.realization, m.key0, m.key1,
                                                    tab_p, g_p, tab_half, g_half, tab_rest, g_rest,
                                                    p_zero);
                 ovf |= sampler::or_all<Q, W>(cn);
                 const uint32_t xm = (x == 0) ? L - 1 : x - 1;
                 const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-                out[xm] = (T)cn[0];
-                out[(uint64_t)(Q - 1) * pitch + xp] = (T)cn[Q - 1];
+                *sampler::row_elem(out, xm) = (T)cn[0];
+                *sampler::row_elem(out + outer, xp) = (T)cn[Q - 1];
                 if constexpr (Q == 3)
-                    out[pitch + x] = (T)cn[1];
+                    *sampler::row_elem(out + pitch, x) = (T)cn[1];
             }
             __syncthreads();
             cur ^= 1u;

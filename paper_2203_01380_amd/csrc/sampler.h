@@ -54,6 +54,21 @@ __device__ __forceinline__ void static_for(F &&f)
     }
 }
 
+// Element x of a velocity row.  For 16-bit counts the byte offset 2x fits in
+// 32 bits (fewer than 2^31 nodes), so the address is a wave-uniform 64-bit
+// row pointer plus a 32-bit lane offset, which the global load and store
+// instructions take directly (no 64-bit add per lane).
+template <typename P>
+__device__ __forceinline__ P *row_elem(P *row, uint32_t x)
+{
+    if constexpr (sizeof(P) == 2) {
+        using B = typename std::conditional<std::is_const<P>::value, const uint8_t, uint8_t>::type;
+        return reinterpret_cast<P *>(reinterpret_cast<B *>(row) + (uint32_t)(x * 2u));
+    } else {
+        return row + x;
+    }
+}
+
 __device__ __forceinline__ bool wave_any(bool p)
 {
     return __builtin_amdgcn_ballot_w64(p) != 0ull;

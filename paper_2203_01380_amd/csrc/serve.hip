@@ -63,12 +63,16 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     // scalar-cache read with no dependence on a per-tile lookup.  (Carrying
     // the descriptor itself measured slower: the compiler keeps it in vector
     // registers.)
-    uint32_t slot = a.tile_slot[lo];
+    // The descriptors are read-only for the launch: read through the
+    // constant address space they are scalar loads at a uniform index.
+    using ConstSlot = const __attribute__((address_space(4))) ServeSlot;
+    ConstSlot *slots = (ConstSlot *)a.slots;
+    uint32_t slot = __builtin_amdgcn_readfirstlane(a.tile_slot[lo]);  // uniform
     uint32_t staged = 0xFFFFFFFFu;
     for (uint32_t tile = lo; tile < hi; ++tile) {
-        while (tile >= a.slots[slot].tile_end)
+        while (tile >= slots[slot].tile_end)
             ++slot;
-        const ServeSlot sl = a.slots[slot];
+        const ServeSlot sl = slots[slot];
         if (a.j >= sl.steps)
             continue;
         if (slot != staged) {
@@ -100,10 +104,15 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         const uint32_t cur = sl.cur0 ^ (a.j & 1u);
         const T *in = reinterpret_cast<const T *>(a.arena) + sl.state_off + cur * qp;
         T *out = reinterpret_cast<T *>(a.arena) + sl.state_off + (cur ^ 1u) * qp;
+        // Flipped loads (a_i = n_{q-1-i}) by swapping the outer row pointers,
+        // a scalar choice per slot.
+        const uint64_t outer = (uint64_t)(Q - 1) * pitch;
+        const T *row_lo = in + (sl.flip ? outer : 0), *row_hi = in + (sl.flip ? 0 : outer);
         W av[Q], cn[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            av[i] = (W)in[(uint64_t)(sl.flip ? Q - 1 - i : i) * pitch + x];
+        av[0] = (W)*sampler::row_elem(row_lo, x);
+        av[Q - 1] = (W)*sampler::row_elem(row_hi, x);
+        if constexpr (Q == 3)
+            av[1] = (W)*sampler::row_elem(in + pitch, x);
         // The key words are uniform; saying so keeps their round schedule in
         // scalar registers (as operands of the Philox xors).
         const uint32_t key0 = __builtin_amdgcn_readfirstlane(sl.key0);
@@ -114,10 +123,10 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         ovf |= sampler::or_all<Q, W>(cn);
         const uint32_t xm = (x == 0) ? L - 1 : x - 1;
         const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-        out[xm] = (T)cn[0];
-        out[(uint64_t)(Q - 1) * pitch + xp] = (T)cn[Q - 1];
+        *sampler::row_elem(out, xm) = (T)cn[0];
+        *sampler::row_elem(out + (uint64_t)(Q - 1) * pitch, xp) = (T)cn[Q - 1];
         if constexpr (Q == 3)
-            out[pitch + x] = (T)cn[1];
+            *sampler::row_elem(out + pitch, x) = (T)cn[1];
     }
     if (ovf > kMax)
         atomicOr(a.err, 1u);

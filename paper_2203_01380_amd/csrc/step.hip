@@ -28,22 +28,9 @@ constexpr int kBlock = 1024;
 constexpr int kWgPerCu = 2;
 using sampler::Wide;
 
-// EX: the D1Q2 exchange form (Q = 2 only).
-// Element x of the velocity row starting at base + row.  For 16-bit counts
-// the byte offset 2x fits in 32 bits (fewer than 2^31 nodes), so the address
-// is a wave-uniform 64-bit row pointer plus a 32-bit lane offset, which the
-// global load and store instructions take directly (no 64-bit add per lane).
-template <typename P>
-__device__ __forceinline__ P *row_elem(P *row, uint32_t x)
-{
-    if constexpr (sizeof(P) == 2) {
-        using B = typename std::conditional<std::is_const<P>::value, const uint8_t, uint8_t>::type;
-        return reinterpret_cast<P *>(reinterpret_cast<B *>(row) + (uint32_t)(x * 2u));
-    } else {
-        return row + x;
-    }
-}
+using sampler::row_elem;
 
+// EX: the D1Q2 exchange form (Q = 2 only).
 template <int Q, typename T, int NB, int GB, int BLOCK, bool FLIP, bool PZ, int NR, bool EX>
 __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
 {
