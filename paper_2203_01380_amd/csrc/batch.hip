@@ -147,6 +147,27 @@ __device__ __forceinline__ void sk_sample(const BatchArgs &a, uint32_t r, const 
 // instead of the step loop losing waves); launches without S(k) use the
 // variant without it.  kMinWaves(BLOCK) is the waves per SIMD needed for two
 // workgroups of 1024 threads (8) or enough smaller ones (6).
+// A member's descriptor read through the constant address space (scalar
+// loads at a uniform index); it is rewritten only after the member's steps.
+__device__ __forceinline__ BatchMeta read_meta(const BatchMeta *p)
+{
+    using ConstMeta = const __attribute__((address_space(4))) BatchMeta;
+    ConstMeta *q = (ConstMeta *)p;
+    BatchMeta m;
+    m.off = q->off;
+    m.length = q->length;
+    m.pitch = q->pitch;
+    m.t = q->t;
+    m.realization = q->realization;
+    m.key0 = q->key0;
+    m.key1 = q->key1;
+    m.flip = q->flip;
+    m.p_zero = q->p_zero;
+    m.cur = q->cur;
+    m.pad = 0;
+    return m;
+}
+
 template <int BLOCK>
 constexpr int kMinWaves = BLOCK >= 1024 ? 8 : 6;
 
@@ -197,8 +218,7 @@ void batch_kernel(BatchArgs a)
         // Member index and descriptor are uniform: scalar registers.  (The
         // descriptor is rewritten only after the member's steps, by thread 0.)
         const uint32_t r = __builtin_amdgcn_readfirstlane(a.order[idx]);
-        using ConstMeta = const __attribute__((address_space(4))) BatchMeta;
-        const BatchMeta m = ((ConstMeta *)a.meta)[r];
+        const BatchMeta m = read_meta(a.meta + r);
         const bool p_zero = m.p_zero != 0;
         const bool flip = m.flip != 0;
         if (!p_zero) {

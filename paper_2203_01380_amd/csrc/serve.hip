@@ -20,6 +20,35 @@ using sampler::Wide;
 
 constexpr int kBlock = kServeTile;  // one node per thread per tile
 
+// The slot descriptors are read-only during a launch: read through the
+// constant address space at a uniform index they are scalar loads.
+using ConstSlot = const __attribute__((address_space(4))) ServeSlot;
+__device__ __forceinline__ ConstSlot *const_space(const ServeSlot *p)
+{
+    return (ConstSlot *)p;
+}
+
+__device__ __forceinline__ ServeSlot read_slot(const ServeSlot *p)
+{
+    ConstSlot *q = const_space(p);
+    ServeSlot s;
+    s.state_off = q->state_off;
+    s.table_off = q->table_off;
+    s.length = q->length;
+    s.pitch = q->pitch;
+    s.t0 = q->t0;
+    s.steps = q->steps;
+    s.realization = q->realization;
+    s.key0 = q->key0;
+    s.key1 = q->key1;
+    s.flip = q->flip;
+    s.p_zero = q->p_zero;
+    s.cur0 = q->cur0;
+    s.tile_begin = q->tile_begin;
+    s.tile_end = q->tile_end;
+    return s;
+}
+
 template <int Q, typename T>
 __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
 {
@@ -63,16 +92,12 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     // scalar-cache read with no dependence on a per-tile lookup.  (Carrying
     // the descriptor itself measured slower: the compiler keeps it in vector
     // registers.)
-    // The descriptors are read-only for the launch: read through the
-    // constant address space they are scalar loads at a uniform index.
-    using ConstSlot = const __attribute__((address_space(4))) ServeSlot;
-    ConstSlot *slots = (ConstSlot *)a.slots;
     uint32_t slot = __builtin_amdgcn_readfirstlane(a.tile_slot[lo]);  // uniform
     uint32_t staged = 0xFFFFFFFFu;
     for (uint32_t tile = lo; tile < hi; ++tile) {
-        while (tile >= slots[slot].tile_end)
+        while (tile >= const_space(a.slots)[slot].tile_end)
             ++slot;
-        const ServeSlot sl = slots[slot];
+        const ServeSlot sl = read_slot(a.slots + slot);
         if (a.j >= sl.steps)
             continue;
         if (slot != staged) {
