@@ -180,19 +180,20 @@ __device__ __forceinline__ uint32_t chunk_count_unclamped(const uint32_t *tab,
                                                           const uint8_t *guide, uint32_t m,
                                                           uint32_t u)
 {
-    const uint32_t *row = tab + dev_row_offset(m);
     const uint32_t g = guide[((m - 1u) << GB) + (u >> (32 - GB))];
     const uint32_t *pg = reinterpret_cast<const uint32_t *>(
         reinterpret_cast<const uint8_t *>(tab) + (s_row_bytes[m] + (g << 2)));
     const uint32_t t0 = pg[0], t1 = pg[1];
     const bool s1 = t1 <= u;
     uint32_t c = g + (t0 <= u ? 1u : 0u) + (s1 ? 1u : 0u);
-    // Lanes past both probes continue the scan (the loop runs under their
-    // lane mask, so a wave without such lanes skips it).
+    // Lanes past both probes (c = g + 2) continue the scan from entry c,
+    // under their own lane mask, so a wave without such lanes skips it.
     bool go = s1;
+    const uint32_t *next = pg + 2;
     while (go) {
-        go = (c < m) && (row[c] <= u);
+        go = (c < m) && (*next <= u);
         c += go ? 1u : 0u;
+        ++next;
     }
     return c;
 }
