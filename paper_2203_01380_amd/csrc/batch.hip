@@ -27,39 +27,63 @@ namespace {
 
 using sampler::Wide;
 
-template <int BLOCK>
-__device__ __forceinline__ double block_sum_d(double v, double *scratch)
+// Workgroup sums of NV per-thread values with one barrier.  Within a wave
+// the values are summed by halving exchanges: at the exchange over lane bit
+// M a lane keeps half of its values (the upper half when the bit is set),
+// adds its partner's copies of them and sends the other half, so NV values
+// take NV - 1 shuffles before the last one is finished by butterflies;
+// afterwards lane l holds value j(l) (lane bits 5, 4, ... give the binary
+// digits of j).  One lane per value parks the wave's sum in LDS as
+// s_red[wave][NV]; after the barrier wave_total() adds the parked sums in
+// wave order.  The caller puts a barrier between the readers of one
+// reduction and the next park into the same array.
+template <int N, int M>
+__device__ __forceinline__ void halve_exchange(double *v, int lane, int &j)
 {
-    for (int off = 32; off > 0; off >>= 1)
-        v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0)
-        scratch[wid] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < BLOCK / 64; ++w)
-            r += scratch[w];
-    __syncthreads();
-    return r;  // valid in thread 0
+    if constexpr (N > 1) {
+        const bool hi = (lane & M) != 0;
+#pragma unroll
+        for (int i = 0; i < N / 2; ++i) {
+            const double keep = hi ? v[i + N / 2] : v[i];
+            const double send = hi ? v[i] : v[i + N / 2];
+            v[i] = keep + __shfl_xor(send, M, 64);
+        }
+        j += hi ? N / 2 : 0;
+        halve_exchange<N / 2, M / 2>(v, lane, j);
+    }
 }
 
-template <int BLOCK>
-__device__ __forceinline__ unsigned long long block_sum_u(unsigned long long v,
-                                                          unsigned long long *scratch)
+template <int NV>
+__device__ __forceinline__ void park_wave_sums(double (&v)[NV], double *s_red)
+{
+    static_assert(NV >= 1 && NV <= 32 && (NV & (NV - 1)) == 0, "NV: a power of two <= 32");
+    constexpr int kLog = NV >= 32 ? 5 : NV >= 16 ? 4 : NV >= 8 ? 3 : NV >= 4 ? 2 : NV >= 2 ? 1 : 0;
+    constexpr int kGroup = 64 >> kLog;  // lanes that share one value after the exchanges
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int j = 0;
+    halve_exchange<NV, 32>(v, lane, j);
+    double t = v[0];
+#pragma unroll
+    for (int m = kGroup / 2; m > 0; m >>= 1)
+        t += __shfl_xor(t, m, 64);
+    if ((lane & (kGroup - 1)) == 0)
+        s_red[wid * NV + j] = t;
+}
+
+template <int BLOCK, int NV>
+__device__ __forceinline__ double wave_total(const double *s_red, int j)
+{
+    double r = 0.0;
+    for (int w = 0; w < BLOCK / 64; ++w)
+        r += s_red[w * NV + j];
+    return r;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u(unsigned long long v)
 {
     for (int off = 32; off > 0; off >>= 1)
         v += __shfl_down(v, off, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0)
-        scratch[wid] = v;
-    __syncthreads();
-    unsigned long long r = 0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < BLOCK / 64; ++w)
-            r += scratch[w];
-    __syncthreads();
-    return r;
+    return v;
 }
 
 // Guide of one LDS table: entry (m, b) = #{j < m : T[m][j] <= b << (32 - GB)},
@@ -84,61 +108,213 @@ __device__ __forceinline__ void build_guide_lds(const uint32_t *tab, uint8_t *gu
     }
 }
 
-// Adds S(k), k = 1..nk, of the state st to member r's sums.  Modes are
-// accumulated kModesPerPass at a time (each pass re-reads N(x) from L2) to
-// bound the number of live FP64 accumulators.
-template <int Q, typename T, int BLOCK>
-__device__ __forceinline__ void sk_sample(const BatchArgs &a, uint32_t r, const T *st, uint32_t L,
-                                       uint64_t pitch, double *s_red, unsigned long long *s_redu)
+// Modes of S(k) accumulated per pass over the member's nodes (each pass
+// re-reads N(x) from L2); eight bounds the live FP64 accumulators.
+constexpr int kModesPerPass = 8;
+// Rows (BLOCK nodes apart) per twiddle run: inside a run the phase
+// e^{-2 pi i x/L} advances row by row by complex multiplication, and the
+// start of the next run by one multiplication with the run's stride, so the
+// rounding accumulated in a twiddle stays at a few units in the last place
+// per run plus one per run boundary.
+constexpr uint32_t kTwiddleRun = 16;
+
+// Per-member twiddle table in LDS, written once when a workgroup takes a
+// member (sincospi never runs inside the step loop, where its polynomial
+// constants would compete with the step's registers):
+//   [0, 64)            e^{-2 pi i lane / L}
+//   [64, 64 + waves)   e^{-2 pi i 64 w / L}
+//   kTwRow             e^{-2 pi i BLOCK / L}       (one row)
+//   kTwRow + 1         e^{-2 pi i kTwiddleRun BLOCK / L}   (one run)
+template <int BLOCK>
+struct Twiddles {
+    static constexpr int kRow = 64 + BLOCK / 64;
+    static constexpr int kRun = kRow + 1;
+    static constexpr int kSize = kRow + 2;
+};
+
+__device__ __forceinline__ void cmul(double &ar, double &ai, double br, double bi)
 {
-    constexpr int kModesPerPass = 8;
+    const double r = ar * br - ai * bi;
+    ai = ar * bi + ai * br;
+    ar = r;
+}
+
+// (br, bi)^e by square-and-multiply, e >= 1.
+__device__ __forceinline__ void cpow(double br, double bi, uint32_t e, double &pr, double &pi)
+{
+    pr = 1.0;
+    pi = 0.0;
+    for (; e != 0; e >>= 1) {
+        if (e & 1u)
+            cmul(pr, pi, br, bi);
+        if (e > 1u)
+            cmul(br, bi, br, bi);
+    }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void build_twiddles(uint32_t L, double *twr, double *twi)
+{
+    using Tw = Twiddles<BLOCK>;
+    for (int e = threadIdx.x; e < Tw::kSize; e += BLOCK) {
+        uint64_t j;
+        if (e < 64)
+            j = (uint64_t)e;
+        else if (e < Tw::kRow)
+            j = 64ull * (uint64_t)(e - 64);
+        else if (e == Tw::kRow)
+            j = BLOCK;
+        else
+            j = (uint64_t)kTwiddleRun * BLOCK;
+        double sv, cv;
+        sincospi(2.0 * (double)(j % L) / (double)L, &sv, &cv);
+        twr[e] = cv;
+        twi[e] = -sv;
+    }
+}
+
+// e^{-2 pi i tid / L} of this thread from the table (one multiplication).
+template <int BLOCK>
+__device__ __forceinline__ void thread_twiddle(const double *twr, const double *twi, double &zr,
+                                               double &zi)
+{
+    const int lane = threadIdx.x & 63, w = 64 + (int)(threadIdx.x >> 6);
+    zr = twr[lane];
+    zi = twi[lane];
+    cmul(zr, zi, twr[w], twi[w]);
+}
+
+// One pass of S(k): modes k0 + 1 .. k0 + kModesPerPass, k0 = 8 PASS.  Every
+// thread accumulates Re and Im of sum_x N(x) z^k over its nodes
+// x = tid + j BLOCK (z = e^{-2 pi i x/L}); the pass's first power z^(k0+1)
+// is taken at the start of every run and advanced with the row twiddle's
+// power.  Returns the thread's share of the mass sum_x N(x).
+template <int Q, typename T, int BLOCK, int PASS>
+__device__ __forceinline__ unsigned long long sk_pass(const T *st, uint32_t L, uint64_t pitch,
+                                                      const double *twr, const double *twi,
+                                                      double (&v)[2 * kModesPerPass])
+{
+    using Tw = Twiddles<BLOCK>;
+    constexpr uint32_t e0 = kModesPerPass * PASS + 1;
+    const double wr = twr[Tw::kRow], wi = twi[Tw::kRow];
+    const double rr = twr[Tw::kRun], ri = twi[Tw::kRun];
+    double ur = 0.0, ui = 0.0;
+    if constexpr (PASS > 0)
+        cpow(wr, wi, e0, ur, ui);
+    double ar, ai;  // twiddle of the run's first node
+    thread_twiddle<BLOCK>(twr, twi, ar, ai);
+#pragma unroll
+    for (int j = 0; j < 2 * kModesPerPass; ++j)
+        v[j] = 0.0;
     unsigned long long mass = 0;
-    for (uint32_t x = threadIdx.x; x < L; x += BLOCK)
-#pragma unroll
-        for (int i = 0; i < Q; ++i)
-            mass += st[(uint64_t)i * pitch + x];
-    const unsigned long long tot = block_sum_u<BLOCK>(mass, s_redu);
-    for (uint32_t k0 = 0; k0 < a.nk; k0 += kModesPerPass) {
-        double re[kModesPerPass], im[kModesPerPass];
-#pragma unroll
-        for (int k = 0; k < kModesPerPass; ++k)
-            re[k] = im[k] = 0.0;
-        for (uint32_t x = threadIdx.x; x < L; x += BLOCK) {
+    for (uint64_t x0 = threadIdx.x; x0 < L; x0 += (uint64_t)kTwiddleRun * BLOCK) {
+        double zr = ar, zi = ai, qr = 0.0, qi = 0.0;
+        if constexpr (PASS > 0)
+            cpow(zr, zi, e0, qr, qi);
+        const uint64_t run_end = x0 + (uint64_t)kTwiddleRun * BLOCK;
+        const uint32_t xend = run_end < L ? (uint32_t)run_end : L;
+        for (uint32_t x = (uint32_t)x0; x < xend; x += BLOCK) {
             uint64_t N = 0;
 #pragma unroll
             for (int i = 0; i < Q; ++i)
                 N += st[(uint64_t)i * pitch + x];
+            mass += N;
             const double Nd = (double)N;
-            double sv, cv;
-            sincospi(2.0 * (double)x / (double)L, &sv, &cv);
-            const double zr = cv, zi = -sv;  // e^{-2 pi i x / L}
-            // p = z^(k0 + 1) by repeated multiplication, then successive powers
-            double pr = zr, pim = zi;
-            for (uint32_t e = 0; e < k0; ++e) {
-                const double nr = pr * zr - pim * zi;
-                pim = pr * zi + pim * zr;
-                pr = nr;
-            }
+            double pr = PASS > 0 ? qr : zr, pim = PASS > 0 ? qi : zi;
 #pragma unroll
             for (int k = 0; k < kModesPerPass; ++k) {
-                re[k] += Nd * pr;
-                im[k] += Nd * pim;
-                const double nr = pr * zr - pim * zi;
-                pim = pr * zi + pim * zr;
-                pr = nr;
+                if (k > 0)
+                    cmul(pr, pim, zr, zi);
+                v[2 * k] += Nd * pr;
+                v[2 * k + 1] += Nd * pim;
             }
+            cmul(zr, zi, wr, wi);
+            if constexpr (PASS > 0)
+                cmul(qr, qi, ur, ui);
         }
-        for (int k = 0; k < kModesPerPass; ++k) {
-            if (k0 + k >= a.nk)
-                break;
-            const double fr = block_sum_d<BLOCK>(re[k], s_red);
-            const double fi = block_sum_d<BLOCK>(im[k], s_red);
-            if (threadIdx.x == 0 && tot > 0)
-                a.sk_sum[(size_t)r * a.nk + k0 + k] += (fr * fr + fi * fi) / (double)tot;
+        cmul(ar, ai, rr, ri);
+    }
+    return mass;
+}
+
+// Adds S(k), k = 1..nk, of the state st to member r's sums: one pass per
+// eight modes, each closed by one barrier-separated reduction that gives
+// thread j the sums of mode k0 + j + 1; the mass is reduced exactly
+// (integers) with the first pass.
+template <int Q, typename T, int BLOCK>
+__device__ __forceinline__ void sk_sample(const BatchArgs &a, uint32_t r, const T *st, uint32_t L,
+                                       uint64_t pitch, const double *twr, const double *twi,
+                                       double *s_red, unsigned long long *s_redu)
+{
+    constexpr int kWaves = BLOCK / 64;
+    constexpr int NV = 2 * kModesPerPass;
+    static_assert(ILG_BATCH_MAX_K <= 2 * kModesPerPass, "two passes cover every mode");
+    unsigned long long tot = 0;
+    for (uint32_t k0 = 0; k0 < a.nk; k0 += kModesPerPass) {
+        double v[NV];
+        unsigned long long mass;
+        if (k0 == 0)
+            mass = sk_pass<Q, T, BLOCK, 0>(st, L, pitch, twr, twi, v);
+        else
+            mass = sk_pass<Q, T, BLOCK, 1>(st, L, pitch, twr, twi, v);
+        __syncthreads();  // readers of the previous reduction are done
+        park_wave_sums<NV>(v, s_red);
+        if (k0 == 0) {
+            mass = wave_sum_u(mass);
+            if ((threadIdx.x & 63) == 0)
+                s_redu[threadIdx.x >> 6] = mass;
+        }
+        __syncthreads();
+        if (k0 == 0)
+            for (int w = 0; w < kWaves; ++w)
+                tot += s_redu[w];
+        const uint32_t k = k0 + threadIdx.x;
+        if (threadIdx.x < (uint32_t)kModesPerPass && k < a.nk && tot > 0) {
+            const double fr = wave_total<BLOCK, NV>(s_red, 2 * threadIdx.x);
+            const double fi = wave_total<BLOCK, NV>(s_red, 2 * threadIdx.x + 1);
+            a.sk_sum[(size_t)r * a.nk + k] += (fr * fr + fi * fi) / (double)tot;
         }
     }
     if (threadIdx.x == 0)
         a.sk_cnt[r] += 1ull;
+}
+
+// A^LG of the state st: sum_x sin(2 pi x/L) N(x) / sum_x sin^2(2 pi x/L),
+// with the twiddles of S(k) (sin = -Im z).  Valid in thread 0.
+template <int Q, typename T, int BLOCK>
+__device__ __forceinline__ double amp_sample(const T *st, uint32_t L, uint64_t pitch,
+                                             const double *twr, const double *twi, double *s_red)
+{
+    using Tw = Twiddles<BLOCK>;
+    const double wr = twr[Tw::kRow], wi = twi[Tw::kRow];
+    const double rr = twr[Tw::kRun], ri = twi[Tw::kRun];
+    double ar, ai;
+    thread_twiddle<BLOCK>(twr, twi, ar, ai);
+    double v[2] = {0.0, 0.0};  // sum sin N, sum sin^2
+    for (uint64_t x0 = threadIdx.x; x0 < L; x0 += (uint64_t)kTwiddleRun * BLOCK) {
+        double zr = ar, zi = ai;
+        const uint64_t run_end = x0 + (uint64_t)kTwiddleRun * BLOCK;
+        const uint32_t xend = run_end < L ? (uint32_t)run_end : L;
+        for (uint32_t x = (uint32_t)x0; x < xend; x += BLOCK) {
+            uint64_t N = 0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                N += st[(uint64_t)i * pitch + x];
+            const double sv = -zi;
+            v[0] += sv * (double)N;
+            v[1] += sv * sv;
+            cmul(zr, zi, wr, wi);
+        }
+        cmul(ar, ai, rr, ri);
+    }
+    __syncthreads();  // earlier readers of s_red are done
+    park_wave_sums<2>(v, s_red);
+    __syncthreads();
+    if (threadIdx.x != 0)
+        return 0.0;
+    const double tn = wave_total<BLOCK, 2>(s_red, 0);
+    const double td = wave_total<BLOCK, 2>(s_red, 1);
+    return td > 0.0 ? tn / td : 0.0;
 }
 
 // SK: the launch samples S(k).  Those FP64 accumulators need about twice
@@ -187,8 +363,10 @@ void batch_kernel(BatchArgs a)
     uint32_t *s_tab = reinterpret_cast<uint32_t *>(s_lds);
     uint8_t *s_guide = s_lds + kTabBytes;
     __shared__ uint32_t s_next;
-    __shared__ double s_red[kWaves];
+    // wave sums of the diagnostics' reductions (S(k): 2 x 8 modes per wave)
+    __shared__ double s_red[kWaves * (SK ? 2 * kModesPerPass : 2)];
     __shared__ unsigned long long s_redu[kWaves];
+    __shared__ double s_twr[Twiddles<BLOCK>::kSize], s_twi[Twiddles<BLOCK>::kSize];
 
     sampler::stage_row_offsets();
     // Shared tables (P = 2^31 and, for q = 3, P_rest) and their guides, once.
@@ -229,6 +407,8 @@ void batch_kernel(BatchArgs a)
             __syncthreads();
             build_guide_lds<GB, BLOCK>(s_tab, s_guide);
         }
+        if (SK || a.amp_every != 0)
+            build_twiddles<BLOCK>(m.length, s_twr, s_twi);
         __syncthreads();
 
         const uint32_t L = m.length;
@@ -265,25 +445,14 @@ void batch_kernel(BatchArgs a)
             const T *st = base + cur * qp;
             if constexpr (SK) {
                 if (a.sk_every != 0 && t_after % a.sk_every == 0)
-                    sk_sample<Q, T, BLOCK>(a, r, st, L, pitch, s_red, s_redu);
+                    sk_sample<Q, T, BLOCK>(a, r, st, L, pitch, s_twr, s_twi, s_red, s_redu);
             }
             if (a.amp_every != 0 && t_after % a.amp_every == 0) {
-                double num = 0.0, den = 0.0;
-                for (uint32_t x = threadIdx.x; x < L; x += BLOCK) {
-                    uint64_t N = 0;
-#pragma unroll
-                    for (int i = 0; i < Q; ++i)
-                        N += st[(uint64_t)i * pitch + x];
-                    const double sv = sinpi(2.0 * (double)x / (double)L);
-                    num += sv * (double)N;
-                    den += sv * sv;
-                }
-                const double tn = block_sum_d<BLOCK>(num, s_red);
-                const double td = block_sum_d<BLOCK>(den, s_red);
+                const double amp = amp_sample<Q, T, BLOCK>(st, L, pitch, s_twr, s_twi, s_red);
                 if (threadIdx.x == 0) {
                     const uint32_t c = a.amp_cnt[r];
                     if (c < a.max_amp)
-                        a.amp[(size_t)r * a.max_amp + c] = td > 0.0 ? tn / td : 0.0;
+                        a.amp[(size_t)r * a.max_amp + c] = amp;
                     a.amp_cnt[r] = c + 1u;
                 }
             }
