@@ -168,6 +168,41 @@ def test_batch_diagnostics(ilg, oracle_lib, q):
     b.close()
 
 
+@pytest.mark.parametrize("q", [2, 3])
+def test_batch_diagnostics_long_members_every_shape(ilg, oracle_lib, q):
+    """S(k) and A^LG of members longer than 16 rows of every workgroup shape
+    (the twiddle restarts from the run stride), lengths not multiples of the
+    workgroup, and one member shorter than a wave; every shape against the
+    oracle."""
+    w = W.D1Q3_WEIGHTS if q == 3 else W.D1Q2_WEIGHTS
+    lens = [40961, 20000, 9000, 2049, 37]
+    members, inits = [], []
+    for r, L in enumerate(lens):
+        members.append(dict(q=q, length=L, count_bytes=4, omega=1.3 + 0.1 * r, seed=900 + r,
+                            realization=r))
+        inits.append(W.init_poisson_sine(w, L, 60.0, 30.0, 4, init_seed=800 + r))
+    nk, steps = 16, 6
+    refs = [_oracle_member(oracle_lib, m, inits[r], steps, sk_every=3, nk=nk, amp_every=2)
+            for r, m in enumerate(members)]
+    for shape in range(ilg.Batch.shape_count()):
+        _say(f"[long members] q={q} shape {shape}")
+        b = ilg.Batch(members, inits, sk_every=3, nk=nk, amp_every=2, max_amp=4)
+        b.set_shape(shape)
+        b.run(steps)
+        sk, nsk = b.structure_factor()
+        amp, namp = b.amplitudes()
+        for r, (ref, rsk, rnsk, ramp) in enumerate(refs):
+            np.testing.assert_array_equal(b.state(r), ref, err_msg=f"shape {shape} member {r}")
+            assert int(nsk[r]) == rnsk and int(namp[r]) == len(ramp)
+            mass = float(inits[r].astype(np.int64).sum())
+            np.testing.assert_allclose(sk[r], rsk, rtol=1e-9, atol=1e-9 * mass,
+                                       err_msg=f"shape {shape} member {r}")
+            np.testing.assert_allclose(amp[r, :len(ramp)], ramp, rtol=1e-9,
+                                       atol=1e-9 * mass / lens[r],
+                                       err_msg=f"shape {shape} member {r}")
+        b.close()
+
+
 def test_config3_ragged_ensemble_full_size(ilg, oracle_lib):
     """4096 D1Q2 members, L log-uniform in [64, 8192], omega ~ U[1, 1.95],
     seed 1000 + r, Poisson(30) uint16, 5000 steps in one graph replay with
