@@ -229,6 +229,27 @@ def bench_batched_ragged(ilg, W, stream, steps: int, loop_members: int):
     }
 
 
+def bench_batched_specs(ilg, W, stream, steps: int):
+    """The ragged D1Q2 ensemble (with its S(k) sampling) under draw
+    specifications v2 (7-round draws) and v3 (the exchange form), each with
+    its own autotuned shape."""
+    ens = W.ensemble_ragged_d1q2(steps=steps)
+    nu = ens.total_nodes * steps
+    out = {}
+    for key, rounds, exchange in (("v2_philox7", 7, False), ("v3_exchange", 10, True)):
+        members = [dict(q=s.q, length=s.length, count_bytes=s.count_bytes, omega=s.omega,
+                        seed=s.seed, realization=s.realization, rounds=rounds,
+                        exchange=exchange) for s in ens.specs]
+        b = ilg.Batch(members, ens.inits, sk_every=10, nk=16)
+        shape = b.tune(40)
+        sec = timed(stream, lambda: b.run(steps))
+        b.close()
+        out[key] = {"node_updates_per_s": nu / sec, "seconds": sec, "shape": shape}
+    out["workload"] = ("the batched ragged ensemble's members and S(k) sampling, "
+                       f"{steps} steps, under draw specifications v2 and v3")
+    return out
+
+
 def bench_batched_decay(ilg, W, stream, steps: int):
     ens = W.ensemble_decay_sweep(steps=steps)
     members = [dict(q=s.q, length=s.length, count_bytes=s.count_bytes, omega=s.omega,
@@ -332,9 +353,9 @@ def main():
     ap.add_argument("--length", type=int, default=1 << 24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,mallfree,philox7,exchange,d2q5,batched,decay,serving",
+    ap.add_argument("--forms", default="plain,mallfree,philox7,exchange,d2q5,batched,batched_specs,decay,serving",
                     help="comma list of plain (always), mallfree, philox7, exchange, d2q5, "
-                         "batched, decay, serving")
+                         "batched, batched_specs, decay, serving")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
@@ -426,6 +447,9 @@ def main():
         say("batched ragged ensemble")
         out["batched"] = bench_batched_ragged(ilg, W, stream, args.batched_steps,
                                               args.loop_members)
+    if "batched_specs" in forms:
+        say("batched ragged ensemble under draw specifications v2 and v3")
+        out["batched_specs"] = bench_batched_specs(ilg, W, stream, args.batched_steps)
     if "decay" in forms:
         say("batched decay sweep")
         out["batched_decay"] = bench_batched_decay(ilg, W, stream, args.decay_steps)

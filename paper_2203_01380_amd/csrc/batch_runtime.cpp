@@ -41,6 +41,7 @@ uint64_t pitch_of(uint64_t length)
 
 struct ilg_batch {
     uint32_t q = 0, cb = 0, nreal = 0;
+    uint32_t rounds = 10, exchange = 0;  // draw specification, batch-wide
     hipStream_t stream = nullptr;      // caller's stream
     hipStream_t cap = nullptr;         // private stream used for graph capture
     std::vector<uint32_t> lengths;
@@ -106,6 +107,8 @@ ilg::BatchArgs make_args(const ilg_batch *b, uint32_t nsteps)
     a.amp = b->amp;
     a.amp_cnt = b->amp_cnt;
     a.err = b->err;
+    a.rounds = b->rounds;
+    a.exchange = b->exchange;
     return a;
 }
 
@@ -136,10 +139,10 @@ int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *
             return rc;
         if (cfgs[r].q == 5)
             return bfail(ILG_E_INVALID, "D2Q5 lattices run in the plain form only");
-        if (fx[r].rounds != 10)
-            return bfail(ILG_E_INVALID, "7-round draws run in the plain form only");
-        if (fx[r].exchange)
-            return bfail(ILG_E_INVALID, "the exchange form runs in the plain form only");
+        if (fx[r].rounds != fx[0].rounds || fx[r].exchange != fx[0].exchange)
+            return bfail(ILG_E_INVALID,
+                         "batch members must share the draw specification (flags "
+                         "ILG_DRAWS_PHILOX7 and ILG_DRAWS_EXCHANGE)");
         if (!inits[r])
             return bfail(ILG_E_INVALID, "null initial state");
         if (cfgs[r].q != cfgs[0].q || cfgs[r].count_bytes != cfgs[0].count_bytes ||
@@ -162,6 +165,8 @@ int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *
         return bfail(ILG_E_NOMEM, "host allocation failed");
     b->q = cfgs[0].q;
     b->cb = cfgs[0].count_bytes;
+    b->rounds = (uint32_t)fx[0].rounds;
+    b->exchange = (uint32_t)fx[0].exchange;
     b->nreal = nreal;
     b->stream = reinterpret_cast<hipStream_t>(stream);
     b->diag = d;

@@ -162,6 +162,8 @@ struct BatchArgs {
     double *amp;                  // [nreal][max_amp]
     uint32_t *amp_cnt;            // [nreal]
     uint32_t *err;
+    uint32_t rounds;              // Philox rounds of the draws, batch-wide: 10 or 7
+    uint32_t exchange;            // D1Q2 exchange form, batch-wide
 };
 
 int batch_shape_count();
@@ -169,6 +171,11 @@ int batch_shape_count();
 void batch_shape(int shape, int q, int *block, int *wg_per_cu);
 hipError_t launch_batch_reset(uint32_t *queue, hipStream_t stream);
 hipError_t launch_batch(int q, int count_bytes, int shape, const BatchArgs &a, hipStream_t stream);
+// The seven-round and exchange-form instantiations (their own translation units).
+hipError_t launch_batch_p7(int q, int count_bytes, int shape, const BatchArgs &a,
+                           hipStream_t stream);
+hipError_t launch_batch_ex(int q, int count_bytes, int shape, const BatchArgs &a,
+                           hipStream_t stream);
 
 // ---------------------------------------------------------------- serving
 // One active request of the server: its buffer pair and table set in the

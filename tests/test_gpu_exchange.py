@@ -4,7 +4,8 @@ fixed-point crossing probability, every compared step bit-exact over ragged
 lengths, both count types, multi-chunk counts, special rates (the zero
 collision fraction shares the three-binomial kernel), combined with 7-round
 draws, a 2^24-node lattice with light-cone samples, and the rejection of the
-flag for q != 2 and by the batched and serving forms."""
+flag for q != 2, by the serving form and in a batch of mixed specifications
+(batched parity: test_gpu_batch_specs.py)."""
 import sys
 
 import numpy as np
@@ -114,7 +115,7 @@ def test_rejections(ilg):
     m = dict(q=2, length=64, count_bytes=2, omega=1.5, seed=1, exchange=True)
     init = np.ones((2, 64), dtype=np.uint16)
     with pytest.raises(ilg.IlgError):
-        ilg.Batch([m], [init])
+        ilg.Batch([m, dict(m, exchange=False)], [init, init])
     srv = ilg.Server(1 << 20, 10)
     try:
         with pytest.raises(ilg.IlgError):
