@@ -65,10 +65,9 @@ typedef enum ilg_status {
  * report that seven rounds pass their statistical test batteries.  A
  * different but equally valid random stream (the collision law of the
  * Integer Lattice Gas section is unchanged), with 30% fewer Philox rounds
- * per node.  Plain and
- * batched forms (all members of a batch share the flag); the serving form
- * rejects it (ILG_E_INVALID).  Device-drawn initial states keep the
- * 10-round generator. */
+ * per node.  Every form:
+ * plain, batched (all members of a batch share the flag) and served.
+ * Device-drawn initial states keep the 10-round generator. */
 #define ILG_DRAWS_PHILOX7 4u
 /* Draw specification v3, D1Q2 only: the exchange form of the same collision.
  * A particle removed with probability omega* and sent to either velocity with
@@ -77,8 +76,8 @@ typedef enum ilg_status {
  * +1 and then Y = Bin(a_+, p_x) from +1 to -1 (chunked as every binomial),
  * with p_x = round-half-even(omega* 2^31) / 2^32, and sets c_- = a_- - X + Y,
  * c_+ = a_+ - Y + X: two binomials per node instead of three.  Combines with
- * ILG_DRAWS_PHILOX7.  Plain and batched forms (all members of a batch share
- * the flag); other q and the serving form reject it (ILG_E_INVALID). */
+ * ILG_DRAWS_PHILOX7.  Plain, batched (all members of a batch share the flag)
+ * and served forms; other q reject it (ILG_E_INVALID). */
 #define ILG_DRAWS_EXCHANGE 8u
 
 /* One lattice run.  Velocity index order is fixed: q = 2 -> v = (-1, +1),

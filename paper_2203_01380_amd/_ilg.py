@@ -19,8 +19,8 @@ ABI_VERSION = 1
 MAX_K = 64
 TABLE_ENTRIES = 2080
 FLIP_MODES = {"auto": 0, "off": 1, "on": 2}
-DRAWS_PHILOX7 = 4  # draw specification v2 (7-round Philox), plain and batched forms
-DRAWS_EXCHANGE = 8  # draw specification v3 (D1Q2 exchange form), plain and batched forms
+DRAWS_PHILOX7 = 4  # draw specification v2 (7-round Philox)
+DRAWS_EXCHANGE = 8  # draw specification v3 (D1Q2 exchange form)
 STATUS = {0: "ILG_OK", -1: "ILG_E_INVALID", -2: "ILG_E_NOMEM", -3: "ILG_E_DEVICE",
           -4: "ILG_E_OVERFLOW", -5: "ILG_E_RANGE", -6: "ILG_E_BUSY"}
 

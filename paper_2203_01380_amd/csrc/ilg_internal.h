@@ -210,6 +210,7 @@ struct ServeArgs {
     uint32_t *err;
 };
 
-hipError_t launch_serve(int q, int count_bytes, const ServeArgs &a, hipStream_t stream);
+hipError_t launch_serve(int q, int count_bytes, int rounds, bool exchange, const ServeArgs &a,
+                        hipStream_t stream);
 
 }  // namespace ilg

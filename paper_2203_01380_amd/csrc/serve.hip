@@ -49,7 +49,10 @@ __device__ __forceinline__ ServeSlot read_slot(const ServeSlot *p)
     return s;
 }
 
-template <int Q, typename T>
+// NR: Philox rounds of the draws (10, or 7 for draw specification v2); EX:
+// the D1Q2 exchange form (specification v3).  The server launches one group
+// of requests per (q, count type, specification).
+template <int Q, typename T, int NR, bool EX>
 __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
 {
     using W = typename Wide<T>::type;
@@ -142,9 +145,15 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         // scalar registers (as operands of the Philox xors).
         const uint32_t key0 = __builtin_amdgcn_readfirstlane(sl.key0);
         const uint32_t key1 = __builtin_amdgcn_readfirstlane(sl.key1);
-        sampler::node_update<Q, W, NB, GB>(av, cn, x, sl.t0 + a.j, sl.realization, key0, key1,
-                                           tab_p, g_p, tab_half, g_half, tab_rest, g_rest,
-                                           sl.p_zero != 0);
+        if constexpr (EX) {
+            static_assert(Q == 2, "the exchange form is defined for D1Q2");
+            sampler::node_exchange<W, NB, GB, NR>(av, cn, x, sl.t0 + a.j, sl.realization, key0,
+                                                  key1, tab_p, g_p, sl.p_zero != 0);
+        } else {
+            sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, sl.t0 + a.j, sl.realization, key0,
+                                                   key1, tab_p, g_p, tab_half, g_half, tab_rest,
+                                                   g_rest, sl.p_zero != 0);
+        }
         ovf |= sampler::or_all<Q, W>(cn);
         const uint32_t xm = (x == 0) ? L - 1 : x - 1;
         const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         atomicOr(a.err, 1u);
 }
 
-template <int Q, typename T>
+template <int Q, typename T, int NR, bool EX>
 hipError_t launch_qt(const ServeArgs &a, hipStream_t stream)
 {
     const uint32_t cus = (uint32_t)device_cu_count();
@@ -166,22 +175,37 @@ hipError_t launch_qt(const ServeArgs &a, hipStream_t stream)
         grid = a.ntiles;
     if (grid == 0)
         return hipSuccess;
-    hipLaunchKernelGGL((serve_kernel<Q, T>), dim3(grid), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL((serve_kernel<Q, T, NR, EX>), dim3(grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
+}
+
+template <int NR, bool EX>
+hipError_t launch_spec(int q, int count_bytes, const ServeArgs &a, hipStream_t stream)
+{
+    if (q == 2 && count_bytes == 2)
+        return launch_qt<2, uint16_t, NR, EX>(a, stream);
+    if (q == 2 && count_bytes == 4)
+        return launch_qt<2, uint32_t, NR, EX>(a, stream);
+    if constexpr (!EX) {
+        if (q == 3 && count_bytes == 2)
+            return launch_qt<3, uint16_t, NR, EX>(a, stream);
+        if (q == 3 && count_bytes == 4)
+            return launch_qt<3, uint32_t, NR, EX>(a, stream);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_serve(int q, int count_bytes, const ServeArgs &a, hipStream_t stream)
+hipError_t launch_serve(int q, int count_bytes, int rounds, bool exchange, const ServeArgs &a,
+                        hipStream_t stream)
 {
-    if (q == 2 && count_bytes == 2)
-        return launch_qt<2, uint16_t>(a, stream);
-    if (q == 2 && count_bytes == 4)
-        return launch_qt<2, uint32_t>(a, stream);
-    if (q == 3 && count_bytes == 2)
-        return launch_qt<3, uint16_t>(a, stream);
-    if (q == 3 && count_bytes == 4)
-        return launch_qt<3, uint32_t>(a, stream);
+    if (rounds == 10)
+        return exchange ? launch_spec<10, true>(q, count_bytes, a, stream)
+                        : launch_spec<10, false>(q, count_bytes, a, stream);
+    if (rounds == 7)
+        return exchange ? launch_spec<7, true>(q, count_bytes, a, stream)
+                        : launch_spec<7, false>(q, count_bytes, a, stream);
     return hipErrorInvalidValue;
 }
 

@@ -3,8 +3,8 @@
 // budget's size holds every active request's double-buffered state and its
 // table set; each poll admits what fits, advances all active requests by a
 // quantum with the multi-slot step kernel (one launch per step and per
-// (q, count type) group, groups on their own streams so their work
-// overlaps), and copies finished states back to host memory.
+// (q, count type, draw specification) group, groups on their own streams so
+// their work overlaps), and copies finished states back to host memory.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -83,16 +83,20 @@ public:
     void *arena = nullptr;
     void *shared = nullptr;  // half table + guide
     uint32_t *err = nullptr;
-    hipStream_t streams[4] = {nullptr, nullptr, nullptr, nullptr};  // (q, count type) groups
-    ilg::ServeSlot *d_slots[4] = {nullptr, nullptr, nullptr, nullptr};
-    uint32_t *d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};  // slot of each tile
-    size_t cap_slots[4] = {0, 0, 0, 0}, cap_tiles[4] = {0, 0, 0, 0};
+    // Launch groups: (q, count type, Philox rounds, exchange form); a group's
+    // stream is created when the group first has work.
+    static constexpr int kGroups = 16;
+    hipStream_t streams[kGroups] = {};
+    ilg::ServeSlot *d_slots[kGroups] = {};
+    uint32_t *d_tiles[kGroups] = {};  // slot of each tile
+    size_t cap_slots[kGroups] = {}, cap_tiles[kGroups] = {};
     hipStream_t io = nullptr;  // copies in and out
     int last_rc = ILG_OK;
 
-    static int group(uint32_t q, uint32_t cb)
+    static int group(uint32_t q, uint32_t cb, const ilg::Fixed &fx)
     {
-        return (q == 3 ? 2 : 0) + (cb == 4 ? 1 : 0);
+        return (q == 3 ? 8 : 0) + (cb == 4 ? 4 : 0) + (fx.rounds == 7 ? 2 : 0) +
+               (fx.exchange ? 1 : 0);
     }
 
     uint64_t footprint(const Req &r) override
@@ -179,8 +183,8 @@ public:
 
     // Host copies of the last launch's slot and tile lists (kept alive until
     // the copies from them have completed).
-    std::vector<ilg::ServeSlot> h_slots[4];
-    std::vector<uint32_t> h_tiles[4];
+    std::vector<ilg::ServeSlot> h_slots[kGroups];
+    std::vector<uint32_t> h_tiles[kGroups];
     std::vector<Req *> launched;
     std::vector<uint32_t> launched_steps;
 
@@ -188,18 +192,18 @@ public:
     {
         std::vector<ilg::ServeSlot> *slots = h_slots;
         std::vector<uint32_t> *tiles = h_tiles;
-        for (int g = 0; g < 4; ++g) {
+        for (int g = 0; g < kGroups; ++g) {
             slots[g].clear();
             tiles[g].clear();
         }
         launched = active;
         launched_steps = steps;
-        uint32_t maxsteps[4] = {0, 0, 0, 0};
+        uint32_t maxsteps[kGroups] = {};
         for (size_t i = 0; i < active.size(); ++i) {
             Req &r = *active[i];
             Payload *p = payload_of(r);
             const ilg_config &c = p->cfg;
-            const int g = group(c.q, c.count_bytes);
+            const int g = group(c.q, c.count_bytes, p->fx);
             ilg::ServeSlot s;
             std::memset(&s, 0, sizeof(s));
             s.state_off = r.mem_off / c.count_bytes;
@@ -222,9 +226,11 @@ public:
             tiles[g].insert(tiles[g].end(), nt, idx);
             maxsteps[g] = std::max(maxsteps[g], steps[i]);
         }
-        for (int g = 0; g < 4; ++g) {
+        for (int g = 0; g < kGroups; ++g) {
             if (slots[g].empty())
                 continue;
+            if (!streams[g])
+                SHIP(hipStreamCreateWithFlags(&streams[g], hipStreamNonBlocking));
             int rc = ensure(g, slots[g].size(), tiles[g].size());
             if (rc != ILG_OK)
                 return rc;
@@ -239,10 +245,11 @@ public:
             a.ntiles = (uint32_t)tiles[g].size();
             a.shared = shared;
             a.err = err;
-            const int q = g >= 2 ? 3 : 2, cb = (g & 1) ? 4 : 2;
+            const int q = (g & 8) ? 3 : 2, cb = (g & 4) ? 4 : 2, rounds = (g & 2) ? 7 : 10;
+            const bool exchange = (g & 1) != 0;
             for (uint32_t j = 0; j < maxsteps[g]; ++j) {
                 a.j = j;
-                hipError_t e = ilg::launch_serve(q, cb, a, streams[g]);
+                hipError_t e = ilg::launch_serve(q, cb, rounds, exchange, a, streams[g]);
                 if (e != hipSuccess)
                     return shfail(e, "serve launch");
             }
@@ -252,7 +259,7 @@ public:
 
     int wait() override
     {
-        for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < kGroups; ++g)
             if (!h_slots[g].empty())
                 SHIP(hipStreamSynchronize(streams[g]));
         uint32_t e = 0;
@@ -301,7 +308,7 @@ public:
 
     ~DeviceExecutor() override
     {
-        for (int g = 0; g < 4; ++g) {
+        for (int g = 0; g < kGroups; ++g) {
             (void)hipFree(d_slots[g]);
             (void)hipFree(d_tiles[g]);
             if (streams[g])
@@ -345,8 +352,6 @@ int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server 
         e = hipMalloc(&ex.shared, ilg::kServeTableBytes + ilg::kServeGuideBytes);
     if (e == hipSuccess)
         e = hipMalloc((void **)&ex.err, sizeof(uint32_t));
-    for (int g = 0; g < 4 && e == hipSuccess; ++g)
-        e = hipStreamCreateWithFlags(&ex.streams[g], hipStreamNonBlocking);
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&ex.io, hipStreamNonBlocking);
     if (e == hipSuccess) {
@@ -380,10 +385,6 @@ int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_hos
         return rc;
     if (cfg->q == 5)
         return sfail(ILG_E_INVALID, "D2Q5 lattices run in the plain form only");
-    if (fx.rounds != 10)
-        return sfail(ILG_E_INVALID, "7-round draws run in the plain form only");
-    if (fx.exchange)
-        return sfail(ILG_E_INVALID, "the exchange form runs in the plain form only");
     if (nsteps == 0)
         return sfail(ILG_E_INVALID, "nsteps must be positive");
     if (cfg->t0 + nsteps > (uint64_t(1) << 32))
@@ -417,10 +418,6 @@ int ilg_server_submit_poisson_sine(ilg_server *s, const ilg_config *cfg, double 
         return rc;
     if (cfg->q == 5)
         return sfail(ILG_E_INVALID, "D2Q5 lattices run in the plain form only");
-    if (fx.rounds != 10)
-        return sfail(ILG_E_INVALID, "7-round draws run in the plain form only");
-    if (fx.exchange)
-        return sfail(ILG_E_INVALID, "the exchange form runs in the plain form only");
     if (nsteps == 0)
         return sfail(ILG_E_INVALID, "nsteps must be positive");
     if (cfg->t0 + nsteps > (uint64_t(1) << 32))
@@ -511,7 +508,7 @@ int ilg_server_destroy(ilg_server *s)
     if (!s)
         return ILG_OK;
     (void)s->sched->settle(s->ex, &steady_now, nullptr);
-    for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < DeviceExecutor::kGroups; ++g)
         if (s->ex.streams[g])
             (void)hipStreamSynchronize(s->ex.streams[g]);
     delete s;

@@ -4,8 +4,9 @@ fixed-point crossing probability, every compared step bit-exact over ragged
 lengths, both count types, multi-chunk counts, special rates (the zero
 collision fraction shares the three-binomial kernel), combined with 7-round
 draws, a 2^24-node lattice with light-cone samples, and the rejection of the
-flag for q != 2, by the serving form and in a batch of mixed specifications
-(batched parity: test_gpu_batch_specs.py)."""
+flag for q != 2 (plain and serving forms) and in a batch of mixed
+specifications (batched parity: test_gpu_batch_specs.py; serving:
+test_gpu_serve.py)."""
 import sys
 
 import numpy as np
@@ -119,8 +120,6 @@ def test_rejections(ilg):
     srv = ilg.Server(1 << 20, 10)
     try:
         with pytest.raises(ilg.IlgError):
-            srv.submit(m, init, 5)
-        with pytest.raises(ilg.IlgError):
-            srv.submit_poisson_sine(m, 10.0, 0.0, 1, 5)
+            srv.submit(dict(m, q=3), np.ones((3, 64), dtype=np.uint16), 5)
     finally:
         srv.close()

@@ -4,8 +4,8 @@ step bit-exact for D1Q2, D1Q3 and D2Q5, both count types, ragged lengths,
 multi-chunk counts (Philox blocks drawn on demand), special rates (the zero
 collision fraction shares the 10-round kernel), a full 2^24-node D1Q3 lattice
 in the benchmark's launch configuration with light-cone samples, and the
-rejection of the flag by the serving form and of mixed specifications in a
-batch (batched parity: test_gpu_batch_specs.py)."""
+rejection of mixed specifications in a batch (batched parity:
+test_gpu_batch_specs.py; serving: test_gpu_serve.py)."""
 import sys
 
 import numpy as np
@@ -140,16 +140,8 @@ def test_full_size_d1q3_l2_24_lightcone(ilg, oracle_lib):
         np.testing.assert_array_equal(win[:, T:T + 256], final[:, idx[T:T + 256]])
 
 
-def test_server_rejects_seven_rounds_and_batch_needs_one_spec(ilg):
+def test_batch_needs_one_spec(ilg):
     m = dict(q=3, length=64, count_bytes=2, omega=1.5, seed=1, rounds=7)
     init = np.ones((3, 64), dtype=np.uint16)
     with pytest.raises(ilg.IlgError):
         ilg.Batch([m, dict(m, rounds=10)], [init, init])
-    srv = ilg.Server(1 << 20, 10)
-    try:
-        with pytest.raises(ilg.IlgError):
-            srv.submit(m, init, 5)
-        with pytest.raises(ilg.IlgError):
-            srv.submit_poisson_sine(m, 10.0, 0.0, 1, 5)
-    finally:
-        srv.close()

@@ -42,7 +42,8 @@ def _requests(n, seed):
 
 def _alone(ilg, m, init, nsteps):
     lat = ilg.Lattice(m["q"], m["length"], m["count_bytes"], m["omega"], m["seed"], init,
-                      realization=m.get("realization", 0), t0=m.get("t0", 0))
+                      realization=m.get("realization", 0), t0=m.get("t0", 0),
+                      rounds=m.get("rounds", 10), exchange=m.get("exchange", False))
     lat.step(nsteps)
     out = lat.state()
     lat.close()
@@ -74,6 +75,39 @@ def test_mixed_requests_equal_alone_and_oracle(ilg, oracle_lib):
         np.testing.assert_array_equal(got, _alone(ilg, m, init, ns), err_msg=f"request {k}")
         if k % 8 == 0:
             p = oracle_lib.Params(m["q"], m["omega"])
+            ref, _, _ = oracle_lib.run(p, init, ns, seed=m["seed"], realization=m["realization"],
+                                       t0=m["t0"])
+            np.testing.assert_array_equal(got, ref, err_msg=f"request {k} vs oracle")
+    srv.close()
+
+
+def test_draw_specifications_in_one_server(ilg, oracle_lib):
+    """Requests under draw specifications v1, v2 (7 rounds) and v3 (D1Q2
+    exchange form, 10 or 7 rounds) share one server (one launch group per
+    specification): each result equals the same configuration run alone and,
+    for a sample, the oracle."""
+    base = _requests(36, seed=4)
+    specs = [(10, False), (7, False), (10, True), (7, True)]
+    reqs = []
+    for i, (m, init, ns) in enumerate(base):
+        rounds, exchange = specs[i % 4]
+        if exchange and m["q"] != 2:
+            exchange = False
+        reqs.append((dict(m, rounds=rounds, exchange=exchange), init, ns))
+    srv = ilg.Server(64 << 20, quantum_steps=29)
+    ids = [srv.submit(m, init, ns) for m, init, ns in reqs]
+    polls = 0
+    while True:
+        st = srv.poll()
+        polls += 1
+        if st["active"] == 0 and st["queued"] == 0:
+            break
+        assert polls < 1000
+    for k, (m, init, ns) in enumerate(reqs):
+        got = srv.result(ids[k])
+        np.testing.assert_array_equal(got, _alone(ilg, m, init, ns), err_msg=f"request {k}")
+        if k % 5 == 0:
+            p = oracle_lib.Params(m["q"], m["omega"], rounds=m["rounds"], exchange=m["exchange"])
             ref, _, _ = oracle_lib.run(p, init, ns, seed=m["seed"], realization=m["realization"],
                                        t0=m["t0"])
             np.testing.assert_array_equal(got, ref, err_msg=f"request {k} vs oracle")
