@@ -264,14 +264,15 @@ def bench_batched_decay(ilg, W, stream, steps: int):
             "node_updates_per_s": nu / sec, "seconds": sec, "node_updates": nu, "shape": shape}
 
 
-def bench_serving(ilg, W, rate: float, duration: float, budget: int, quantum: int):
+def bench_serving(ilg, W, rate: float, duration: float, budget: int, quantum: int,
+                  step_nodes: int = 0):
     """Replay a Poisson request stream in real time through the server: each
     request is submitted once its arrival time has passed, every loop iteration
     polls once (admit, one quantum of shared launches, retire).  Latency is
     completion minus arrival."""
     reqs = W.request_stream(rate_per_s=rate, duration_s=duration)
     pool = W.RequestInitPool()
-    srv = ilg.Server(budget, quantum)
+    srv = ilg.Server(budget, quantum, step_nodes=step_nodes)
     clock = ilg.Server.clock
     t0 = clock()
     i = 0
@@ -357,6 +358,9 @@ def main():
                     help="comma list of plain (always), mallfree, philox7, exchange, d2q5, "
                          "batched, batched_specs, decay, serving")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-step-nodes", type=int, default=0,
+                    help="server policy: at most this many nodes advanced per quantum, least "
+                         "remaining work first (0: every active request)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--serve-quantum", type=int, default=100)
@@ -459,7 +463,7 @@ def main():
             say(f"serving at {frac:g} x {args.serve_rate:g} req/s for {args.serve_seconds:g} s")
             out["serving"].append(bench_serving(ilg, W, args.serve_rate * frac, args.serve_seconds,
                                                 int(args.serve_budget_gib * (1 << 30)),
-                                                args.serve_quantum))
+                                                args.serve_quantum, args.serve_step_nodes))
     if not args.no_cpu_baseline:
         say(f"cpu baseline (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(init, spec, args.cpu_seconds)

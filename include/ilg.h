@@ -272,10 +272,11 @@ int ilg_batch_destroy(ilg_batch *b);
  * its initial state and a step count) queue in FIFO order until their device
  * memory (double-buffered state and fixed-point tables) fits the budget;
  * admitted requests become active slots whose state stays on the device.
- * Each ilg_server_poll admits what fits, advances every active request by
+ * Each ilg_server_poll admits what fits, advances every active request (or,
+ * under a step node cap, those with the least remaining work that fit it) by
  * up to quantum_steps steps in shared launches (one per step and per
- * (q, count type) group, groups on separate streams), and retires finished
- * requests to host memory.  A request's result is bit-identical to the same
+ * (q, count type, draw specification) group, groups on separate streams),
+ * and retires finished requests to host memory.  A request's result is bit-identical to the same
  * configuration run alone through ilg_create/ilg_step.
  * ---------------------------------------------------------------------- */
 typedef struct ilg_server ilg_server; /* opaque; owned by the library */
@@ -307,6 +308,16 @@ double ilg_server_clock(void);
 /* Server owning a device arena of budget_bytes; every poll advances active
  * requests by up to quantum_steps steps. */
 int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server **out);
+
+/* Scheduling policy of the polls that follow.  max_nodes = 0 (the default):
+ * every poll advances every active request.  max_nodes > 0: a poll advances
+ * the active requests in increasing order of remaining work (nodes x steps
+ * left, ties by id), skipping any that would bring the quantum's total past
+ * max_nodes nodes, and always at least one.  Every launch advances its
+ * requests by one step in time proportional to the nodes it holds, so near
+ * saturation this shortens the typical latency; a request can wait while
+ * smaller ones keep arriving.  Results do not depend on the policy. */
+int ilg_server_set_step_nodes(ilg_server *s, uint64_t max_nodes);
 
 /* Queue a request: cfg (q = 2 or 3), host [q][L] initial counts (copied),
  * nsteps > 0.  ILG_E_BUSY if it can never fit the budget. */

@@ -118,6 +118,7 @@ def _load():
         "ilg_batch_destroy": ([hp], i32),
         "ilg_server_clock": ([], ctypes.c_double),
         "ilg_server_create": ([u64, u32, ctypes.POINTER(hp)], i32),
+        "ilg_server_set_step_nodes": ([hp, u64], i32),
         "ilg_server_submit": ([hp, cfgp, vp, u64, ctypes.POINTER(u64)], i32),
         "ilg_server_submit_poisson_sine": ([hp, cfgp, ctypes.c_double, ctypes.c_double, u64, u64,
                                             ctypes.POINTER(u64)], i32),
@@ -390,10 +391,17 @@ REQ_STATES = {0: "queued", 1: "active", 2: "done", 3: "cancelled"}
 class Server:
     """Continuous-batching request server (ilg_server_*)."""
 
-    def __init__(self, budget_bytes: int, quantum_steps: int = 100):
+    def __init__(self, budget_bytes: int, quantum_steps: int = 100, step_nodes: int = 0):
         self._h = ctypes.c_void_p()
         check(lib.ilg_server_create(budget_bytes, quantum_steps, ctypes.byref(self._h)))
+        if step_nodes:
+            self.set_step_nodes(step_nodes)
         self._shapes = {}
+
+    def set_step_nodes(self, max_nodes: int):
+        """Advance at most max_nodes nodes per quantum, least remaining work
+        first (0: every active request)."""
+        check(lib.ilg_server_set_step_nodes(self._h, max_nodes))
 
     @staticmethod
     def clock() -> float:

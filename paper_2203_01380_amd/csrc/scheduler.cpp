@@ -137,6 +137,30 @@ int Scheduler::admit(Executor &ex, double (*clock)(), uint32_t *admitted)
     return 0;
 }
 
+void Scheduler::pick(std::vector<Req *> *out) const
+{
+    if (step_nodes_ == 0) {
+        *out = active_;
+        return;
+    }
+    // Least remaining work first (ties by id), greedily within the cap; a
+    // request that does not fit is passed over for smaller ones after it.
+    std::vector<Req *> order(active_);
+    std::stable_sort(order.begin(), order.end(), [](const Req *a, const Req *b) {
+        const uint64_t wa = a->nodes * (a->total - a->done);
+        const uint64_t wb = b->nodes * (b->total - b->done);
+        return wa != wb ? wa < wb : a->id < b->id;
+    });
+    out->clear();
+    uint64_t used = 0;
+    for (Req *r : order) {
+        if (!out->empty() && used + r->nodes > step_nodes_)
+            continue;
+        out->push_back(r);
+        used += r->nodes;
+    }
+}
+
 int Scheduler::poll(Executor &ex, PollStats *st, double (*clock)())
 {
     PollStats s;
@@ -151,10 +175,10 @@ int Scheduler::poll(Executor &ex, PollStats *st, double (*clock)())
     if (rc != 0)
         return rc;
     if (!active_.empty()) {
-        inflight_ = active_;
-        inflight_steps_.resize(active_.size());
-        for (size_t i = 0; i < active_.size(); ++i) {
-            const uint64_t left = active_[i]->total - active_[i]->done;
+        pick(&inflight_);
+        inflight_steps_.resize(inflight_.size());
+        for (size_t i = 0; i < inflight_.size(); ++i) {
+            const uint64_t left = inflight_[i]->total - inflight_[i]->done;
             inflight_steps_[i] = (uint32_t)std::min<uint64_t>(left, quantum_);
             s.quantum_steps = std::max(s.quantum_steps, inflight_steps_[i]);
         }

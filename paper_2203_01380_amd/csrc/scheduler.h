@@ -6,8 +6,13 @@
 // in flight), waits for the quantum launched by the previous poll, retires the
 // requests it finished (freeing their memory), admits again, and launches the
 // next quantum for every active slot (fewer steps for a slot that finishes
-// earlier).  It returns while the device works, so the caller's host work
-// overlaps the quantum.  The executor does the device work; the scheduler only
+// earlier).  With a node cap (set_step_nodes) a quantum advances only the
+// active requests with the least remaining work (nodes x steps left) that
+// fit the cap together, at least one: shortest-remaining-work first, which
+// shortens the typical latency while the device is near saturation, since
+// every launch advances its requests by one step and costs time in
+// proportion to the nodes it holds.  It returns while the device works, so
+// the caller's host work overlaps the quantum.  The executor does the device work; the scheduler only
 // does bookkeeping, so it is tested on the CPU with a counting executor.
 #pragma once
 
@@ -25,6 +30,7 @@ enum class ReqState : uint32_t { Queued = 0, Active = 1, Done = 2, Cancelled = 3
 struct Req {
     uint64_t id = 0;
     uint32_t q = 0;
+    uint64_t nodes = 0;     // lattice nodes (for the step node cap)
     uint64_t bytes = 0;     // device bytes while active (from the executor's layout)
     uint64_t total = 0;     // steps requested
     uint64_t done = 0;      // steps taken so far
@@ -92,12 +98,16 @@ public:
     uint64_t used_bytes() const { return arena_.used(); }
     size_t queued() const { return queue_.size(); }
     size_t active() const { return active_.size(); }
+    // At most this many nodes advanced per quantum (0: every active request).
+    void set_step_nodes(uint64_t nodes) { step_nodes_ = nodes; }
 
 private:
     int admit(Executor &ex, double (*clock)(), uint32_t *admitted);
+    void pick(std::vector<Req *> *out) const;
 
     uint64_t budget_;
     uint32_t quantum_;
+    uint64_t step_nodes_ = 0;
     Arena arena_;
     uint64_t next_id_ = 1;
     std::deque<Req *> queue_;

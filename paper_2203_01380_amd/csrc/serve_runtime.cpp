@@ -374,6 +374,14 @@ int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server 
     return ILG_OK;
 }
 
+int ilg_server_set_step_nodes(ilg_server *s, uint64_t max_nodes)
+{
+    if (!s)
+        return sfail(ILG_E_INVALID, "null server");
+    s->sched->set_step_nodes(max_nodes);
+    return ILG_OK;
+}
+
 int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_host, uint64_t nsteps,
                       uint64_t *id)
 {
@@ -397,6 +405,7 @@ int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_hos
                    static_cast<const unsigned char *>(init_host) + bytes);
     std::unique_ptr<Req> r(new Req);
     r->q = cfg->q;
+    r->nodes = cfg->length;
     r->total = nsteps;
     r->payload = p;
     if (!s->sched->submit(std::move(r), s->ex, id, steady_now()))
@@ -431,6 +440,7 @@ int ilg_server_submit_poisson_sine(ilg_server *s, const ilg_config *cfg, double 
     p->init_seed = init_seed;
     std::unique_ptr<Req> r(new Req);
     r->q = cfg->q;
+    r->nodes = cfg->length;
     r->total = nsteps;
     r->payload = p;
     if (!s->sched->submit(std::move(r), s->ex, id, steady_now()))

@@ -21,6 +21,8 @@ struct Counting : Executor {
     uint64_t budget = 0;
     std::map<uint64_t, uint64_t> steps_seen, loads, unloads;
     std::vector<uint64_t> load_order;
+    std::vector<uint64_t> last_launch;  // ids of the last launch, in order
+    uint64_t step_nodes = 0;            // node cap the scheduler was given
     uint64_t active_bytes = 0;
     int violations = 0;
     uint64_t footprint(const Req &r) override
@@ -42,6 +44,14 @@ struct Counting : Executor {
         if (in_flight)
             ++violations;  // a launch before the previous one was waited for
         in_flight = true;
+        last_launch.clear();
+        uint64_t nodes = 0;
+        for (const Req *r : active) {
+            last_launch.push_back(r->id);
+            nodes += r->nodes;
+        }
+        if (step_nodes != 0 && active.size() > 1 && nodes > step_nodes)
+            ++violations;  // more nodes than the cap in a multi-request quantum
         for (size_t i = 0; i < active.size(); ++i) {
             Req *r = active[i];
             if (r->state != ReqState::Active || steps[i] == 0 || steps[i] > quantum ||
@@ -97,6 +107,34 @@ void *h_new(uint64_t budget, uint32_t quantum)
 void h_free(void *h)
 {
     delete static_cast<Harness *>(h);
+}
+
+int h_submit_nodes(void *hv, uint32_t q, uint64_t bytes, uint64_t steps, uint64_t nodes,
+                   uint64_t *id)
+{
+    Harness *h = static_cast<Harness *>(hv);
+    std::unique_ptr<Req> r(new Req);
+    r->q = q;
+    r->nodes = nodes;
+    r->total = steps;
+    r->payload = std::make_shared<uint64_t>(bytes);
+    return h->sched.submit(std::move(r), h->ex, id, fake_now) ? 0 : -6;
+}
+
+void h_set_step_nodes(void *hv, uint64_t nodes)
+{
+    Harness *h = static_cast<Harness *>(hv);
+    h->sched.set_step_nodes(nodes);
+    h->ex.step_nodes = nodes;
+}
+
+int h_last_launch(void *hv, uint64_t *out, int cap)
+{
+    Harness *h = static_cast<Harness *>(hv);
+    int n = (int)h->ex.last_launch.size();
+    for (int i = 0; i < n && i < cap; ++i)
+        out[i] = h->ex.last_launch[i];
+    return n;
 }
 
 int h_submit(void *hv, uint32_t q, uint64_t bytes, uint64_t steps, uint64_t *id)

@@ -39,6 +39,10 @@ def H(tmp_path_factory):
     L.h_used.restype = ctypes.c_uint64
     L.h_violations.argtypes = [ctypes.c_void_p]
     L.h_load_order.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
+    L.h_submit_nodes.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                                 ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+    L.h_set_step_nodes.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    L.h_last_launch.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
     return L
 
 
@@ -60,6 +64,17 @@ class Sched:
         d, ta, td = ctypes.c_uint64(), ctypes.c_double(), ctypes.c_double()
         s = self.H.h_state(self.h, rid, ctypes.byref(d), ctypes.byref(ta), ctypes.byref(td))
         return s, int(d.value), ta.value, td.value
+
+    def submit_nodes(self, nodes, steps, nbytes=1000):
+        rid = ctypes.c_uint64()
+        rc = self.H.h_submit_nodes(self.h, 2, nbytes, steps, nodes, ctypes.byref(rid))
+        assert rc == 0
+        return int(rid.value)
+
+    def last_launch(self):
+        buf = (ctypes.c_uint64 * 4096)()
+        n = self.H.h_last_launch(self.h, buf, 4096)
+        return list(buf[:n])
 
     def load_order(self):
         buf = (ctypes.c_uint64 * 4096)()
@@ -129,6 +144,70 @@ def test_cancel_queued_and_active(H):
     assert H.h_cancel(s.h, c) != 0     # finished requests cannot be cancelled
     assert H.h_release(s.h, c) == 0 and s.state(c)[0] == -1
     assert H.h_violations(s.h) == 0
+    s.close()
+
+
+def test_step_node_cap_least_remaining_work_first(H):
+    """With a node cap a quantum advances the active requests in increasing
+    order of remaining work (nodes x steps left, ties by id) that fit the cap
+    together, passing over one that does not fit for smaller ones after it;
+    every request still completes exactly."""
+    s = Sched(H, 1 << 30, 10)
+    H.h_set_step_nodes(s.h, 1000)
+    # (nodes, steps): works 6000, 2000, 2000, 8000, 900, 10000
+    spec = [(600, 10), (100, 20), (200, 10), (800, 10), (90, 10), (1000, 10)]
+    ids = [s.submit_nodes(n, t) for n, t in spec]
+    s.poll()
+    # order by work: id4 (900), id1 (2000, lower id), id2 (2000), id0 (6000),
+    # id3 (8000), id5 (10000); 90 + 100 + 200 + 600 = 990 fit, 800 and 1000 not
+    assert s.last_launch() == [ids[4], ids[1], ids[2], ids[0]]
+    s.poll()   # ids 4, 2, 0 finished after 10 steps; id1 has 10 left (work 1000)
+    assert s.last_launch() == [ids[1], ids[3]]            # 100 + 800 <= 1000
+    s.poll()   # id1 and id3 finished
+    assert s.last_launch() == [ids[5]]                    # alone, at the cap
+    drain(s)
+    for rid, (n, t) in zip(ids, spec):
+        st, done, _, _ = s.state(rid)
+        assert st == 2 and done == t
+    assert H.h_violations(s.h) == 0
+    s.close()
+
+
+def test_step_node_cap_single_request_above_cap_and_off(H):
+    s = Sched(H, 1 << 30, 4)
+    H.h_set_step_nodes(s.h, 50)
+    big = s.submit_nodes(500, 8)          # above the cap: advanced alone
+    s.poll()
+    assert s.last_launch() == [big]
+    small = s.submit_nodes(10, 8)
+    s.poll()
+    assert s.last_launch() == [small]     # less remaining work, and both do not fit
+    H.h_set_step_nodes(s.h, 0)            # every active request again
+    s.poll()
+    assert sorted(s.last_launch()) == sorted([big, small])
+    drain(s)
+    assert s.state(big)[1] == 8 and s.state(small)[1] == 8
+    assert H.h_violations(s.h) == 0
+    s.close()
+
+
+def test_step_node_cap_random_workload(H):
+    rng = np.random.default_rng(4)
+    s = Sched(H, 1 << 22, 7)
+    H.h_set_step_nodes(s.h, 5000)
+    ids, want = [], {}
+    for it in range(400):
+        if rng.random() < 0.6:
+            n, t = int(rng.integers(1, 3000)), int(rng.integers(1, 60))
+            rid = s.submit_nodes(n, t, nbytes=int(rng.integers(100, 50000)))
+            ids.append(rid)
+            want[rid] = t
+        s.poll()
+    drain(s)
+    for rid in ids:
+        st, done, _, _ = s.state(rid)
+        assert st == 2 and done == want[rid]
+    assert H.h_violations(s.h) == 0 and H.h_used(s.h) == 0
     s.close()
 
 
