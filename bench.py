@@ -111,6 +111,75 @@ def cpu_baseline(init, spec, seconds: float):
                       f"({spec.length * steps} node-updates, {el:.1f} s)"}
 
 
+def cpu_other_configs(W, seconds: float):
+    """The oracle on bounded samples of the other workloads (each about
+    `seconds` of host time): the D1Q2 L = 256 case in full, and members or
+    requests of the batched, decay and serving workloads at their real
+    lengths for a few steps each."""
+    from oracle import oracle
+    threads = oracle.default_threads()
+
+    def run_members(items):
+        """items: (q, omega, seed, realization, init) lattices, 20 steps each,
+        one single-threaded oracle run per host thread at a time (the calls
+        release the interpreter lock), rounds over the items until `seconds`
+        have passed."""
+        from concurrent.futures import ThreadPoolExecutor
+        steps_each = 20
+
+        params = {}
+        for q, omega, _, _, _ in items:      # tables built once, outside the timing
+            params.setdefault((q, omega), oracle.Params(q, omega))
+
+        def one(item):
+            q, omega, seed, r, init = item
+            oracle.run(params[(q, omega)], init, steps_each, seed=seed, realization=r,
+                       nthreads=1)
+            return init.shape[1] * steps_each
+
+        work, k = 0, 0
+        with ThreadPoolExecutor(threads) as ex:
+            t0 = time.perf_counter()
+            while True:
+                work += sum(ex.map(one, items))
+                k += len(items)
+                el = time.perf_counter() - t0
+                if el >= seconds:
+                    return work / el, k, el
+
+    out = {}
+    spec, init = W.workload_d1q2_l256()
+    p1 = oracle.Params(spec.q, spec.omega)
+    t0 = time.perf_counter()
+    oracle.run(p1, init, spec.steps, seed=spec.seed, nthreads=1)
+    el = time.perf_counter() - t0
+    out["d1q2_l256"] = {"node_updates_per_s": spec.length * spec.steps / el, "cores": 1,
+                        "sample": f"the full run: {spec.steps} steps of L = 256 in {el:.2f} s"}
+    ens = W.ensemble_ragged_d1q2(steps=20)
+    order = np.argsort([s.length for s in ens.specs])
+    pick = order[np.linspace(0, len(order) - 1, 64).astype(int)]
+    rate, k, el = run_members([(2, ens.specs[r].omega, ens.specs[r].seed,
+                                ens.specs[r].realization, ens.inits[r]) for r in pick])
+    out["batched_ragged"] = {"node_updates_per_s": rate, "cores": threads,
+                             "sample": f"{k} member runs of 20 steps over 64 members spread "
+                                       f"by length ({el:.1f} s; no S(k))"}
+    ens = W.ensemble_decay_sweep(nper=1, steps=20)
+    rate, k, el = run_members([(3, s.omega, s.seed, s.realization, ens.inits[i])
+                               for i, s in enumerate(ens.specs)])
+    out["batched_decay"] = {"node_updates_per_s": rate, "cores": threads,
+                            "sample": f"{k} runs of 20 steps, one L = 4096 uint32 member per "
+                                      f"omega ({el:.1f} s; no A^LG)"}
+    reqs = W.request_stream(rate_per_s=200, duration_s=0.2)
+    pool = W.RequestInitPool(npool=2)
+    rate, k, el = run_members([(rq.spec.q, rq.spec.omega, rq.spec.seed, rq.spec.realization,
+                                pool.init(i, rq.spec.q, rq.spec.length))
+                               for i, rq in enumerate(reqs)])
+    out["serving_requests"] = {"node_updates_per_s": rate, "cores": threads,
+                               "sample": f"{k} runs of 20 steps over {len(reqs)} requests of the "
+                                         f"stream ({el:.1f} s)"}
+    return out
+
+
 def bench_plain_mall_free(ilg, W, stream, warmup: int, steps: int = 500):
     """The headline kernel on a lattice whose double-buffered state (768 MiB)
     does not fit the 256 MB MALL, so every step really streams from HBM."""
@@ -467,6 +536,8 @@ def main():
     if not args.no_cpu_baseline:
         say(f"cpu baseline (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(init, spec, args.cpu_seconds)
+        say("cpu baseline on the other workloads")
+        out["cpu_baseline"]["other_workloads"] = cpu_other_configs(W, args.cpu_seconds / 4)
     print(json.dumps(out), flush=True)
 
 
