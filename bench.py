@@ -319,6 +319,26 @@ def bench_batched_specs(ilg, W, stream, steps: int):
     return out
 
 
+def bench_batched_d2q5(ilg, stream, steps: int = 2000, n: int = 2048, side: int = 64):
+    """An ensemble of small D2Q5 lattices: n members of side x side nodes,
+    uint16, Poisson means (25, 25, 50, 25, 25), omega ~ U[1, 1.95], own seeds."""
+    rng = np.random.default_rng(12)
+    means = np.array([25.0, 25.0, 50.0, 25.0, 25.0])[:, None, None]
+    members, inits = [], []
+    for r in range(n):
+        members.append(dict(q=5, length=side, height=side, count_bytes=2,
+                            omega=float(rng.uniform(1.0, 1.95)), seed=20_000 + r, realization=r))
+        inits.append(rng.poisson(means, size=(5, side, side)).astype(np.uint16))
+    b = ilg.Batch(members, inits)
+    shape = b.tune(20)
+    sec = timed(stream, lambda: b.run(steps))
+    b.close()
+    nu = n * side * side * steps
+    return {"workload": f"{n} D2Q5 lattices of {side} x {side}, uint16, Poisson means "
+                        f"(25, 25, 50, 25, 25), omega ~ U[1, 1.95], own seeds, {steps} steps",
+            "node_updates_per_s": nu / sec, "seconds": sec, "node_updates": nu, "shape": shape}
+
+
 def bench_batched_decay(ilg, W, stream, steps: int):
     ens = W.ensemble_decay_sweep(steps=steps)
     members = [dict(q=s.q, length=s.length, count_bytes=s.count_bytes, omega=s.omega,
@@ -423,9 +443,9 @@ def main():
     ap.add_argument("--length", type=int, default=1 << 24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,mallfree,philox7,exchange,d2q5,batched,batched_specs,decay,serving",
+    ap.add_argument("--forms", default="plain,mallfree,philox7,exchange,d2q5,batched,batched_specs,batched_d2q5,decay,serving",
                     help="comma list of plain (always), mallfree, philox7, exchange, d2q5, "
-                         "batched, batched_specs, decay, serving")
+                         "batched, batched_specs, batched_d2q5, decay, serving")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-step-nodes", type=int, default=0,
                     help="server policy: at most this many nodes advanced per quantum, least "
@@ -523,6 +543,9 @@ def main():
     if "batched_specs" in forms:
         say("batched ragged ensemble under draw specifications v2 and v3")
         out["batched_specs"] = bench_batched_specs(ilg, W, stream, args.batched_steps)
+    if "batched_d2q5" in forms:
+        say("batched D2Q5 ensemble")
+        out["batched_d2q5"] = bench_batched_d2q5(ilg, stream)
     if "decay" in forms:
         say("batched decay sweep")
         out["batched_decay"] = bench_batched_decay(ilg, W, stream, args.decay_steps)

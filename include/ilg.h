@@ -233,8 +233,10 @@ typedef struct ilg_batch_diag {
 } ilg_batch_diag;
 
 /* cfgs[nreal] and inits[nreal] (host [q][L_r] compact counts, copied before
- * return).  diag may be NULL (no diagnostics).  q = 2 or 3 (D2Q5 runs in
- * the plain form only: ILG_E_INVALID). */
+ * return; [5][height][length] for D2Q5).  diag may be NULL (no
+ * diagnostics).  q = 2, 3 or 5; S(k) and A^LG are defined along a 1D
+ * lattice, so a D2Q5 batch with sk_every or amp_every set is refused
+ * (ILG_E_INVALID). */
 int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *inits,
                      const ilg_batch_diag *diag, void *stream, ilg_batch **out);
 

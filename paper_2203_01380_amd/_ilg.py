@@ -294,12 +294,20 @@ class Lattice:
             pass
 
 
+def _member_shape(m: dict) -> tuple:
+    """Host layout of a member's counts: [q][L], or [5][height][length]."""
+    if m["q"] == 5:
+        return (5, m["height"], m["length"])
+    return (m["q"], m["length"])
+
+
 class Batch:
     """An ensemble of independent lattices advanced by one persistent launch.
 
     members: sequence of dicts with keys q, length, count_bytes, omega, seed
-    and optionally realization, t0, theta, flip; inits: matching [q][L]
-    arrays.  Work goes to torch's current stream unless `stream` is given."""
+    and optionally realization, t0, theta, flip, rounds, exchange and (D2Q5)
+    height; inits: matching [q][L] arrays ([5][height][length] for D2Q5).
+    Work goes to torch's current stream unless `stream` is given."""
 
     def __init__(self, members, inits, sk_every: int = 0, nk: int = 0, amp_every: int = 0,
                  max_amp: int = 0, stream=None):
@@ -315,7 +323,7 @@ class Batch:
                                   m.get("flip", "auto"), m.get("height", 0),
                                   m.get("rounds", 10), m.get("exchange", False))
             a = np.ascontiguousarray(init, dtype=_dtype(m["count_bytes"]))
-            if a.shape != (m["q"], m["length"]):
+            if a.shape != _member_shape(m):
                 raise ValueError(f"member {r}: init shape {a.shape}")
             keep.append(a)
             ptrs[r] = a.ctypes.data
@@ -350,7 +358,7 @@ class Batch:
 
     def state(self, r: int) -> np.ndarray:
         m = self.members[r]
-        out = np.empty((m["q"], m["length"]), dtype=_dtype(m["count_bytes"]))
+        out = np.empty(_member_shape(m), dtype=_dtype(m["count_bytes"]))
         check(lib.ilg_batch_get_state(self._h, r, out.ctypes.data))
         return out
 

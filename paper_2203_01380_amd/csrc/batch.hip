@@ -22,7 +22,7 @@ int batch_shape_count()
 void batch_shape(int shape, int q, int *block, int *wg_per_cu)
 {
     *block = kShapes[shape].block;
-    *wg_per_cu = q == 3 ? kShapes[shape].wg_per_cu_q3 : kShapes[shape].wg_per_cu_q2;
+    *wg_per_cu = q == 2 ? kShapes[shape].wg_per_cu_q2 : kShapes[shape].wg_per_cu_q3;
 }
 
 hipError_t launch_batch_reset(uint32_t *queue, hipStream_t stream)
@@ -49,6 +49,10 @@ hipError_t launch_batch(int q, int count_bytes, int shape, const BatchArgs &a, h
         return launch_qt<3, uint16_t, 10, false>(shape, a, stream);
     if (q == 3 && count_bytes == 4)
         return launch_qt<3, uint32_t, 10, false>(shape, a, stream);
+    if (q == 5 && count_bytes == 2)
+        return launch_qt<5, uint16_t, 10, false>(shape, a, stream);
+    if (q == 5 && count_bytes == 4)
+        return launch_qt<5, uint32_t, 10, false>(shape, a, stream);
     return hipErrorInvalidValue;
 }
 

@@ -344,7 +344,7 @@ __device__ __forceinline__ BatchMeta read_meta(const BatchMeta *p)
     m.flip = q->flip;
     m.p_zero = q->p_zero;
     m.cur = q->cur;
-    m.pad = 0;
+    m.width = q->width;
     return m;
 }
 
@@ -358,8 +358,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kMinWaves
 void batch_kernel(BatchArgs a)
 {
     using W = typename Wide<T>::type;
-    constexpr int NB = (Q == 3) ? 2 : 1;
-    constexpr int kTabs = (Q == 3) ? 3 : 2;
+    constexpr int NB = (Q == 5) ? 3 : (Q == 3) ? 2 : 1;  // Philox blocks drawn up front
+    constexpr int kTabs = (Q == 2) ? 2 : 3;
+    static_assert(Q != 5 || !SK, "S(k) is defined for 1D members");
     constexpr int kRowGuide = 1 << GB;
     constexpr int kG = kChunk * kRowGuide;
     constexpr int kWaves = BLOCK / 64;
@@ -434,6 +435,12 @@ void batch_kernel(BatchArgs a)
                 av[Q - 1] = (W)*sampler::row_elem(row_hi, x);
                 if constexpr (Q == 3)
                     av[1] = (W)*sampler::row_elem(in + pitch, x);
+                if constexpr (Q == 5) {
+                    // the flip also swaps the y pair (rows 1 and 3)
+                    av[1] = (W)*sampler::row_elem(in + (flip ? 3 : 1) * pitch, x);
+                    av[2] = (W)*sampler::row_elem(in + 2 * pitch, x);
+                    av[3] = (W)*sampler::row_elem(in + (flip ? 1 : 3) * pitch, x);
+                }
                 if constexpr (EX) {
                     static_assert(Q == 2, "the exchange form is defined for D1Q2");
                     sampler::node_exchange<W, NB, GB, NR>(av, cn, x, t, m.realization, m.key0,
@@ -444,12 +451,37 @@ void batch_kernel(BatchArgs a)
                                                            tab_rest, g_rest, p_zero);
                 }
                 ovf |= sampler::or_all<Q, W>(cn);
-                const uint32_t xm = (x == 0) ? L - 1 : x - 1;
-                const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-                *sampler::row_elem(out, xm) = (T)cn[0];
-                *sampler::row_elem(out + outer, xp) = (T)cn[Q - 1];
-                if constexpr (Q == 3)
-                    *sampler::row_elem(out + pitch, x) = (T)cn[1];
+                if constexpr (Q == 5) {
+                    // D2Q5 on the node index x + Lx y, periodic in both
+                    // directions: -x, -y, rest, +y, +x.  The row and column
+                    // come from the pass's first node (one scalar division
+                    // per pass over the member).
+                    const uint32_t width = m.width;
+                    const uint32_t x0 = __builtin_amdgcn_readfirstlane(x - threadIdx.x);
+                    const uint32_t row0 = x0 / width;
+                    uint32_t cx = x0 - row0 * width + threadIdx.x, cy = row0;
+                    if (cx >= width) {
+                        const uint32_t k = cx / width;
+                        cx -= k * width;
+                        cy += k;
+                    }
+                    const uint32_t dxm = cx == 0 ? x + width - 1 : x - 1;
+                    const uint32_t dxp = cx + 1 == width ? x + 1 - width : x + 1;
+                    const uint32_t dym = cy == 0 ? x + (L - width) : x - width;
+                    const uint32_t dyp = x + width >= L ? x + width - L : x + width;
+                    *sampler::row_elem(out, dxm) = (T)cn[0];
+                    *sampler::row_elem(out + pitch, dym) = (T)cn[1];
+                    *sampler::row_elem(out + 2 * pitch, x) = (T)cn[2];
+                    *sampler::row_elem(out + 3 * pitch, dyp) = (T)cn[3];
+                    *sampler::row_elem(out + 4 * pitch, dxp) = (T)cn[4];
+                } else {
+                    const uint32_t xm = (x == 0) ? L - 1 : x - 1;
+                    const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+                    *sampler::row_elem(out, xm) = (T)cn[0];
+                    *sampler::row_elem(out + outer, xp) = (T)cn[Q - 1];
+                    if constexpr (Q == 3)
+                        *sampler::row_elem(out + pitch, x) = (T)cn[1];
+                }
             }
             __syncthreads();
             cur ^= 1u;
@@ -459,7 +491,7 @@ void batch_kernel(BatchArgs a)
                 if (a.sk_every != 0 && t_after % a.sk_every == 0)
                     sk_sample<Q, T, BLOCK>(a, r, st, L, pitch, s_twr, s_twi, s_red, s_redu);
             }
-            if (a.amp_every != 0 && t_after % a.amp_every == 0) {
+            if (Q != 5 && a.amp_every != 0 && t_after % a.amp_every == 0) {
                 const double amp = amp_sample<Q, T, BLOCK>(st, L, pitch, s_twr, s_twi, s_red);
                 if (threadIdx.x == 0) {
                     const uint32_t c = a.amp_cnt[r];
@@ -501,12 +533,19 @@ hipError_t launch_shape(const BatchArgs &a, hipStream_t stream, int wg_per_cu)
         grid = a.nreal;
     if (grid == 0)
         grid = 1;
-    if (a.sk_every != 0)
-        hipLaunchKernelGGL((batch_kernel<Q, T, BLOCK, GB, true, NR, EX>), dim3(grid), dim3(BLOCK), 0,
-                           stream, a);
-    else
-        hipLaunchKernelGGL((batch_kernel<Q, T, BLOCK, GB, false, NR, EX>), dim3(grid), dim3(BLOCK), 0,
-                           stream, a);
+    if constexpr (Q == 5) {
+        if (a.sk_every != 0)
+            return hipErrorInvalidValue;  // S(k) is defined for 1D members
+        hipLaunchKernelGGL((batch_kernel<Q, T, BLOCK, GB, false, NR, EX>), dim3(grid), dim3(BLOCK),
+                           0, stream, a);
+    } else {
+        if (a.sk_every != 0)
+            hipLaunchKernelGGL((batch_kernel<Q, T, BLOCK, GB, true, NR, EX>), dim3(grid),
+                               dim3(BLOCK), 0, stream, a);
+        else
+            hipLaunchKernelGGL((batch_kernel<Q, T, BLOCK, GB, false, NR, EX>), dim3(grid),
+                               dim3(BLOCK), 0, stream, a);
+    }
     return hipGetLastError();
 }
 
@@ -529,7 +568,7 @@ template <int Q, typename T, int NR, bool EX>
 hipError_t launch_qt(int shape, const BatchArgs &a, hipStream_t stream)
 {
     const Shape &s = kShapes[shape];
-    const int wg = (Q == 3) ? s.wg_per_cu_q3 : s.wg_per_cu_q2;
+    const int wg = (Q == 2) ? s.wg_per_cu_q2 : s.wg_per_cu_q3;  // q = 3, 5: three tables
     if (s.guide_bits == 8)
         return launch_block<Q, T, 8, NR, EX>(s.block, a, stream, wg);
     return launch_block<Q, T, 6, NR, EX>(s.block, a, stream, wg);

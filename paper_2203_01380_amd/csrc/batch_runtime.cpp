@@ -137,8 +137,6 @@ int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *
         int rc = ilg::check_config(&cfgs[r], &fx[r]);
         if (rc != ILG_OK)
             return rc;
-        if (cfgs[r].q == 5)
-            return bfail(ILG_E_INVALID, "D2Q5 lattices run in the plain form only");
         if (fx[r].rounds != fx[0].rounds || fx[r].exchange != fx[0].exchange)
             return bfail(ILG_E_INVALID,
                          "batch members must share the draw specification (flags "
@@ -146,7 +144,7 @@ int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *
         if (!inits[r])
             return bfail(ILG_E_INVALID, "null initial state");
         if (cfgs[r].q != cfgs[0].q || cfgs[r].count_bytes != cfgs[0].count_bytes ||
-            (cfgs[0].q == 3 && fx[r].p_rest != fx[0].p_rest))
+            (cfgs[0].q != 2 && fx[r].p_rest != fx[0].p_rest))
             return bfail(ILG_E_INVALID, "batch members must share q, count_bytes and theta");
     }
     ilg_batch_diag d{0, 0, 0, 0};
@@ -156,6 +154,8 @@ int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *
             return bfail(ILG_E_INVALID, "nk must lie in 1..ILG_BATCH_MAX_K");
         if (!d.sk_every)
             d.nk = 0;
+        if (cfgs[0].q == 5 && (d.sk_every || d.amp_every))
+            return bfail(ILG_E_INVALID, "S(k) and A^LG are defined for 1D members");
         if (!d.amp_every)
             d.max_amp = 0;
     }
@@ -179,7 +179,9 @@ int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *
     b->off.resize(nreal);
     uint64_t off = 0;
     for (uint32_t r = 0; r < nreal; ++r) {
-        const uint64_t L = cfgs[r].length, pitch = pitch_of(L);
+        // nodes: L in 1D, Lx Ly for D2Q5 (node x + Lx y)
+        const uint64_t L = cfgs[r].length * (q == 5 ? (uint64_t)cfgs[r].height : 1u);
+        const uint64_t pitch = pitch_of(L);
         b->lengths[r] = (uint32_t)L;
         b->t_next[r] = cfgs[r].t0;
         b->off[r] = off;
@@ -187,6 +189,7 @@ int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *
         std::memset(&m, 0, sizeof(m));
         m.off = off;
         m.length = (uint32_t)L;
+        m.width = (uint32_t)cfgs[r].length;
         m.pitch = (uint32_t)pitch;
         m.t = (uint32_t)cfgs[r].t0;
         m.realization = cfgs[r].realization;
@@ -232,7 +235,7 @@ int ilg_batch_create(const ilg_config *cfgs, uint32_t nreal, const void *const *
         std::vector<uint32_t> packed(ilg::kTableEntries);
         ilg::build_binomial_table(uint64_t(1) << 31, packed.data());
         ilg::pad_table(packed.data(), shared.data());
-        if (q == 3) {
+        if (q != 2) {
             ilg::build_binomial_table(fx[0].p_rest, packed.data());
             ilg::pad_table(packed.data(), shared.data() + ilg::kDevTableEntries);
         }

@@ -141,7 +141,7 @@ struct BatchMeta {
     uint32_t realization, key0, key1;
     uint32_t flip, p_zero;
     uint32_t cur;          // which buffer holds the current state
-    uint32_t pad;
+    uint32_t width;        // nodes per row: Lx for D2Q5 (length = Lx Ly), L in 1D
 };
 
 constexpr int kBatchMaxK = 16;
@@ -151,7 +151,7 @@ struct BatchArgs {
     void *arena;
     BatchMeta *meta;
     const uint32_t *tabs_p;       // [nreal][kDevTableEntries] removal tables
-    const uint32_t *tabs_shared;  // [2][kDevTableEntries]: P = 2^31, P = P_rest
+    const uint32_t *tabs_shared;  // [2][kDevTableEntries]: P = 2^31, P = P_rest (q = 3, 5)
     const uint32_t *order;        // members, longest first
     uint32_t *queue;              // next index into order
     uint32_t nreal;
