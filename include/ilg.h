@@ -321,8 +321,9 @@ int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server 
  * smaller ones keep arriving.  Results do not depend on the policy. */
 int ilg_server_set_step_nodes(ilg_server *s, uint64_t max_nodes);
 
-/* Queue a request: cfg (q = 2 or 3), host [q][L] initial counts (copied),
- * nsteps > 0.  ILG_E_BUSY if it can never fit the budget. */
+/* Queue a request: cfg (q = 2, 3 or 5), host initial counts (copied):
+ * [q][L], or [5][height][length] for D2Q5; nsteps > 0.  ILG_E_BUSY if it can
+ * never fit the budget. */
 int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_host,
                       uint64_t nsteps, uint64_t *id);
 

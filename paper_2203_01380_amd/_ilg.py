@@ -422,12 +422,12 @@ class Server:
                           member.get("height", 0), member.get("rounds", 10),
                           member.get("exchange", False))
         a = np.ascontiguousarray(init, dtype=_dtype(member["count_bytes"]))
-        if a.shape != (member["q"], member["length"]):
+        if a.shape != _member_shape(member):
             raise ValueError(f"init shape {a.shape}")
         rid = ctypes.c_uint64()
         check(lib.ilg_server_submit(self._h, ctypes.byref(cfg), a.ctypes.data, nsteps,
                                     ctypes.byref(rid)))
-        self._shapes[int(rid.value)] = (member["q"], member["length"], member["count_bytes"])
+        self._shapes[int(rid.value)] = (_member_shape(member), member["count_bytes"])
         return int(rid.value)
 
     def submit_poisson_sine(self, member: dict, nave: float, amp: float, init_seed: int,
@@ -443,7 +443,7 @@ class Server:
         check(lib.ilg_server_submit_poisson_sine(self._h, ctypes.byref(cfg), float(nave),
                                                  float(amp), int(init_seed), nsteps,
                                                  ctypes.byref(rid)))
-        self._shapes[int(rid.value)] = (member["q"], member["length"], member["count_bytes"])
+        self._shapes[int(rid.value)] = (_member_shape(member), member["count_bytes"])
         return int(rid.value)
 
     def poll(self) -> dict:
@@ -459,8 +459,8 @@ class Server:
         return d
 
     def result(self, rid: int) -> np.ndarray:
-        q, L, cb = self._shapes[rid]
-        out = np.empty((q, L), dtype=_dtype(cb))
+        shape, cb = self._shapes[rid]
+        out = np.empty(shape, dtype=_dtype(cb))
         check(lib.ilg_server_result(self._h, rid, out.ctypes.data))
         del self._shapes[rid]
         return out

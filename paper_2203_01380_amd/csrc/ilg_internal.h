@@ -183,7 +183,8 @@ hipError_t launch_batch_ex(int q, int count_bytes, int shape, const BatchArgs &a
 struct ServeSlot {
     uint64_t state_off;    // element offset of buffer 0 (buffer 1 at q*pitch)
     uint64_t table_off;    // byte offset of the slot's table set
-    uint32_t length, pitch;
+    uint32_t length, pitch;  // nodes (Lx Ly for D2Q5) and row pitch
+    uint32_t width;          // D2Q5: nodes per lattice row (Lx); 1D: L
     uint32_t t0;           // absolute index of the quantum's first step
     uint32_t steps;        // steps in this quantum
     uint32_t realization, key0, key1;
@@ -192,12 +193,12 @@ struct ServeSlot {
 };
 constexpr int kServeGuideBits = 8;
 constexpr int kServeTile = 1024;  // nodes per tile (one workgroup pass)
-// Slot table set: removal table, rest table (q = 3), then their guides.
+// Slot table set: removal table, rest table (q = 3, 5), then their guides.
 constexpr size_t kServeTableBytes = kDevTableEntries * sizeof(uint32_t);
 constexpr size_t kServeGuideBytes = (size_t)kChunk << kServeGuideBits;
 inline size_t serve_table_set_bytes(int q)
 {
-    return (q == 3 ? 2 : 1) * (kServeTableBytes + kServeGuideBytes);
+    return (q == 2 ? 1 : 2) * (kServeTableBytes + kServeGuideBytes);
 }
 
 struct ServeArgs {

@@ -1,4 +1,5 @@
-// Multi-slot lattice-gas step for the continuous-batching server.
+// Multi-slot lattice-gas step for the continuous-batching server (D1Q2, D1Q3
+// and D2Q5 requests).
 //
 // One launch advances every active request (slot) of one (q, count type) by
 // one step: the host lists the slots' tiles of 1024 nodes, slot by slot (each
@@ -36,6 +37,7 @@ __device__ __forceinline__ ServeSlot read_slot(const ServeSlot *p)
     s.table_off = q->table_off;
     s.length = q->length;
     s.pitch = q->pitch;
+    s.width = q->width;
     s.t0 = q->t0;
     s.steps = q->steps;
     s.realization = q->realization;
@@ -56,9 +58,9 @@ template <int Q, typename T, int NR, bool EX>
 __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
 {
     using W = typename Wide<T>::type;
-    constexpr int NB = (Q == 3) ? 2 : 1;
+    constexpr int NB = (Q == 5) ? 3 : (Q == 3) ? 2 : 1;  // Philox blocks drawn up front
     constexpr int GB = kServeGuideBits;
-    constexpr int kTabs = (Q == 3) ? 3 : 2;
+    constexpr int kTabs = (Q == 2) ? 2 : 3;
     constexpr int kG = kChunk << GB;
     // tables first, then guides (nonzero guide addresses fold into offsets)
     constexpr int kTabBytes = kTabs * kDevTableEntries * (int)sizeof(uint32_t);
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
             // after it (the new tables are visible).
             __syncthreads();
             const uint8_t *set = reinterpret_cast<const uint8_t *>(a.arena) + sl.table_off;
-            const int nt = (Q == 3) ? 2 : 1;  // removal (+ rest) tables
+            const int nt = (Q == 2) ? 1 : 2;  // removal (+ rest) tables
             for (int t = 0; t < nt; ++t) {
                 const uint4 *src = reinterpret_cast<const uint4 *>(set + t * kServeTableBytes);
                 uint4 *dst = reinterpret_cast<uint4 *>(s_tab + (t == 0 ? 0 : 2) * kDevTableEntries);
@@ -141,6 +143,12 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         av[Q - 1] = (W)*sampler::row_elem(row_hi, x);
         if constexpr (Q == 3)
             av[1] = (W)*sampler::row_elem(in + pitch, x);
+        if constexpr (Q == 5) {
+            // the flip also swaps the y pair (rows 1 and 3)
+            av[1] = (W)*sampler::row_elem(in + (sl.flip ? 3 : 1) * pitch, x);
+            av[2] = (W)*sampler::row_elem(in + 2 * pitch, x);
+            av[3] = (W)*sampler::row_elem(in + (sl.flip ? 1 : 3) * pitch, x);
+        }
         // The key words are uniform; saying so keeps their round schedule in
         // scalar registers (as operands of the Philox xors).
         const uint32_t key0 = __builtin_amdgcn_readfirstlane(sl.key0);
@@ -155,12 +163,36 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
                                                    g_rest, sl.p_zero != 0);
         }
         ovf |= sampler::or_all<Q, W>(cn);
-        const uint32_t xm = (x == 0) ? L - 1 : x - 1;
-        const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-        *sampler::row_elem(out, xm) = (T)cn[0];
-        *sampler::row_elem(out + (uint64_t)(Q - 1) * pitch, xp) = (T)cn[Q - 1];
-        if constexpr (Q == 3)
-            *sampler::row_elem(out + pitch, x) = (T)cn[1];
+        if constexpr (Q == 5) {
+            // D2Q5 on the node index x + Lx y, periodic in both directions:
+            // -x, -y, rest, +y, +x.  Row and column of the tile's first node
+            // by one scalar division.
+            const uint32_t width = sl.width;
+            const uint32_t x0 = (tile - sl.tile_begin) * (uint32_t)kBlock;
+            const uint32_t row0 = x0 / width;
+            uint32_t cx = x0 - row0 * width + threadIdx.x, cy = row0;
+            if (cx >= width) {
+                const uint32_t k = cx / width;
+                cx -= k * width;
+                cy += k;
+            }
+            const uint32_t dxm = cx == 0 ? x + width - 1 : x - 1;
+            const uint32_t dxp = cx + 1 == width ? x + 1 - width : x + 1;
+            const uint32_t dym = cy == 0 ? x + (L - width) : x - width;
+            const uint32_t dyp = x + width >= L ? x + width - L : x + width;
+            *sampler::row_elem(out, dxm) = (T)cn[0];
+            *sampler::row_elem(out + pitch, dym) = (T)cn[1];
+            *sampler::row_elem(out + 2 * pitch, x) = (T)cn[2];
+            *sampler::row_elem(out + 3 * pitch, dyp) = (T)cn[3];
+            *sampler::row_elem(out + 4 * pitch, dxp) = (T)cn[4];
+        } else {
+            const uint32_t xm = (x == 0) ? L - 1 : x - 1;
+            const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
+            *sampler::row_elem(out, xm) = (T)cn[0];
+            *sampler::row_elem(out + (uint64_t)(Q - 1) * pitch, xp) = (T)cn[Q - 1];
+            if constexpr (Q == 3)
+                *sampler::row_elem(out + pitch, x) = (T)cn[1];
+        }
     }
     if (ovf > kMax)
         atomicOr(a.err, 1u);
@@ -191,6 +223,10 @@ hipError_t launch_spec(int q, int count_bytes, const ServeArgs &a, hipStream_t s
             return launch_qt<3, uint16_t, NR, EX>(a, stream);
         if (q == 3 && count_bytes == 4)
             return launch_qt<3, uint32_t, NR, EX>(a, stream);
+        if (q == 5 && count_bytes == 2)
+            return launch_qt<5, uint16_t, NR, EX>(a, stream);
+        if (q == 5 && count_bytes == 4)
+            return launch_qt<5, uint32_t, NR, EX>(a, stream);
     }
     return hipErrorInvalidValue;
 }

@@ -73,9 +73,15 @@ Payload *payload_of(Req &r)
     return static_cast<Payload *>(r.payload.get());
 }
 
+// Nodes of a request: L in 1D, Lx Ly for D2Q5 (node x + Lx y).
+uint64_t nodes_of(const ilg_config &c)
+{
+    return c.length * (c.q == 5 ? (uint64_t)c.height : 1u);
+}
+
 uint64_t state_bytes(const ilg_config &c)
 {
-    return align256(2ull * c.q * pitch_of(c.length) * c.count_bytes);
+    return align256(2ull * c.q * pitch_of(nodes_of(c)) * c.count_bytes);
 }
 
 class DeviceExecutor : public ilg::serve::Executor {
@@ -85,7 +91,7 @@ public:
     uint32_t *err = nullptr;
     // Launch groups: (q, count type, Philox rounds, exchange form); a group's
     // stream is created when the group first has work.
-    static constexpr int kGroups = 16;
+    static constexpr int kGroups = 24;
     hipStream_t streams[kGroups] = {};
     ilg::ServeSlot *d_slots[kGroups] = {};
     uint32_t *d_tiles[kGroups] = {};  // slot of each tile
@@ -95,7 +101,7 @@ public:
 
     static int group(uint32_t q, uint32_t cb, const ilg::Fixed &fx)
     {
-        return (q == 3 ? 8 : 0) + (cb == 4 ? 4 : 0) + (fx.rounds == 7 ? 2 : 0) +
+        return (q == 5 ? 16 : q == 3 ? 8 : 0) + (cb == 4 ? 4 : 0) + (fx.rounds == 7 ? 2 : 0) +
                (fx.exchange ? 1 : 0);
     }
 
@@ -109,7 +115,7 @@ public:
     {
         Payload *p = payload_of(r);
         const ilg_config &c = p->cfg;
-        const size_t cb = c.count_bytes, pitch = pitch_of(c.length);
+        const size_t cb = c.count_bytes, n = nodes_of(c), pitch = pitch_of(n);
         unsigned char *base = static_cast<unsigned char *>(arena) + r.mem_off;
         if (p->device_init) {
             // Poisson sine state drawn in place; a count above the type sets
@@ -118,16 +124,23 @@ public:
             ilg::InitArgs a;
             a.out = base;
             a.pitch = pitch;
-            a.length = (uint32_t)c.length;
+            a.length = (uint32_t)n;
             a.width = (uint32_t)c.length;
             a.q = c.q;
             a.realization = c.realization;
             a.key0 = (uint32_t)(p->init_seed & 0xFFFFFFFFu);
             a.key1 = (uint32_t)(p->init_seed >> 32);
-            a.w[0] = c.q == 2 ? 0.5 : theta * 0.5;
-            a.w[1] = c.q == 2 ? 0.5 : 1.0 - theta;
-            a.w[2] = c.q == 2 ? 0.0 : theta * 0.5;
-            a.w[3] = a.w[4] = 0.0;
+            for (int i = 0; i < 5; ++i)
+                a.w[i] = 0.0;
+            if (c.q == 2) {
+                a.w[0] = a.w[1] = 0.5;
+            } else if (c.q == 3) {
+                a.w[0] = a.w[2] = theta * 0.5;
+                a.w[1] = 1.0 - theta;
+            } else {
+                a.w[0] = a.w[1] = a.w[3] = a.w[4] = theta * 0.5;
+                a.w[2] = 1.0 - 2.0 * theta;
+            }
             a.nave = p->nave;
             a.amp = p->amp;
             a.err = err;
@@ -135,11 +148,11 @@ public:
             if (e != hipSuccess)
                 return shfail(e, "init launch");
         } else {
-            SHIP(hipMemcpy2DAsync(base, pitch * cb, p->host.data(), c.length * cb, c.length * cb,
-                                  c.q, hipMemcpyHostToDevice, io));
+            SHIP(hipMemcpy2DAsync(base, pitch * cb, p->host.data(), n * cb, n * cb, c.q,
+                                  hipMemcpyHostToDevice, io));
         }
-        // table set: removal table (+ rest table for q = 3) then their guides
-        const int nt = c.q == 3 ? 2 : 1;
+        // table set: removal table (+ rest table for q = 3, 5) then their guides
+        const int nt = c.q == 2 ? 1 : 2;
         std::vector<unsigned char> set(ilg::serve_table_set_bytes((int)c.q), 0);
         const uint64_t ps[2] = {p->fx.p, p->fx.p_rest};
         std::vector<uint32_t> packed(ilg::kTableEntries);
@@ -208,8 +221,9 @@ public:
             std::memset(&s, 0, sizeof(s));
             s.state_off = r.mem_off / c.count_bytes;
             s.table_off = r.mem_off + state_bytes(c);
-            s.length = (uint32_t)c.length;
-            s.pitch = (uint32_t)pitch_of(c.length);
+            s.length = (uint32_t)nodes_of(c);
+            s.width = (uint32_t)c.length;
+            s.pitch = (uint32_t)pitch_of(nodes_of(c));
             s.t0 = (uint32_t)p->t;
             s.steps = steps[i];
             s.realization = c.realization;
@@ -219,7 +233,7 @@ public:
             s.p_zero = p->fx.p == 0 ? 1u : 0u;
             s.cur0 = p->cur;
             const uint32_t idx = (uint32_t)slots[g].size();
-            const uint32_t nt = (uint32_t)((c.length + ilg::kServeTile - 1) / ilg::kServeTile);
+            const uint32_t nt = (uint32_t)((nodes_of(c) + ilg::kServeTile - 1) / ilg::kServeTile);
             s.tile_begin = (uint32_t)tiles[g].size();
             s.tile_end = s.tile_begin + nt;
             slots[g].push_back(s);
@@ -245,7 +259,8 @@ public:
             a.ntiles = (uint32_t)tiles[g].size();
             a.shared = shared;
             a.err = err;
-            const int q = (g & 8) ? 3 : 2, cb = (g & 4) ? 4 : 2, rounds = (g & 2) ? 7 : 10;
+            const int q = g >= 16 ? 5 : (g & 8) ? 3 : 2, cb = (g & 4) ? 4 : 2;
+            const int rounds = (g & 2) ? 7 : 10;
             const bool exchange = (g & 1) != 0;
             for (uint32_t j = 0; j < maxsteps[g]; ++j) {
                 a.j = j;
@@ -280,12 +295,12 @@ public:
     {
         Payload *p = payload_of(r);
         const ilg_config &c = p->cfg;
-        const size_t cb = c.count_bytes, pitch = pitch_of(c.length);
+        const size_t cb = c.count_bytes, n = nodes_of(c), pitch = pitch_of(n);
         const unsigned char *src = static_cast<const unsigned char *>(arena) + r.mem_off +
                                    (size_t)p->cur * c.q * pitch * cb;
         // a request drawn on the device has no host copy of its state yet
-        p->host.resize((size_t)c.q * c.length * cb);
-        SHIP(hipMemcpy2DAsync(p->host.data(), c.length * cb, src, pitch * cb, c.length * cb, c.q,
+        p->host.resize((size_t)c.q * n * cb);
+        SHIP(hipMemcpy2DAsync(p->host.data(), n * cb, src, pitch * cb, n * cb, c.q,
                               hipMemcpyDeviceToHost, io));
         SHIP(hipStreamSynchronize(io));
         return ILG_OK;
@@ -391,8 +406,6 @@ int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_hos
     int rc = ilg::check_config(cfg, &fx);
     if (rc != ILG_OK)
         return rc;
-    if (cfg->q == 5)
-        return sfail(ILG_E_INVALID, "D2Q5 lattices run in the plain form only");
     if (nsteps == 0)
         return sfail(ILG_E_INVALID, "nsteps must be positive");
     if (cfg->t0 + nsteps > (uint64_t(1) << 32))
@@ -400,12 +413,12 @@ int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_hos
     auto p = std::make_shared<Payload>();
     p->cfg = *cfg;
     p->fx = fx;
-    const size_t bytes = (size_t)cfg->q * cfg->length * cfg->count_bytes;
+    const size_t bytes = (size_t)cfg->q * nodes_of(*cfg) * cfg->count_bytes;
     p->host.assign(static_cast<const unsigned char *>(init_host),
                    static_cast<const unsigned char *>(init_host) + bytes);
     std::unique_ptr<Req> r(new Req);
     r->q = cfg->q;
-    r->nodes = cfg->length;
+    r->nodes = nodes_of(*cfg);
     r->total = nsteps;
     r->payload = p;
     if (!s->sched->submit(std::move(r), s->ex, id, steady_now()))
@@ -425,8 +438,6 @@ int ilg_server_submit_poisson_sine(ilg_server *s, const ilg_config *cfg, double 
     int rc = ilg::check_config(cfg, &fx);
     if (rc != ILG_OK)
         return rc;
-    if (cfg->q == 5)
-        return sfail(ILG_E_INVALID, "D2Q5 lattices run in the plain form only");
     if (nsteps == 0)
         return sfail(ILG_E_INVALID, "nsteps must be positive");
     if (cfg->t0 + nsteps > (uint64_t(1) << 32))
@@ -440,7 +451,7 @@ int ilg_server_submit_poisson_sine(ilg_server *s, const ilg_config *cfg, double 
     p->init_seed = init_seed;
     std::unique_ptr<Req> r(new Req);
     r->q = cfg->q;
-    r->nodes = cfg->length;
+    r->nodes = nodes_of(*cfg);
     r->total = nsteps;
     r->payload = p;
     if (!s->sched->submit(std::move(r), s->ex, id, steady_now()))

@@ -43,7 +43,8 @@ def _requests(n, seed):
 def _alone(ilg, m, init, nsteps):
     lat = ilg.Lattice(m["q"], m["length"], m["count_bytes"], m["omega"], m["seed"], init,
                       realization=m.get("realization", 0), t0=m.get("t0", 0),
-                      rounds=m.get("rounds", 10), exchange=m.get("exchange", False))
+                      rounds=m.get("rounds", 10), exchange=m.get("exchange", False),
+                      height=m.get("height", 0))
     lat.step(nsteps)
     out = lat.state()
     lat.close()
@@ -111,6 +112,54 @@ def test_draw_specifications_in_one_server(ilg, oracle_lib):
             ref, _, _ = oracle_lib.run(p, init, ns, seed=m["seed"], realization=m["realization"],
                                        t0=m["t0"])
             np.testing.assert_array_equal(got, ref, err_msg=f"request {k} vs oracle")
+    srv.close()
+
+
+def test_d2q5_requests_with_1d_ones(ilg, oracle_lib):
+    """D2Q5 requests (shapes from one node to rows wider than a tile, both
+    count types, 10- and 7-round draws, a device-drawn initial state) served
+    beside D1Q2/D1Q3 requests: each equals the configuration run alone and,
+    sampled, the oracle's 2D run."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(21)
+    shapes = [(1, 1), (33, 7), (64, 64), (1500, 3), (5, 300), (129, 17)]
+    reqs = []
+    for i, (lx, ly) in enumerate(shapes):
+        cb = 2 if i % 2 == 0 else 4
+        m = dict(q=5, length=lx, height=ly, count_bytes=cb, omega=[1.8, 0.7, 1.3][i % 3],
+                 seed=900 + i, realization=i, t0=int(rng.integers(0, 30)),
+                 rounds=7 if i == 4 else 10)
+        dt = np.uint16 if cb == 2 else np.uint32
+        init = rng.poisson([[[25.0]], [[25.0]], [[50.0]], [[25.0]], [[25.0]]],
+                           size=(5, ly, lx)).astype(dt)
+        reqs.append((m, init, int(rng.integers(5, 90))))
+    reqs += _requests(12, seed=22)
+    srv = ilg.Server(64 << 20, quantum_steps=23)
+    ids = [srv.submit(m, init, ns) for m, init, ns in reqs]
+    drawn = dict(q=5, length=96, height=40, count_bytes=2, omega=1.5, seed=77, realization=3,
+                 t0=0)
+    did = srv.submit_poisson_sine(drawn, 80.0, 40.0, 9, 33)
+    polls = 0
+    while True:
+        st = srv.poll()
+        polls += 1
+        if st["active"] == 0 and st["queued"] == 0:
+            break
+        assert polls < 1000
+    for k, (m, init, ns) in enumerate(reqs):
+        got = srv.result(ids[k])
+        np.testing.assert_array_equal(got, _alone(ilg, m, init, ns), err_msg=f"request {k}")
+        if m["q"] == 5 and k % 2 == 0:
+            p = oracle_lib.Params(5, m["omega"], rounds=m["rounds"])
+            ref, _, ov = oracle_lib.run2d(p, init, ns, seed=m["seed"],
+                                          realization=m["realization"], t0=m["t0"])
+            assert not ov
+            np.testing.assert_array_equal(got, ref, err_msg=f"request {k} vs oracle")
+    got = srv.result(did)
+    init, ov = O.init_poisson_sine(5, 2, 96, 80.0, 40.0, 9, realization=3, height=40)
+    assert not ov
+    want, _, _ = oracle_lib.run2d(oracle_lib.Params(5, 1.5), init, 33, seed=77, realization=3)
+    np.testing.assert_array_equal(got, want)
     srv.close()
 
 
