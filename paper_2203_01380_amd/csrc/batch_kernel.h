@@ -452,23 +452,11 @@ void batch_kernel(BatchArgs a)
                 }
                 ovf |= sampler::or_all<Q, W>(cn);
                 if constexpr (Q == 5) {
-                    // D2Q5 on the node index x + Lx y, periodic in both
-                    // directions: -x, -y, rest, +y, +x.  The row and column
-                    // come from the pass's first node (one scalar division
-                    // per pass over the member).
-                    const uint32_t width = m.width;
-                    const uint32_t x0 = __builtin_amdgcn_readfirstlane(x - threadIdx.x);
-                    const uint32_t row0 = x0 / width;
-                    uint32_t cx = x0 - row0 * width + threadIdx.x, cy = row0;
-                    if (cx >= width) {
-                        const uint32_t k = cx / width;
-                        cx -= k * width;
-                        cy += k;
-                    }
-                    const uint32_t dxm = cx == 0 ? x + width - 1 : x - 1;
-                    const uint32_t dxp = cx + 1 == width ? x + 1 - width : x + 1;
-                    const uint32_t dym = cy == 0 ? x + (L - width) : x - width;
-                    const uint32_t dyp = x + width >= L ? x + width - L : x + width;
+                    // D2Q5 on the node index x + Lx y: -x, -y, rest, +y, +x
+                    uint32_t dxm, dym, dyp, dxp;
+                    sampler::d2q5_neighbours<BLOCK>(
+                        x, __builtin_amdgcn_readfirstlane(x - threadIdx.x), m.width, L, dxm, dym,
+                        dyp, dxp);
                     *sampler::row_elem(out, dxm) = (T)cn[0];
                     *sampler::row_elem(out + pitch, dym) = (T)cn[1];
                     *sampler::row_elem(out + 2 * pitch, x) = (T)cn[2];

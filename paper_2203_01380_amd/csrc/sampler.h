@@ -606,5 +606,36 @@ __device__ __forceinline__ void node_exchange(const W (&av)[2], W (&cn)[2], uint
     cn[1] = av[1] - Y + X;
 }
 
+// Destinations of a D2Q5 node's movers on the node index x + Lx y, periodic
+// in both directions: -x, -y, +y, +x.  x0 (uniform) is the first node of the
+// pass, x = x0 + lane index < x0 + BLOCK; the pass's row and column come from
+// one scalar division, each lane's from a float quotient with one exact
+// correction (its dividend is below Lx + BLOCK, and a quotient of such small
+// integers is off by at most one below an exact multiple).
+template <int BLOCK>
+__device__ __forceinline__ void d2q5_neighbours(uint32_t x, uint32_t x0, uint32_t width,
+                                                uint32_t nodes, uint32_t &dxm, uint32_t &dym,
+                                                uint32_t &dyp, uint32_t &dxp)
+{
+    const uint32_t row0 = x0 / width;
+    uint32_t cx = x0 - row0 * width + (x - x0), cy = row0;
+    if (cx >= width) {
+        uint32_t k;
+        if (width >= (uint32_t)BLOCK) {
+            k = 1u;
+        } else {
+            k = (uint32_t)((float)cx * (1.0f / (float)width));
+            if (cx - k * width >= width)
+                ++k;
+        }
+        cx -= k * width;
+        cy += k;
+    }
+    dxm = cx == 0 ? x + width - 1 : x - 1;
+    dxp = cx + 1 == width ? x + 1 - width : x + 1;
+    dym = cy == 0 ? x + (nodes - width) : x - width;
+    dyp = x + width >= nodes ? x + width - nodes : x + width;
+}
+
 }  // namespace sampler
 }  // namespace ilg

@@ -126,21 +126,9 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         }
         ovf |= sampler::or_all<Q, W>(cn);
         if constexpr (Q == 5) {
-            // D2Q5 streaming on the node index x + Lx y (periodic in both):
-            // -x, -y, rest, +y, +x.  The column and row of the node come from
-            // the tile's first node (one scalar division per tile).
-            const uint32_t tile0 = tile * kTile;
-            const uint32_t row0 = tile0 / a.width;
-            uint32_t cx = tile0 - row0 * a.width + threadIdx.x, cy = row0;
-            if (cx >= a.width) {
-                const uint32_t k = cx / a.width;
-                cx -= k * a.width;
-                cy += k;
-            }
-            const uint32_t dxm = cx == 0 ? x + a.width - 1 : x - 1;
-            const uint32_t dxp = cx + 1 == a.width ? x + 1 - a.width : x + 1;
-            const uint32_t dym = cy == 0 ? x + (L - a.width) : x - a.width;
-            const uint32_t dyp = cy + 1 == a.height ? x - (L - a.width) : x + a.width;
+            // D2Q5 streaming on the node index x + Lx y: -x, -y, rest, +y, +x
+            uint32_t dxm, dym, dyp, dxp;
+            sampler::d2q5_neighbours<BLOCK>(x, tile * kTile, a.width, L, dxm, dym, dyp, dxp);
             *row_elem(out_row[0], dxm) = (T)cn[0];
             *row_elem(out_row[1], dym) = (T)cn[1];
             *row_elem(out_row[2], x) = (T)cn[2];

@@ -2,8 +2,8 @@
 two-dimensional five-velocity set) against the oracle: every compared step
 bit-exact over lattice shapes whose 1024-node tiles wrap rows, both count
 types, special rates, multi-chunk counts, per-step hashes, moments, the
-device-drawn initial state, a 2048 x 2048 lattice, and the rejection of
-D2Q5 by the batched and serving forms."""
+device-drawn initial state, a 2048 x 2048 lattice, and the layout checks of
+the batched and serving forms."""
 import sys
 
 import numpy as np
@@ -124,15 +124,26 @@ def test_full_size_2048(ilg):
     lat.close()
 
 
-def test_batch_and_server_reject_d2q5(ilg):
+def test_batch_and_server_check_d2q5_layouts(ilg):
+    """The batched and serving forms take D2Q5 members as [5][height][length]
+    (parity in test_gpu_batch_d2q5.py and test_gpu_serve.py): a flattened
+    state is refused, and so are the 1D diagnostics for a D2Q5 batch."""
     m = dict(q=5, length=8, count_bytes=2, omega=1.5, seed=1, height=4)
-    init = np.zeros((5, 8 * 4), dtype=np.uint16)
-    with pytest.raises((ilg.IlgError, ValueError)):
+    init = np.zeros((5, 4, 8), dtype=np.uint16)
+    with pytest.raises(ValueError):
         ilg.Batch([m], [init.reshape(5, 32)])
-    srv = ilg.Server(1 << 20, 10)
     with pytest.raises(ilg.IlgError):
-        srv.submit_poisson_sine(m, 10.0, 0.0, 1, 5)
-    srv.close()
+        ilg.Batch([m], [init], sk_every=2, nk=2)
+    srv = ilg.Server(1 << 20, 10)
+    try:
+        with pytest.raises(ValueError):
+            srv.submit(m, init.reshape(5, 32), 5)
+        rid = srv.submit(m, init, 5)
+        while srv.poll()["active"]:
+            pass
+        np.testing.assert_array_equal(srv.result(rid), init)   # an empty lattice stays empty
+    finally:
+        srv.close()
 
 
 def test_rest_count_chunk_layouts(ilg):
