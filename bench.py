@@ -465,7 +465,7 @@ def main():
         summarize_counters(*args.summarize_counters, args.length)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(ensembles would shard by realization, one lattice along x).", file=sys.stderr)
         sys.exit(2)
     forms = set(args.forms.split(","))

@@ -546,10 +546,10 @@ void oracle_binomial_samples(uint64_t n, const uint32_t *table, uint64_t seed, u
  * n_i(x) is a Poisson variate with expectation w_i times the density profile
  * N [1 + sin(2 pi x / L)]; here with a general amplitude A,
  *   mean_i(x) = w_i (N + A sin(2 pi x / L)).
- * Reading (a specification of this build, "init v1"): so that two IEEE-754
- * machines draw the same counts, every floating-point step below is one
- * correctly rounded double operation (no fused multiply-add, no library
- * transcendental):
+ * Reading (a specification fixed here and in the library, "init v1"): so
+ * that two IEEE-754 machines draw the same counts, every floating-point step
+ * below is one correctly rounded double operation (no fused multiply-add, no
+ * library transcendental):
  *   sin(2 pi x / L): 8x = k L + rem with integers (octant k); for even k
  *     t = rem / L, for odd k t = (L - rem) / L (the distance to the octant's
  *     end, again from integers); a = t * (pi/4), a2 = a * a,
