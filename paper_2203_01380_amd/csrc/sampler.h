@@ -527,19 +527,31 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
     const uint64_t three_mask = __builtin_amdgcn_ballot_w64(three);
     bool done = false;
     if (ok_mask == lanes) {
+        // Every count is at most three chunks here, so every intermediate and
+        // result fits 32 bits: the straight-line paths run in 32-bit
+        // arithmetic also for uint32 lattices (whose generic path is 64-bit).
+        uint32_t a32[Q], c32[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            a32[i] = (uint32_t)av[i];
         if constexpr (Q == 5)
-            done = node_fast5<W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
-                                         g_rest, p_zero);
+            done = node_fast5<uint32_t, NB, GB>(a32, c32, d, tab_p, g_p, tab_half, g_half,
+                                                tab_rest, g_rest, p_zero);
         else if (two_mask == 0ull)
-            done = node_fast<Q, 1, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
-                                              g_rest, p_zero);
+            done = node_fast<Q, 1, uint32_t, NB, GB>(a32, c32, d, tab_p, g_p, tab_half, g_half,
+                                                     tab_rest, g_rest, p_zero);
         else if constexpr (Q == 3) {
             if (two_mask == lanes && three_mask == 0ull)
-                done = node_fast<Q, 2, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half,
-                                                  tab_rest, g_rest, p_zero);
+                done = node_fast<Q, 2, uint32_t, NB, GB>(a32, c32, d, tab_p, g_p, tab_half,
+                                                         g_half, tab_rest, g_rest, p_zero);
             else
-                done = node_var3<W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest,
-                                            g_rest, p_zero);
+                done = node_var3<uint32_t, NB, GB>(a32, c32, d, tab_p, g_p, tab_half, g_half,
+                                                   tab_rest, g_rest, p_zero);
+        }
+        if (done) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                cn[i] = (W)c32[i];
         }
     }
     if (!done) {
