@@ -494,6 +494,48 @@ template <> struct Wide<uint32_t> { using type = uint64_t; };
 // Full node update: av holds the (already flipped) occupations; cn receives
 // the post-collision counts.  Table pointers are LDS addresses.  NR: Philox
 // rounds of the draws (10 or 7).
+// The generic path: every binomial chunk by chunk in the draw order, in
+// the arithmetic type WW (wide enough for every count, sum and result).
+template <int Q, typename WW, int NB, int GB, int NR>
+__device__ __forceinline__ void node_generic(const WW (&av)[Q], WW (&cn)[Q], Draws<NB, NR> &d,
+                                             const uint32_t *tab_p, const uint8_t *g_p,
+                                             const uint32_t *tab_half, const uint8_t *g_half,
+                                             const uint32_t *tab_rest, const uint8_t *g_rest,
+                                             bool p_zero)
+{
+    using W = WW;
+    W kv[Q], mv[Q];
+    uint32_t j = 0;
+    W M = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        kv[i] = binomial<W, NB, GB>(av[i], j, tab_p, g_p, p_zero, d);
+        M += kv[i];
+    }
+    if constexpr (Q == 2) {
+        mv[0] = binomial<W, NB, GB>(M, j, tab_half, g_half, false, d);
+        mv[1] = M - mv[0];
+    } else if constexpr (Q == 5) {
+        // rest, then the x/y pair split, then -x within x, -y within y
+        mv[2] = binomial<W, NB, GB>(M, j, tab_rest, g_rest, false, d);
+        const W R = M - mv[2];
+        const W mx = binomial<W, NB, GB>(R, j, tab_half, g_half, false, d);
+        const W my = R - mx;
+        mv[0] = binomial<W, NB, GB>(mx, j, tab_half, g_half, false, d);
+        mv[4] = mx - mv[0];
+        mv[1] = binomial<W, NB, GB>(my, j, tab_half, g_half, false, d);
+        mv[3] = my - mv[1];
+    } else {
+        mv[1] = binomial<W, NB, GB>(M, j, tab_rest, g_rest, false, d);
+        const W R = M - mv[1];
+        mv[0] = binomial<W, NB, GB>(R, j, tab_half, g_half, false, d);
+        mv[2] = R - mv[0];
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        cn[i] = av[i] - kv[i] + mv[i];
+}
+
 template <int Q, typename W, int NB, int GB, int NR = 10>
 __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32_t x, uint32_t t,
                                             uint32_t r, uint32_t key0, uint32_t key1,
@@ -502,7 +544,6 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
                                             const uint32_t *tab_rest, const uint8_t *g_rest,
                                             bool p_zero)
 {
-    W kv[Q], mv[Q];
     Draws<NB, NR> d;
     d.init(x, t, r, key0, key1);
     // Common draw layout, decided once per wave for this node slot.  The
@@ -555,35 +596,28 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
         }
     }
     if (!done) {
-        uint32_t j = 0;
-        W M = 0;
+        if constexpr (sizeof(W) > sizeof(uint32_t)) {
+            // uint32 lattices: below 2^29 per count, every sum and result of
+            // the node fits 32 bits (at most 5 x 2^29 + 2^29 < 2^32).
+            bool small = true;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            kv[i] = binomial<W, NB, GB>(av[i], j, tab_p, g_p, p_zero, d);
-            M += kv[i];
-        }
-        if constexpr (Q == 2) {
-            mv[0] = binomial<W, NB, GB>(M, j, tab_half, g_half, false, d);
-            mv[1] = M - mv[0];
-        } else if constexpr (Q == 5) {
-            // rest, then the x/y pair split, then -x within x, -y within y
-            mv[2] = binomial<W, NB, GB>(M, j, tab_rest, g_rest, false, d);
-            const W R = M - mv[2];
-            const W mx = binomial<W, NB, GB>(R, j, tab_half, g_half, false, d);
-            const W my = R - mx;
-            mv[0] = binomial<W, NB, GB>(mx, j, tab_half, g_half, false, d);
-            mv[4] = mx - mv[0];
-            mv[1] = binomial<W, NB, GB>(my, j, tab_half, g_half, false, d);
-            mv[3] = my - mv[1];
-        } else {
-            mv[1] = binomial<W, NB, GB>(M, j, tab_rest, g_rest, false, d);
-            const W R = M - mv[1];
-            mv[0] = binomial<W, NB, GB>(R, j, tab_half, g_half, false, d);
-            mv[2] = R - mv[0];
-        }
+            for (int i = 0; i < Q; ++i)
+                small &= av[i] < ((W)1 << 29);
+            if (__builtin_amdgcn_ballot_w64(small) == lanes) {
+                uint32_t a32[Q], c32[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            cn[i] = av[i] - kv[i] + mv[i];
+                for (int i = 0; i < Q; ++i)
+                    a32[i] = (uint32_t)av[i];
+                node_generic<Q, uint32_t, NB, GB>(a32, c32, d, tab_p, g_p, tab_half, g_half,
+                                                  tab_rest, g_rest, p_zero);
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    cn[i] = (W)c32[i];
+                return;
+            }
+        }
+        node_generic<Q, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest, g_rest,
+                                   p_zero);
     }
 }
 
