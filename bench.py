@@ -353,6 +353,47 @@ def bench_batched_decay(ilg, W, stream, steps: int):
             "node_updates_per_s": nu / sec, "seconds": sec, "node_updates": nu, "shape": shape}
 
 
+def bench_serving_saturated(ilg, W, stream, steps: int = 1000, nreq: int = 64):
+    """Serving capacity: nreq requests of 2^20 nodes submitted at once (the
+    first nreq requests of the stream's rates and seeds), all D1Q2, all D1Q3,
+    then mixed, against plain 2^22-node lattices stepped at the first 16 of
+    the same rates (the comparison the server's per-tile overhead is read
+    from)."""
+    import torch
+    base = W.request_stream(rate_per_s=200, duration_s=2.0)[:nreq]
+    pool = W.RequestInitPool()
+    out = {"workload": f"{nreq} requests of 2^20 nodes, uint16, Poisson(40), omega ~ U[1, 1.95], "
+                       f"{steps} steps each, submitted at once; plain: 16 lattices of 2^22 at "
+                       f"the same rates"}
+    for label, qfun in (("d1q2", lambda rq: 2), ("d1q3", lambda rq: 3),
+                        ("mixed", lambda rq: rq.spec.q)):
+        srv = ilg.Server(16 << 30, 100)
+        for i, rq in enumerate(base):
+            q = qfun(rq)
+            m = dict(q=q, length=1 << 20, count_bytes=2, omega=rq.spec.omega, seed=rq.spec.seed,
+                     realization=rq.spec.realization)
+            srv.submit(m, pool.init(i, q, m["length"]), steps)
+        t0 = time.perf_counter()
+        while True:
+            st = srv.poll()
+            if st["active"] == 0 and st["queued"] == 0:
+                break
+        sec = time.perf_counter() - t0
+        srv.close()
+        out[label] = {"node_updates_per_s": len(base) * (1 << 20) * steps / sec, "seconds": sec}
+    for q in (2, 3):
+        tot, work, L = 0.0, 0, 1 << 22
+        for i, rq in enumerate(base[:16]):
+            lat = ilg.Lattice(q, L, 2, rq.spec.omega, rq.spec.seed,
+                              W.init_poisson_iid(q, L, 40.0, 2, init_seed=5 + i))
+            lat.step(20)
+            tot += timed(stream, lambda: lat.step(300))
+            work += L * 300
+            lat.close()
+        out[f"plain_d1q{q}_same_rates"] = {"node_updates_per_s": work / tot}
+    return out
+
+
 def bench_serving(ilg, W, rate: float, duration: float, budget: int, quantum: int,
                   step_nodes: int = 0):
     """Replay a Poisson request stream in real time through the server: each
@@ -443,9 +484,10 @@ def main():
     ap.add_argument("--length", type=int, default=1 << 24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,mallfree,philox7,exchange,d2q5,batched,batched_specs,batched_d2q5,decay,serving",
+    ap.add_argument("--forms", default="plain,mallfree,philox7,exchange,d2q5,batched,batched_specs,batched_d2q5,decay,serving_saturated,serving",
                     help="comma list of plain (always), mallfree, philox7, exchange, d2q5, "
-                         "batched, batched_specs, batched_d2q5, decay, serving")
+                         "batched, batched_specs, batched_d2q5, decay, serving_saturated, "
+                         "serving")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-step-nodes", type=int, default=0,
                     help="server policy: at most this many nodes advanced per quantum, least "
@@ -549,6 +591,9 @@ def main():
     if "decay" in forms:
         say("batched decay sweep")
         out["batched_decay"] = bench_batched_decay(ilg, W, stream, args.decay_steps)
+    if "serving_saturated" in forms:
+        say("serving capacity: 64 requests of 2^20 nodes at once")
+        out["serving_saturated"] = bench_serving_saturated(ilg, W, stream)
     if "serving" in forms:
         out["serving"] = []
         for frac in (1.0, 0.5, 0.25):
