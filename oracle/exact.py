@@ -471,8 +471,14 @@ def structure_factor(N: np.ndarray, kmax: int) -> np.ndarray:
 
 
 def moments_raw(state: np.ndarray, q: int):
-    """Per-node exact integer moments: rho = sum n_i, J = sum v_i n_i,
-    E = sum v_i^2 n_i."""
-    s = state.astype(np.int64)
+    """Per-node exact integer moments (the density and current of the named
+    moments, Eq. transform, before their Hermite normalisation): rho =
+    sum_i n_i, J = sum_i v_i n_i, E = sum_i |v_i|^2 n_i.  D2Q5 ([5][nodes] or
+    [5][Ly][Lx]): J is the x component sum_i v_ix n_i."""
+    s = state.astype(np.int64).reshape(q, -1)
     v = velocities(q)
-    return s.sum(axis=0), (v[:, None] * s).sum(axis=0), ((v ** 2)[:, None] * s).sum(axis=0)
+    vx = v[:, 0] if v.ndim == 2 else v
+    v2 = (v * v).sum(axis=1) if v.ndim == 2 else v * v
+    shape = state.shape[1:]
+    return (s.sum(axis=0).reshape(shape), (vx[:, None] * s).sum(axis=0).reshape(shape),
+            (v2[:, None] * s).sum(axis=0).reshape(shape))

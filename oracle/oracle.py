@@ -17,7 +17,9 @@ from . import exact
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ilg_oracle.c")
 _BUILD_DIR = os.path.join(_HERE, "_build")
-_LIB_PATH = os.path.join(_BUILD_DIR, "libilg_oracle.so")
+# ILG_ORACLE_LIB names another build of ilg_oracle.c to load instead (the
+# mutation tests load scratch copies with planted mistakes this way).
+_LIB_PATH = os.environ.get("ILG_ORACLE_LIB") or os.path.join(_BUILD_DIR, "libilg_oracle.so")
 _lib = None
 
 

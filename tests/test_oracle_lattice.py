@@ -104,3 +104,101 @@ def test_config_one_initial_state():
     assert int(rho.sum()) == 5120
     assert int((rho % 2).sum()) == 112
     assert np.all(st[1].astype(np.int64) - st[0] == rho % 2)
+
+
+# ---------------------------------------------------------------- state hash
+# The hash mixes each term with the SplitMix64 finaliser (Steele, Lea & Flood,
+# OOPSLA 2014; Vigna's splitmix64.c): splitmix64(z) is the first output of
+# the SplitMix64 generator seeded with z.  Published first outputs pin the
+# constants and shifts; the term layout is checked on hand-made states.
+_SPLITMIX_FIRST_OUTPUT = {
+    0: 0xE220A8397B1DCDAF,                   # seed 0 (splitmix64.c reference run)
+    1234567: 6457827717110365317,            # seed 1234567 (widely reproduced test vector)
+}
+_M64 = (1 << 64) - 1
+
+
+def _splitmix64_generator(seed, n):
+    """The published generator written out: state += gamma, then the
+    finaliser; n outputs."""
+    out, s = [], seed
+    for _ in range(n):
+        s = (s + 0x9E3779B97F4A7C15) & _M64
+        z = s
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def test_splitmix64_generator_published_outputs():
+    """The Python generator reproduces the published sequences, so it can
+    serve to evaluate the hash definition on small states below."""
+    assert _splitmix64_generator(0, 4) == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                           0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    assert _splitmix64_generator(1234567, 5) == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423,
+        4593380528125082431, 16408922859458223821]
+
+
+@pytest.mark.parametrize("seed", sorted(_SPLITMIX_FIRST_OUTPUT))
+def test_hash_single_term_is_splitmix64(oracle_lib, seed):
+    """One velocity, one node, count n: the hash is splitmix64((0 << 32) ^ n),
+    the first SplitMix64 output for seed n."""
+    st = np.array([[seed]], dtype=np.uint32)
+    assert oracle_lib.state_hash(st) == _SPLITMIX_FIRST_OUTPUT[seed]
+
+
+def _hash_by_definition(state):
+    """sum_{x,i} splitmix64(((x q + i) << 32) ^ n_i(x)) mod 2^64, term by term."""
+    q = state.shape[0]
+    flat = state.reshape(q, -1)
+    h = 0
+    for x in range(flat.shape[1]):
+        for i in range(q):
+            h = (h + _splitmix64_generator(((x * q + i) << 32) ^ int(flat[i, x]), 1)[0]) & _M64
+    return h
+
+
+@pytest.mark.parametrize("q,cb,L", [(2, 4, 5), (3, 2, 7), (3, 4, 3), (5, 2, 4)])
+def test_hash_matches_definition(oracle_lib, q, cb, L):
+    """Small hand-made states (including the largest counts of the type and
+    zeros): the oracle's hash equals the definition evaluated term by term,
+    so the (x q + i) << 32 position word, the xor with the count and the sum
+    modulo 2^64 are pinned."""
+    dt = np.uint16 if cb == 2 else np.uint32
+    top = np.iinfo(dt).max
+    st = (np.arange(q * L, dtype=np.int64).reshape(q, L) * 7919 % (top + 1)).astype(dt)
+    st[0, 0] = top
+    st[q - 1, L - 1] = 0
+    assert oracle_lib.state_hash(st) == _hash_by_definition(st)
+    # D2Q5 states given as [5][Ly][Lx] hash by node index x + Lx y
+    if q == 5:
+        st2 = st.reshape(5, 2, L // 2)
+        assert oracle_lib.state_hash(np.ascontiguousarray(st2)) == _hash_by_definition(st)
+
+
+# ---------------------------------------------------------------- raw moments
+def test_moments_raw_hand_computed():
+    """rho, J = sum v_i n_i, E = sum |v_i|^2 n_i for hand-made states, worked
+    out by hand from the velocity sets (D1Q2 (-1, +1); D1Q3 (-1, 0, +1); D2Q5
+    (-1,0), (0,-1), (0,0), (0,+1), (+1,0) with J its x component)."""
+    # D1Q2: nodes (n_-, n_+) = (3, 1), (0, 4), (5, 2)
+    rho, j, e = exact.moments_raw(np.array([[3, 0, 5], [1, 4, 2]], dtype=np.uint16), 2)
+    assert rho.tolist() == [4, 4, 7]
+    assert j.tolist() == [-2, 4, -3]
+    assert e.tolist() == [4, 4, 7]
+    # D1Q3: nodes (n_-, n_0, n_+) = (1, 5, 3), (2, 0, 7)
+    rho, j, e = exact.moments_raw(np.array([[1, 2], [5, 0], [3, 7]], dtype=np.uint32), 3)
+    assert rho.tolist() == [9, 9]
+    assert j.tolist() == [2, 5]
+    assert e.tolist() == [4, 9]
+    # D2Q5: node (n_-x, n_-y, n_0, n_+y, n_+x) = (1, 2, 3, 4, 5) and (6, 0, 2, 0, 1)
+    st = np.array([[1, 6], [2, 0], [3, 2], [4, 0], [5, 1]], dtype=np.uint16)
+    rho, j, e = exact.moments_raw(st, 5)
+    assert rho.tolist() == [15, 9]
+    assert j.tolist() == [4, -5]
+    assert e.tolist() == [12, 7]
+    # the same D2Q5 nodes as a [5][Ly][Lx] state keep the node shape
+    rho2, j2, e2 = exact.moments_raw(st.reshape(5, 1, 2), 5)
+    assert rho2.tolist() == [[15, 9]] and j2.tolist() == [[4, -5]] and e2.tolist() == [[12, 7]]
