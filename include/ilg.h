@@ -287,6 +287,10 @@ typedef struct ilg_server ilg_server; /* opaque; owned by the library */
 #define ILG_REQ_ACTIVE 1u
 #define ILG_REQ_DONE 2u
 #define ILG_REQ_CANCELLED 3u
+#define ILG_REQ_FAILED 4u   /* a count of this request exceeded its count type
+                               (at admission or in a quantum); its memory is
+                               freed and its state lost; the other requests are
+                               unaffected */
 
 typedef struct ilg_request_info {
     uint64_t id;
@@ -300,7 +304,8 @@ typedef struct ilg_request_info {
 typedef struct ilg_poll_info {
     uint32_t admitted, active, queued, finished; /* in this poll / after it */
     uint32_t quantum_steps;                      /* longest advance in this poll */
-    uint32_t reserved;
+    uint32_t failed;                             /* requests that failed in this poll
+                                                    (ILG_REQ_FAILED) */
     uint64_t bytes_in_use, bytes_peak;           /* device budget accounting */
 } ilg_poll_info;
 
@@ -342,7 +347,9 @@ int ilg_server_poll(ilg_server *s, ilg_poll_info *info);
 /* State and timestamps of a request that has not been collected. */
 int ilg_server_info(ilg_server *s, uint64_t id, ilg_request_info *out);
 
-/* Copy a finished request's final [q][L] counts to host_out and forget it. */
+/* Copy a finished request's final [q][L] counts to host_out and forget it.
+ * For a failed request (ILG_REQ_FAILED) nothing is copied: it is forgotten
+ * and ILG_E_OVERFLOW is returned, with the request id in ilg_last_error(). */
 int ilg_server_result(ilg_server *s, uint64_t id, void *host_out);
 
 /* Drop a queued or active request and release its memory. */

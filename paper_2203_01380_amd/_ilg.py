@@ -70,7 +70,7 @@ class IlgRequestInfo(ctypes.Structure):
 class IlgPollInfo(ctypes.Structure):
     _fields_ = [("admitted", ctypes.c_uint32), ("active", ctypes.c_uint32),
                 ("queued", ctypes.c_uint32), ("finished", ctypes.c_uint32),
-                ("quantum_steps", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("quantum_steps", ctypes.c_uint32), ("failed", ctypes.c_uint32),
                 ("bytes_in_use", ctypes.c_uint64), ("bytes_peak", ctypes.c_uint64)]
 
 
@@ -393,7 +393,7 @@ class Batch:
             pass
 
 
-REQ_STATES = {0: "queued", 1: "active", 2: "done", 3: "cancelled"}
+REQ_STATES = {0: "queued", 1: "active", 2: "done", 3: "cancelled", 4: "failed"}
 
 
 class Server:

@@ -208,7 +208,7 @@ struct ServeArgs {
     uint32_t ntiles;
     uint32_t j;             // step index within the quantum
     const void *shared;     // half table then its guide
-    uint32_t *err;
+    uint32_t *slot_err;     // one sticky error word per slot (bit 0: overflow)
 };
 
 hipError_t launch_serve(int q, int count_bytes, int rounds, bool exchange, const ServeArgs &a,

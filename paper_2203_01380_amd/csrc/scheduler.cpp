@@ -80,26 +80,46 @@ bool Scheduler::submit(std::unique_ptr<Req> r, Executor &ex, uint64_t *id, doubl
     return true;
 }
 
-int Scheduler::settle(Executor &ex, double (*clock)(), uint32_t *finished)
+void Scheduler::retire_failed(Req *r, double now)
 {
-    uint32_t nfin = 0;
+    arena_.free(r->mem_off, r->bytes);
+    r->state = ReqState::Failed;
+    r->t_done = now;
+    r->payload.reset();
+}
+
+int Scheduler::settle(Executor &ex, double (*clock)(), uint32_t *finished, uint32_t *failed)
+{
+    uint32_t nfin = 0, nfail = 0;
     if (!inflight_.empty()) {
         int rc = ex.wait();
-        if (rc != 0)
-            return rc;
         const double now = clock();
-        for (size_t i = 0; i < inflight_.size(); ++i) {
+        for (size_t i = 0; i < inflight_.size() && rc == 0; ++i) {
             Req *r = inflight_[i];
+            if (r->failed) {
+                retire_failed(r, now);
+                ++nfail;
+                continue;
+            }
             r->done += inflight_steps_[i];
             if (r->done >= r->total) {
                 rc = ex.unload(*r);
                 if (rc != 0)
-                    return rc;
+                    break;
                 arena_.free(r->mem_off, r->bytes);
                 r->state = ReqState::Done;
                 r->t_done = now;
                 ++nfin;
             }
+        }
+        if (rc != 0) {
+            // The device failed: the state of every request of the quantum is
+            // lost.  Retire them so that the others (queued) can still run.
+            for (Req *r : inflight_)
+                if (r->state == ReqState::Active) {
+                    retire_failed(r, now);
+                    ++nfail;
+                }
         }
         std::vector<Req *> still;
         for (Req *r : active_)
@@ -108,13 +128,18 @@ int Scheduler::settle(Executor &ex, double (*clock)(), uint32_t *finished)
         active_.swap(still);
         inflight_.clear();
         inflight_steps_.clear();
+        if (finished)
+            *finished = nfin;
+        if (failed)
+            *failed += nfail;
+        return rc;
     }
     if (finished)
         *finished = nfin;
     return 0;
 }
 
-int Scheduler::admit(Executor &ex, double (*clock)(), uint32_t *admitted)
+int Scheduler::admit(Executor &ex, double (*clock)(), uint32_t *admitted, uint32_t *failed)
 {
     // Strict FIFO, so a large request is never starved by later small ones.
     while (!queue_.empty()) {
@@ -128,9 +153,14 @@ int Scheduler::admit(Executor &ex, double (*clock)(), uint32_t *admitted)
             arena_.free(off, r->bytes);
             return rc;
         }
-        r->state = ReqState::Active;
-        r->t_admit = clock();
         queue_.pop_front();
+        r->t_admit = clock();
+        if (r->failed) {
+            retire_failed(r, r->t_admit);
+            ++*failed;
+            continue;
+        }
+        r->state = ReqState::Active;
         active_.push_back(r);
         ++*admitted;
     }
@@ -167,11 +197,11 @@ int Scheduler::poll(Executor &ex, PollStats *st, double (*clock)())
     // Admissions into memory that is already free overlap the quantum in
     // flight (they touch only their own, unused, memory); a second pass after
     // the quantum has completed uses the memory its finished requests freed.
-    int rc = admit(ex, clock, &s.admitted);
+    int rc = admit(ex, clock, &s.admitted, &s.failed);
     if (rc == 0)
-        rc = settle(ex, clock, &s.finished);
+        rc = settle(ex, clock, &s.finished, &s.failed);
     if (rc == 0)
-        rc = admit(ex, clock, &s.admitted);
+        rc = admit(ex, clock, &s.admitted, &s.failed);
     if (rc != 0)
         return rc;
     if (!active_.empty()) {
@@ -226,7 +256,8 @@ bool Scheduler::cancel(uint64_t id, Executor &ex, double (*clock)())
 bool Scheduler::release(uint64_t id)
 {
     Req *r = find(id);
-    if (!r || (r->state != ReqState::Done && r->state != ReqState::Cancelled))
+    if (!r || (r->state != ReqState::Done && r->state != ReqState::Cancelled &&
+               r->state != ReqState::Failed))
         return false;
     all_.erase(id);
     return true;

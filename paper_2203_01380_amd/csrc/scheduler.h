@@ -25,7 +25,7 @@
 namespace ilg {
 namespace serve {
 
-enum class ReqState : uint32_t { Queued = 0, Active = 1, Done = 2, Cancelled = 3 };
+enum class ReqState : uint32_t { Queued = 0, Active = 1, Done = 2, Cancelled = 3, Failed = 4 };
 
 struct Req {
     uint64_t id = 0;
@@ -37,6 +37,11 @@ struct Req {
     double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;  // steady-clock seconds
     ReqState state = ReqState::Queued;
     uint64_t mem_off = 0;   // arena offset while active
+    // Set by the executor when this request's own device work reported an
+    // error (a count beyond its type, at admission or in a quantum): the
+    // scheduler then retires the request as Failed and frees its memory;
+    // the other requests are unaffected.
+    bool failed = false;
     std::shared_ptr<void> payload;  // executor data (initial / final state, tables)
 };
 
@@ -60,12 +65,16 @@ public:
     virtual ~Executor() = default;
     // Bytes of device memory a request needs while active.
     virtual uint64_t footprint(const Req &r) = 0;
-    // Place the request's initial state and tables at r.mem_off.
+    // Place the request's initial state and tables at r.mem_off.  Sets
+    // r.failed if the request itself cannot start (its initial state does not
+    // fit the count type); a nonzero return is a failure of the device.
     virtual int load(Req &r) = 0;
     // Start advancing active[i] by steps[i] >= 1 steps (may return before the
     // work is done).
     virtual int launch(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) = 0;
-    // Wait for the work of the last launch.
+    // Wait for the work of the last launch and account for it; sets failed on
+    // each launched request whose own work reported an error.  A nonzero
+    // return is a failure of the device (every launched request is then lost).
     virtual int wait() = 0;
     // Copy a finished request's final state out of the device.
     virtual int unload(Req &r) = 0;
@@ -73,6 +82,7 @@ public:
 
 struct PollStats {
     uint32_t admitted = 0, active = 0, queued = 0, finished = 0;
+    uint32_t failed = 0;         // requests retired as Failed by this poll
     uint32_t quantum_steps = 0;  // steps of the longest slot advance launched by this poll
 };
 
@@ -86,13 +96,14 @@ public:
     // fits (FIFO), launch the next quantum.  After a poll that reports no
     // active and no queued request, nothing is in flight.
     int poll(Executor &ex, PollStats *st, double (*clock)());
-    // Wait for the quantum in flight, if any (and retire what it finished).
-    int settle(Executor &ex, double (*clock)(), uint32_t *finished);
+    // Wait for the quantum in flight, if any (and retire what it finished or
+    // what failed).
+    int settle(Executor &ex, double (*clock)(), uint32_t *finished, uint32_t *failed = nullptr);
     Req *find(uint64_t id);
     // Cancel a queued or active request (its memory is released; an active
     // one only after the quantum in flight has completed).
     bool cancel(uint64_t id, Executor &ex, double (*clock)());
-    // Forget a finished or cancelled request.
+    // Forget a finished, failed or cancelled request.
     bool release(uint64_t id);
     uint64_t peak_bytes() const { return arena_.peak(); }
     uint64_t used_bytes() const { return arena_.used(); }
@@ -102,7 +113,8 @@ public:
     void set_step_nodes(uint64_t nodes) { step_nodes_ = nodes; }
 
 private:
-    int admit(Executor &ex, double (*clock)(), uint32_t *admitted);
+    int admit(Executor &ex, double (*clock)(), uint32_t *admitted, uint32_t *failed);
+    void retire_failed(Req *r, double now);
     void pick(std::vector<Req *> *out) const;
 
     uint64_t budget_;

@@ -4,7 +4,9 @@
 // One launch advances every active request (slot) of one (q, count type) by
 // one step: the host lists the slots' tiles of 1024 nodes, slot by slot (each
 // slot's descriptor holds its tile range), and each workgroup of a persistent
-// grid walks a contiguous range of that list.
+// grid walks a contiguous range of that list.  A count beyond the type sets
+// the error word of its own slot only, so one overflowing request does not
+// affect the others.
 // When the walk enters a new slot the workgroup stages the slot's removal and
 // rest tables with their guides in LDS (the half table is shared and staged
 // once).  Slots whose quantum is shorter than the current step index are
@@ -100,8 +102,15 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     uint32_t slot = __builtin_amdgcn_readfirstlane(a.tile_slot[lo]);  // uniform
     uint32_t staged = 0xFFFFFFFFu;
     for (uint32_t tile = lo; tile < hi; ++tile) {
-        while (tile >= const_space(a.slots)[slot].tile_end)
-            ++slot;
+        if (tile >= const_space(a.slots)[slot].tile_end) {
+            // leaving a slot: its overflow is reported in its own error word
+            if (ovf > kMax)
+                atomicOr(a.slot_err + slot, 1u);
+            ovf = 0;
+            do
+                ++slot;
+            while (tile >= const_space(a.slots)[slot].tile_end);
+        }
         const ServeSlot sl = read_slot(a.slots + slot);
         if (a.j >= sl.steps)
             continue;
@@ -183,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         }
     }
     if (ovf > kMax)
-        atomicOr(a.err, 1u);
+        atomicOr(a.slot_err + slot, 1u);
 }
 
 template <int Q, typename T, int NR, bool EX>

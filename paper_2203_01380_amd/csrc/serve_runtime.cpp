@@ -5,6 +5,8 @@
 // quantum with the multi-slot step kernel (one launch per step and per
 // (q, count type, draw specification) group, groups on their own streams so
 // their work overlaps), and copies finished states back to host memory.
+// Every slot of a launch has its own error word, so a request whose counts
+// overflow is retired alone (ILG_REQ_FAILED) and the others go on.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -88,16 +90,16 @@ class DeviceExecutor : public ilg::serve::Executor {
 public:
     void *arena = nullptr;
     void *shared = nullptr;  // half table + guide
-    uint32_t *err = nullptr;
+    uint32_t *init_err = nullptr;  // error word of a device-drawn initial state
     // Launch groups: (q, count type, Philox rounds, exchange form); a group's
     // stream is created when the group first has work.
     static constexpr int kGroups = 24;
     hipStream_t streams[kGroups] = {};
     ilg::ServeSlot *d_slots[kGroups] = {};
+    uint32_t *d_err[kGroups] = {};    // error word of each slot of the last launch
     uint32_t *d_tiles[kGroups] = {};  // slot of each tile
     size_t cap_slots[kGroups] = {}, cap_tiles[kGroups] = {};
     hipStream_t io = nullptr;  // copies in and out
-    int last_rc = ILG_OK;
 
     static int group(uint32_t q, uint32_t cb, const ilg::Fixed &fx)
     {
@@ -119,7 +121,7 @@ public:
         unsigned char *base = static_cast<unsigned char *>(arena) + r.mem_off;
         if (p->device_init) {
             // Poisson sine state drawn in place; a count above the type sets
-            // the sticky error word, reported by the next wait.
+            // init_err, read back below: the request then fails at admission.
             const double theta = c.theta == 0.0 ? 1.0 / 3.0 : c.theta;
             ilg::InitArgs a;
             a.out = base;
@@ -143,7 +145,8 @@ public:
             }
             a.nave = p->nave;
             a.amp = p->amp;
-            a.err = err;
+            a.err = init_err;
+            SHIP(hipMemsetAsync(init_err, 0, sizeof(uint32_t), io));
             hipError_t e = ilg::launch_init((int)cb, a, io);
             if (e != hipSuccess)
                 return shfail(e, "init launch");
@@ -166,7 +169,12 @@ public:
         }
         SHIP(hipMemcpyAsync(base + state_bytes(c), set.data(), set.size(), hipMemcpyHostToDevice,
                             io));
+        uint32_t ierr = 0;
+        if (p->device_init)
+            SHIP(hipMemcpyAsync(&ierr, init_err, sizeof(ierr), hipMemcpyDeviceToHost, io));
         SHIP(hipStreamSynchronize(io));
+        if (ierr & 1u)
+            r.failed = true;  // a drawn count does not fit the count type
         p->t = c.t0;
         p->cur = 0;
         return ILG_OK;
@@ -198,8 +206,10 @@ public:
     // the copies from them have completed).
     std::vector<ilg::ServeSlot> h_slots[kGroups];
     std::vector<uint32_t> h_tiles[kGroups];
+    std::vector<uint32_t> h_err[kGroups];
     std::vector<Req *> launched;
     std::vector<uint32_t> launched_steps;
+    std::vector<std::pair<int, uint32_t>> launched_slot;  // (group, slot) of launched[i]
 
     int launch(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) override
     {
@@ -211,6 +221,7 @@ public:
         }
         launched = active;
         launched_steps = steps;
+        launched_slot.clear();
         uint32_t maxsteps[kGroups] = {};
         for (size_t i = 0; i < active.size(); ++i) {
             Req &r = *active[i];
@@ -233,6 +244,7 @@ public:
             s.p_zero = p->fx.p == 0 ? 1u : 0u;
             s.cur0 = p->cur;
             const uint32_t idx = (uint32_t)slots[g].size();
+            launched_slot.emplace_back(g, idx);
             const uint32_t nt = (uint32_t)((nodes_of(c) + ilg::kServeTile - 1) / ilg::kServeTile);
             s.tile_begin = (uint32_t)tiles[g].size();
             s.tile_end = s.tile_begin + nt;
@@ -252,13 +264,14 @@ public:
                                 hipMemcpyHostToDevice, streams[g]));
             SHIP(hipMemcpyAsync(d_tiles[g], tiles[g].data(), tiles[g].size() * sizeof(uint32_t),
                                 hipMemcpyHostToDevice, streams[g]));
+            SHIP(hipMemsetAsync(d_err[g], 0, slots[g].size() * sizeof(uint32_t), streams[g]));
             ilg::ServeArgs a;
             a.arena = arena;
             a.slots = d_slots[g];
             a.tile_slot = d_tiles[g];
             a.ntiles = (uint32_t)tiles[g].size();
             a.shared = shared;
-            a.err = err;
+            a.slot_err = d_err[g];
             const int q = g >= 16 ? 5 : (g & 8) ? 3 : 2, cb = (g & 4) ? 4 : 2;
             const int rounds = (g & 2) ? 7 : 10;
             const bool exchange = (g & 1) != 0;
@@ -274,21 +287,36 @@ public:
 
     int wait() override
     {
-        for (int g = 0; g < kGroups; ++g)
-            if (!h_slots[g].empty())
-                SHIP(hipStreamSynchronize(streams[g]));
-        uint32_t e = 0;
-        SHIP(hipMemcpy(&e, err, sizeof(e), hipMemcpyDeviceToHost));
-        if (e & 1u)
-            return sfail(ILG_E_OVERFLOW, "a post-collision count exceeded the count type");
+        // Every launched request's step count and buffer parity advance with
+        // the launch, also when its own work overflowed (it is then retired).
         for (size_t i = 0; i < launched.size(); ++i) {
             Payload *p = payload_of(*launched[i]);
             p->t += launched_steps[i];
             p->cur ^= (launched_steps[i] & 1u);
         }
+        int rc = ILG_OK;
+        for (int g = 0; g < kGroups && rc == ILG_OK; ++g) {
+            if (h_slots[g].empty())
+                continue;
+            hipError_t e = hipStreamSynchronize(streams[g]);
+            h_err[g].assign(h_slots[g].size(), 0u);
+            if (e == hipSuccess)
+                e = hipMemcpy(h_err[g].data(), d_err[g], h_err[g].size() * sizeof(uint32_t),
+                              hipMemcpyDeviceToHost);
+            if (e != hipSuccess)
+                rc = shfail(e, "serve quantum");
+        }
+        if (rc == ILG_OK) {
+            for (size_t i = 0; i < launched.size(); ++i) {
+                const auto gs = launched_slot[i];
+                if (h_err[gs.first][gs.second] & 1u)
+                    launched[i]->failed = true;
+            }
+        }
         launched.clear();
         launched_steps.clear();
-        return ILG_OK;
+        launched_slot.clear();
+        return rc;
     }
 
     int unload(Req &r) override
@@ -310,8 +338,12 @@ public:
     {
         if (nslots > cap_slots[g]) {
             (void)hipFree(d_slots[g]);
+            (void)hipFree(d_err[g]);
+            d_slots[g] = nullptr;
+            d_err[g] = nullptr;
             cap_slots[g] = std::max(nslots, 2 * cap_slots[g]);
             SHIP(hipMalloc((void **)&d_slots[g], cap_slots[g] * sizeof(ilg::ServeSlot)));
+            SHIP(hipMalloc((void **)&d_err[g], cap_slots[g] * sizeof(uint32_t)));
         }
         if (ntiles > cap_tiles[g]) {
             (void)hipFree(d_tiles[g]);
@@ -325,6 +357,7 @@ public:
     {
         for (int g = 0; g < kGroups; ++g) {
             (void)hipFree(d_slots[g]);
+            (void)hipFree(d_err[g]);
             (void)hipFree(d_tiles[g]);
             if (streams[g])
                 (void)hipStreamDestroy(streams[g]);
@@ -333,7 +366,7 @@ public:
             (void)hipStreamDestroy(io);
         (void)hipFree(arena);
         (void)hipFree(shared);
-        (void)hipFree(err);
+        (void)hipFree(init_err);
     }
 };
 
@@ -366,7 +399,7 @@ int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server 
     if (e == hipSuccess)
         e = hipMalloc(&ex.shared, ilg::kServeTableBytes + ilg::kServeGuideBytes);
     if (e == hipSuccess)
-        e = hipMalloc((void **)&ex.err, sizeof(uint32_t));
+        e = hipMalloc((void **)&ex.init_err, sizeof(uint32_t));
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&ex.io, hipStreamNonBlocking);
     if (e == hipSuccess) {
@@ -377,8 +410,6 @@ int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server 
         ilg::pad_table(packed.data(), reinterpret_cast<uint32_t *>(sh.data()));
         e = hipMemcpy(ex.shared, sh.data(), sh.size(), hipMemcpyHostToDevice);
     }
-    if (e == hipSuccess)
-        e = hipMemset(ex.err, 0, sizeof(uint32_t));
     if (e != hipSuccess) {
         const int code = e == hipErrorOutOfMemory ? ILG_E_NOMEM : ILG_E_DEVICE;
         std::string msg = std::string("server setup: ") + hipGetErrorString(e);
@@ -474,6 +505,7 @@ int ilg_server_poll(ilg_server *s, ilg_poll_info *info)
         info->queued = st.queued;
         info->finished = st.finished;
         info->quantum_steps = st.quantum_steps;
+        info->failed = st.failed;
         info->bytes_in_use = s->sched->used_bytes();
         info->bytes_peak = s->sched->peak_bytes();
     }
@@ -506,6 +538,11 @@ int ilg_server_result(ilg_server *s, uint64_t id, void *host_out)
     if (!s || !host_out)
         return sfail(ILG_E_INVALID, "null argument");
     Req *r = s->sched->find(id);
+    if (r && r->state == ReqState::Failed) {
+        s->sched->release(id);
+        return sfail(ILG_E_OVERFLOW, "request " + std::to_string(id) +
+                                         ": a count exceeded the count type (its state is lost)");
+    }
     if (!r || r->state != ReqState::Done)
         return sfail(ILG_E_INVALID, "request is not finished");
     const Payload *p = static_cast<const Payload *>(r->payload.get());

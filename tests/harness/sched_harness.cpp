@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <set>
 #include <vector>
 
 #include "scheduler.h"
@@ -25,6 +26,10 @@ struct Counting : Executor {
     uint64_t step_nodes = 0;            // node cap the scheduler was given
     uint64_t active_bytes = 0;
     int violations = 0;
+    // failure injection: requests whose admission fails, and requests whose
+    // next quantum reports an overflow
+    std::set<uint64_t> fail_load, fail_wait;
+    std::vector<Req *> launched;
     uint64_t footprint(const Req &r) override
     {
         return *static_cast<const uint64_t *>(r.payload.get());
@@ -33,9 +38,13 @@ struct Counting : Executor {
     {
         loads[r.id] += 1;
         load_order.push_back(r.id);
-        active_bytes += r.bytes;
         if (r.mem_off + r.bytes > budget)
             ++violations;
+        if (fail_load.count(r.id)) {
+            r.failed = true;
+            return 0;
+        }
+        active_bytes += r.bytes;
         return 0;
     }
     bool in_flight = false;
@@ -45,6 +54,7 @@ struct Counting : Executor {
             ++violations;  // a launch before the previous one was waited for
         in_flight = true;
         last_launch.clear();
+        launched = active;
         uint64_t nodes = 0;
         for (const Req *r : active) {
             last_launch.push_back(r->id);
@@ -64,6 +74,15 @@ struct Counting : Executor {
     int wait() override
     {
         in_flight = false;
+        for (Req *r : launched) {
+            if (fail_wait.count(r->id)) {
+                if (r->failed)
+                    ++violations;  // a failed request was launched again
+                r->failed = true;
+                active_bytes -= r->bytes;
+            }
+        }
+        launched.clear();
         return 0;
     }
     int unload(Req &r) override
@@ -145,6 +164,31 @@ int h_submit(void *hv, uint32_t q, uint64_t bytes, uint64_t steps, uint64_t *id)
     r->total = steps;
     r->payload = std::make_shared<uint64_t>(bytes);
     return h->sched.submit(std::move(r), h->ex, id, fake_now) ? 0 : -6;
+}
+
+void h_fail_load(void *hv, uint64_t id)
+{
+    static_cast<Harness *>(hv)->ex.fail_load.insert(id);
+}
+
+void h_fail_wait(void *hv, uint64_t id)
+{
+    static_cast<Harness *>(hv)->ex.fail_wait.insert(id);
+}
+
+int h_poll5(void *hv, uint32_t *out5)
+{
+    Harness *h = static_cast<Harness *>(hv);
+    PollStats st;
+    int rc = h->sched.poll(h->ex, &st, &fake_clock);
+    out5[0] = st.admitted;
+    out5[1] = st.active;
+    out5[2] = st.queued;
+    out5[3] = st.finished;
+    out5[4] = st.failed;
+    if (h->sched.used_bytes() > h->ex.budget)
+        ++h->ex.violations;
+    return rc;
 }
 
 int h_poll(void *hv, uint32_t *out4)

@@ -203,12 +203,11 @@ def test_batch_diagnostics_long_members_every_shape(ilg, oracle_lib, q):
         b.close()
 
 
-def test_config3_ragged_ensemble_full_size(ilg, oracle_lib):
+@pytest.fixture(scope="module")
+def config3_gpu(ilg):
     """4096 D1Q2 members, L log-uniform in [64, 8192], omega ~ U[1, 1.95],
     seed 1000 + r, Poisson(30) uint16, 5000 steps in one graph replay with
-    S(k), k = 1..16, every 10 steps.  Exact mass for every member; sampled
-    members (shortest, longest and a spread in between) bit-exact against the
-    oracle with their S(k) sums."""
+    S(k), k = 1..16, every 10 steps: final states and S(k) sums."""
     ens = W.ensemble_ragged_d1q2()
     members = [_member(s) for s in ens.specs]
     b = ilg.Batch(members, ens.inits, sk_every=10, nk=16)
@@ -216,42 +215,86 @@ def test_config3_ragged_ensemble_full_size(ilg, oracle_lib):
     b.tune(10)
     b.run(5000)
     sk, nsk = b.structure_factor()
-    assert np.all(nsk == 500)
+    states = [b.state(r) for r in range(len(members))]
+    b.close()
+    return ens, members, states, sk, nsk
+
+
+def _config3_picks(ens, n=256):
+    """n members spread evenly over the length order (shortest and longest
+    included)."""
     lens = np.array([s.length for s in ens.specs])
+    order = np.argsort(lens, kind="stable")
+    return [int(order[i]) for i in np.linspace(0, len(order) - 1, n).round().astype(int)]
+
+
+def test_config3_ragged_ensemble_diagnostics(config3_gpu, oracle_lib):
+    """Exact mass for every member; S(k) sums of 32 members spread by length
+    against the oracle's (with their states); equilibrium S(k) ~ 1."""
+    ens, members, states, sk, nsk = config3_gpu
+    assert np.all(nsk == 500)
     for r in range(len(members)):
-        assert int(b.state(r).astype(np.int64).sum()) == int(ens.inits[r].astype(np.int64).sum())
-    order = np.argsort(lens)
-    picks = list(order[:6]) + list(order[len(order) // 2:len(order) // 2 + 2]) + [order[-1]]
-    _say(f"[config3] oracle for members {picks}")
-    with ThreadPoolExecutor(9) as ex:
+        assert int(states[r].astype(np.int64).sum()) == int(ens.inits[r].astype(np.int64).sum())
+    picks = _config3_picks(ens, 32)
+    _say(f"[config3] oracle with S(k) for {len(picks)} members")
+    with ThreadPoolExecutor(16) as ex:
         res = list(ex.map(lambda r: _oracle_member(oracle_lib, members[r], ens.inits[r], 5000,
                                                    sk_every=10, nk=16), picks))
     for r, (ref, rsk, rnsk, _) in zip(picks, res):
-        np.testing.assert_array_equal(b.state(r), ref, err_msg=f"member {r}")
+        np.testing.assert_array_equal(states[r], ref, err_msg=f"member {r}")
+        assert rnsk == 500
         np.testing.assert_allclose(sk[r], rsk, rtol=1e-9)
     # equilibrium S(k) ~ 1 (Poisson occupations), ensemble mean over members
     Sbar = (sk / nsk[:, None]).mean()
     assert abs(Sbar - 1.0) < 0.02
-    b.close()
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_config3_ragged_ensemble_members(config3_gpu, oracle_lib, part):
+    """256 members spread evenly over the length order (64 per part), each
+    whole final state bit-exact against the oracle's 5000-step run."""
+    ens, members, states, _, _ = config3_gpu
+    picks = _config3_picks(ens, 256)[part::4]
+    _say(f"[config3] oracle for {len(picks)} members (part {part})")
+
+    def one(r):
+        m = members[r]
+        ref, _, ov = oracle_lib.run(oracle_lib.Params(m["q"], m["omega"]), ens.inits[r], 5000,
+                                    seed=m["seed"], realization=m["realization"], nthreads=1)
+        assert not ov
+        return ref
+
+    with ThreadPoolExecutor(16) as ex:
+        refs = list(ex.map(one, picks))
+    for r, ref in zip(picks, refs):
+        np.testing.assert_array_equal(states[r], ref, err_msg=f"member {r}")
 
 
 def _decay_fit(a0, aT, T):
     return -math.log(aT.sum() / a0.sum()) / T
 
 
-def test_config4_decay_sweep_full_size(ilg, oracle_lib):
+@pytest.fixture(scope="module")
+def config4_gpu(ilg):
     """6 omega x 1024 members of D1Q3, L = 4096, uint32, Poisson sine init
-    (mean w_i (100 + 40 sin)), 10^4 steps with A^LG every 100 steps.  One
-    member per omega bit-exact against the oracle; the fitted decay rate per
-    omega against 4 pi^2 D / L^2, D = theta (1/omega^j - 1/2), within 5 of its
-    statistical standard deviations (the ensemble cannot resolve 1e-2 here
-    for omega >= 1.75; the gate at the paper's geometry is the next test)."""
+    (mean w_i (100 + 40 sin)), 10^4 steps with A^LG every 100 steps."""
     ens = W.ensemble_decay_sweep()
     members = [_member(s) for s in ens.specs]
     b = ilg.Batch(members, ens.inits, amp_every=100, max_amp=100)
     _say("[config4] run 10000 steps")
     b.run(10000)
     amp, namp = b.amplitudes()
+    states = [b.state(r) for r in range(len(members))]
+    b.close()
+    return ens, members, states, amp, namp
+
+
+def test_config4_decay_rates(config4_gpu):
+    """The fitted decay rate per omega against 4 pi^2 D / L^2, D = theta
+    (1/omega^j - 1/2), within 5 of its statistical standard deviations (the
+    ensemble cannot resolve 1e-2 here for omega >= 1.75; the gate at the
+    paper's geometry is a separate test)."""
+    ens, members, states, amp, namp = config4_gpu
     assert np.all(namp == 100)
     L, T, nper = 4096, 10000, 1024
     a0 = np.array([exact.amplitude_lg(x.astype(np.int64).sum(axis=0)) for x in ens.inits])
@@ -266,15 +309,24 @@ def test_config4_decay_sweep_full_size(ilg, oracle_lib):
         sig = math.sqrt(var_eq * (1 - math.exp(-2 * gth * T)) / nper) / (40 * math.exp(-gth * T) * gth * T)
         _say(f"[config4] omega={om} gamma/gamma_th={g / gth:.4f} sigma={sig:.4f}")
         assert abs(g / gth - 1) < 5 * sig + 1e-3
-    picks = [oi * nper + 17 for oi in range(6)]
-    _say("[config4] oracle for one member per omega")
-    with ThreadPoolExecutor(6) as ex:
+
+
+@pytest.mark.parametrize("oi", range(len(W.DECAY_SWEEP_OMEGAS)),
+                         ids=[f"omega{om}" for om in W.DECAY_SWEEP_OMEGAS])
+def test_config4_members(config4_gpu, oracle_lib, oi):
+    """16 members of each omega (spread over its 1024), each whole final state
+    and its A^LG series against the oracle's 10^4-step run."""
+    ens, members, states, amp, _ = config4_gpu
+    nper, T = 1024, 10000
+    picks = [oi * nper + k for k in range(5, nper, 64)]
+    assert len(picks) == 16
+    _say(f"[config4] oracle for 16 members of omega {W.DECAY_SWEEP_OMEGAS[oi]}")
+    with ThreadPoolExecutor(16) as ex:
         res = list(ex.map(lambda r: _oracle_member(oracle_lib, members[r], ens.inits[r], T,
                                                    amp_every=100), picks))
     for r, (ref, _, _, ramp) in zip(picks, res):
-        np.testing.assert_array_equal(b.state(r), ref, err_msg=f"member {r}")
+        np.testing.assert_array_equal(states[r], ref, err_msg=f"member {r}")
         np.testing.assert_allclose(amp[r], ramp, rtol=1e-9, atol=1e-9)
-    b.close()
 
 
 def test_decay_rate_gate_paper_geometry(ilg):

@@ -279,33 +279,3 @@ def test_diagnostics(ilg, oracle_lib, q, cb, L):
     Sk = exact.structure_factor(rho, 16)
     np.testing.assert_allclose(m["sk"], Sk, rtol=1e-8, atol=1e-9 * N.sum())
     lat.close()
-
-
-def test_full_size_d1q3_l2_24_lightcone(ilg, oracle_lib):
-    """D1Q3, L = 2^24, uint16, Poisson(50), omega = 1.8, 2000 steps, in the
-    launch configuration of the benchmark.  Sampled parity: the oracle runs
-    light-cone windows of 2T + 256 nodes from the initial state and must agree
-    with the GPU on the 256 central nodes (windows include the wrap at x = 0);
-    plus exact mass conservation and a full-lattice one-step comparison."""
-    spec, init = W.workload_d1q3_big()
-    L, T = spec.length, spec.steps
-    p = oracle_lib.Params(3, spec.omega)
-    _say("[full-size] one step, full lattice")
-    lat = ilg.Lattice(3, L, 2, spec.omega, spec.seed, init)
-    lat.step(1)
-    one, _, _ = oracle_lib.run(p, init, 1, seed=spec.seed)
-    np.testing.assert_array_equal(lat.state(), one)
-    _say("[full-size] remaining steps on the GPU")
-    lat.step(T - 1)
-    final = lat.state()
-    assert int(final.astype(np.int64).sum()) == int(init.astype(np.int64).sum())
-    lat.close()
-    width = 2 * T + 256
-    for centre in [0, 12345, L // 2, L - 100]:
-        x0 = (centre - T) % L
-        idx = (x0 + np.arange(width)) % L
-        _say(f"[full-size] light-cone window at {centre}")
-        win, ov = oracle_lib.run_window(p, np.ascontiguousarray(init[:, idx]), L, x0, T,
-                                        seed=spec.seed)
-        assert not ov
-        np.testing.assert_array_equal(win[:, T:T + 256], final[:, idx[T:T + 256]])

@@ -263,3 +263,85 @@ def test_device_drawn_initial_states(ilg, oracle_lib):
                                     seed=m["seed"], realization=m["realization"], t0=m["t0"])
         np.testing.assert_array_equal(got, want)
     srv.close()
+
+
+def _drain(srv, limit=100000):
+    failed = 0
+    for _ in range(limit):
+        st = srv.poll()
+        failed += st["failed"]
+        if st["active"] == 0 and st["queued"] == 0:
+            return failed
+    raise AssertionError("server did not drain")
+
+
+def test_overflowing_request_fails_alone(ilg):
+    """One request whose counts overflow uint16 in its first step and one
+    whose device-drawn initial state overflows at admission are each retired
+    as failed (ILG_E_OVERFLOW from result, naming the request); the requests
+    beside them in the same launches finish bit-identical to their runs
+    alone, and the server goes on serving."""
+    reqs = _requests(12, seed=31)
+    srv = ilg.Server(64 << 20, quantum_steps=20)
+    ids = [srv.submit(m, init, ns) for m, init, ns in reqs[:6]]
+    # omega = 1, no flip: every particle collides; 3 x 40000 particles per
+    # node send about 80000 to the rest velocity, beyond 65535
+    bad = srv.submit(dict(q=3, length=3000, count_bytes=2, omega=1.0, seed=5),
+                     np.full((3, 3000), 40000, np.uint16), 50)
+    # Poisson means of 5e5 per velocity do not fit uint16
+    bad_init = srv.submit_poisson_sine(dict(q=2, length=700, count_bytes=2, omega=1.5, seed=6),
+                                       1.0e6, 0.0, 3, 40)
+    ids += [srv.submit(m, init, ns) for m, init, ns in reqs[6:]]
+    assert _drain(srv) == 2
+    for rid in (bad, bad_init):
+        assert srv.info(rid)["state"] == "failed"
+        with pytest.raises(ilg.IlgError) as e:
+            srv.result(rid)
+        assert e.value.code == -4 and f"request {rid}" in str(e.value)
+    for rid, (m, init, ns) in zip(ids, reqs):
+        assert srv.info(rid)["state"] == "done"
+        np.testing.assert_array_equal(srv.result(rid), _alone(ilg, m, init, ns),
+                                      err_msg=f"request {rid}")
+    m, init, ns = reqs[7]
+    rid = srv.submit(m, init, ns)
+    assert _drain(srv) == 0
+    np.testing.assert_array_equal(srv.result(rid), _alone(ilg, m, init, ns))
+    srv.close()
+
+
+def test_stream_sized_requests_equal_alone_and_oracle(ilg, oracle_lib):
+    """Requests at the sizes of the serving workload's largest (2^18..2^20
+    nodes, 1024 tiles per slot, hundreds to thousands of steps over many
+    quanta) served beside small ones: each equals its run alone, and the
+    whole final state of every large request equals the oracle's."""
+    large = [(dict(q=3, length=1 << 20, count_bytes=2, omega=1.7, seed=41, realization=1), 2000),
+             (dict(q=2, length=(1 << 19) + 12345, count_bytes=2, omega=1.35, seed=42,
+                   realization=2, t0=17), 700),
+             (dict(q=3, length=1 << 18, count_bytes=4, omega=1.95, seed=43, realization=3), 300),
+             (dict(q=2, length=(1 << 20) - 1, count_bytes=2, omega=1.02, seed=44,
+                   realization=4), 250)]
+    reqs = []
+    for i, (m, ns) in enumerate(large):
+        m.setdefault("t0", 0)
+        reqs.append((m, W.init_poisson_iid(m["q"], m["length"], 40.0, m["count_bytes"],
+                                           init_seed=70 + i), ns))
+    small = _requests(12, seed=32)
+    srv = ilg.Server(1 << 30, quantum_steps=100)
+    ids = []
+    for k, (m, init, ns) in enumerate(reqs + small):
+        ids.append(srv.submit(m, init, ns))
+        if k % 3 == 2:
+            srv.poll()
+    assert _drain(srv) == 0
+    _say("[serve] stream-sized requests done")
+    for k, (m, init, ns) in enumerate(reqs + small):
+        got = srv.result(ids[k])
+        np.testing.assert_array_equal(got, _alone(ilg, m, init, ns), err_msg=f"request {k}")
+        if k < len(reqs):
+            _say(f"[serve] oracle for request {k}: q={m['q']} L={m['length']} steps={ns}")
+            p = oracle_lib.Params(m["q"], m["omega"])
+            ref, _, ov = oracle_lib.run(p, init, ns, seed=m["seed"], realization=m["realization"],
+                                        t0=m["t0"])
+            assert not ov
+            np.testing.assert_array_equal(got, ref, err_msg=f"request {k} vs oracle")
+    srv.close()

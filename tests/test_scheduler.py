@@ -43,6 +43,9 @@ def H(tmp_path_factory):
                                  ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
     L.h_set_step_nodes.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
     L.h_last_launch.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
+    L.h_fail_load.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    L.h_fail_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    L.h_poll5.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]
     return L
 
 
@@ -259,3 +262,59 @@ def test_random_stress(H):
     assert H.h_violations(s.h) == 0 and H.h_used(s.h) == 0
     assert H.h_peak(s.h) <= budget
     s.close()
+
+
+FAILED = 4
+
+
+def test_failed_request_retired_alone(H):
+    """A request whose quantum reports an overflow is retired as Failed (its
+    memory freed, never launched again) while the requests beside it finish
+    with all their steps; later polls keep working and the failed request
+    can be released."""
+    s = Sched(H, 10_000, 10)
+    ids = [s.submit(2, 1000, 35)[1] for _ in range(4)]
+    H.h_fail_wait(s.h, ids[1])
+    failed = 0
+    for _ in range(50):
+        out = (ctypes.c_uint32 * 5)()
+        assert H.h_poll5(s.h, out) == 0
+        failed += out[4]
+        if out[1] == 0 and out[2] == 0:
+            break
+    assert failed == 1
+    assert s.state(ids[1])[0] == FAILED
+    for rid in ids[:1] + ids[2:]:
+        st, done, _, _ = s.state(rid)
+        assert st == 2 and done == 35
+    assert H.h_used(s.h) == 0
+    assert H.h_violations(s.h) == 0
+    assert H.h_release(s.h, ids[1]) == 0
+    # the server still admits and finishes new work
+    rid = s.submit(2, 1000, 5)[1]
+    for _ in range(5):
+        s.poll()
+    assert s.state(rid)[0] == 2
+    H.h_free(s.h)
+
+
+def test_failed_admission_retired_alone(H):
+    """A request whose admission fails (its drawn initial state overflows) is
+    retired as Failed at admission, never launched; FIFO admission goes on
+    with the next request."""
+    s = Sched(H, 2_500, 10)
+    ids = [s.submit(2, 1000, 20)[1] for _ in range(4)]
+    H.h_fail_load(s.h, ids[0])
+    failed = 0
+    for _ in range(50):
+        out = (ctypes.c_uint32 * 5)()
+        assert H.h_poll5(s.h, out) == 0
+        failed += out[4]
+        if out[1] == 0 and out[2] == 0:
+            break
+    assert failed == 1
+    assert s.state(ids[0])[0] == FAILED
+    assert all(s.state(r)[0] == 2 for r in ids[1:])
+    assert H.h_used(s.h) == 0
+    assert H.h_violations(s.h) == 0
+    H.h_free(s.h)
