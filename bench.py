@@ -35,16 +35,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit integer VALU lane operations
-# per second (one wave64 VALU instruction per SIMD every 4 cycles).
-INT_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic integer work per node-update of the headline workload at
-# steady state: 6 draws (one chunk each for a_-, a_+, M, R; two for the rest
-# population a_0 ~ 100) -> 2 Philox4x32-10 blocks of 10 rounds x (2 full
-# 32x32 multiplies + 4 xors) = 120 ops, plus one table compare per draw.
-ALG_INT_OPS_PER_NODE = 2 * 10 * 6 + 6
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: VALU lane-instruction slots per
+# second (a SIMD issues one wave64 VALU instruction every 4 cycles; a
+# half-rate instruction such as the 32x32->64 multiply takes two slots).
+VALU_PEAK_T_LANE_INSTS = 256 * 4 * 16 * 2.4e9 / 1e12
+ALG_BYTES_PER_NODE_UPDATE = 12    # D1Q3 uint16: 3 counts read + 3 written
+
+
 def traffic_file(length: int) -> str:
     return os.path.join(ROOT, "profiles", f"traffic_step_d1q3_u16_l2p{length.bit_length() - 1}.json")
+
+
+SQ_FILE = os.path.join(ROOT, "profiles", "sq_step_d1q3_u16_l2p24.json")
 
 
 MALL_FREE_LENGTH = 1 << 26   # 768 MiB of double-buffered state, beyond the 256 MB MALL
@@ -60,18 +62,41 @@ def step_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(length: int):
-    """HBM bytes per launch of the step kernel from the committed counter
-    summary for this lattice length, or None if absent or taken on a different
-    version of the kernel."""
+def _current_record(path):
+    """A committed counter record, or None if absent or taken on a different
+    version of the step kernel."""
     try:
-        with open(traffic_file(length)) as f:
+        with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     if rec.get("step_source_sha256_16") != step_source_digest():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def counter_traffic(length: int):
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary for this lattice length (None if absent or stale)."""
+    rec = _current_record(traffic_file(length))
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def alu_roofline(ms_per_launch: float, length: int):
+    """The step's VALU issue against the chip's VALU issue slots: wave
+    instructions per launch (SQ_INSTS_VALU, from the committed counter record
+    of the current kernel) x 64 lanes / the launch time measured here."""
+    rec = _current_record(SQ_FILE)
+    if not rec or rec.get("length") != length:
+        return None
+    insts = rec["valu_wave_insts_per_launch"]
+    achieved = insts * 64 / (ms_per_launch / 1e3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_T_LANE_INSTS,
+            "unit": "T VALU lane-instructions/s", "frac": achieved / VALU_PEAK_T_LANE_INSTS,
+            "valu_lane_insts_per_node_update": insts * 64 / length,
+            "source": os.path.relpath(SQ_FILE, ROOT),
+            "note": "instruction issue; 32x32->64 multiplies (two per Philox round) "
+                    "take two issue slots each, so cycle use is higher than this fraction"}
 
 
 def say(msg):
@@ -177,6 +202,56 @@ def cpu_other_configs(W, seconds: float):
     out["serving_requests"] = {"node_updates_per_s": rate, "cores": threads,
                                "sample": f"{k} runs of 20 steps over {len(reqs)} requests of the "
                                          f"stream ({el:.1f} s)"}
+    return out
+
+
+def bench_probes(ilg, stream, warmup: int, launches: int = 200):
+    """The two costs of the headline step apart, in its launch shape: the
+    streaming-only probe (the step's memory traffic, no collision) at 2^24 and
+    2^26 nodes, and the draws-only probe (two Philox4x32 blocks per node, 10
+    and 7 rounds) at 2^24 nodes."""
+    import torch
+    out = {"workload": "D1Q3 uint16 step pattern, one launch per step; draws: 2 Philox "
+                       "blocks per node (counter (x, t, 0, b)), xor-folded to 4 B per node",
+           "launches": launches}
+    # ~0.25 s of streaming launches first, untimed, so that the clock has
+    # ramped up before any timed launch
+    L = 1 << 24
+    pitch = (L + 63) // 64 * 64
+    a = torch.zeros(3 * pitch, dtype=torch.int16, device="cuda")
+    b = torch.zeros_like(a)
+    t_end = time.perf_counter() + 0.25
+    while time.perf_counter() < t_end:
+        for _ in range(100):
+            ilg.probe_stream(3, L, a, b, stream)
+        torch.cuda.synchronize()
+    del a, b
+    for L in (1 << 24, 1 << 26):
+        pitch = (L + 63) // 64 * 64
+        a = torch.zeros(3 * pitch, dtype=torch.int16, device="cuda")
+        b = torch.zeros_like(a)
+        for _ in range(warmup):
+            ilg.probe_stream(3, L, a, b, stream)
+        sec = timed(stream, lambda: [ilg.probe_stream(3, L, a, b, stream)
+                                     for _ in range(launches)])
+        ms = sec * 1e3 / launches
+        gbs = 12 * L / (ms / 1e3) / 1e9
+        out[f"stream_only_l2p{L.bit_length() - 1}"] = {
+            "ms_per_launch": ms, "alg_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "node_updates_per_s": L / (ms / 1e3)}
+        del a, b
+    L = 1 << 24
+    o = torch.zeros(L, dtype=torch.int32, device="cuda")
+    for rounds in (10, 7):
+        for _ in range(warmup):
+            ilg.probe_philox(L, 2, o, rounds=rounds, stream=stream)
+        sec = timed(stream, lambda: [ilg.probe_philox(L, 2, o, rounds=rounds, t=k, stream=stream)
+                                     for k in range(launches)])
+        ms = sec * 1e3 / launches
+        out[f"draws_only_{rounds}_rounds"] = {
+            "ms_per_launch": ms, "philox_blocks_per_s": 2 * L / (ms / 1e3),
+            "node_updates_per_s_bound": L / (ms / 1e3),
+            "hbm_frac_bound": 12 * L / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
     return out
 
 
@@ -476,6 +551,29 @@ def summarize_counters(fetch_csv: str, write_csv: str, length: int):
     print(json.dumps(rec))
 
 
+def summarize_sq(csv_path: str, length: int, skip: int):
+    """Turn a rocprofv3 --pmc run of the SQ counters (SQ_INSTS_VALU,
+    SQ_INSTS_SALU, SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT, SQ_WAVE_CYCLES,
+    SQ_WAIT_ANY, SQ_WAIT_INST_ANY, SQ_ACTIVE_INST_ANY) of `bench.py --forms
+    plain` into a per-launch record of the step kernel (dispatches after the
+    first `skip`, when the state has relaxed), kept with the kernel digest."""
+    import csv
+    vals = {}
+    for r in csv.DictReader(open(csv_path)):
+        if "step_kernel" not in r["Kernel_Name"]:
+            continue
+        vals.setdefault(r["Counter_Name"], {})[int(r["Dispatch_Id"])] = float(r["Counter_Value"])
+    rec = {"step_source_sha256_16": step_source_digest(), "length": length, "skipped": skip}
+    for name, per in vals.items():
+        ids = sorted(per)[skip:]
+        rec[name.lower() + "_per_launch"] = float(np.mean([per[i] for i in ids]))
+        rec["dispatches"] = len(ids)
+    rec["valu_wave_insts_per_launch"] = rec.get("sq_insts_valu_per_launch")
+    with open(SQ_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -484,9 +582,9 @@ def main():
     ap.add_argument("--length", type=int, default=1 << 24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,mallfree,philox7,exchange,d2q5,batched,batched_specs,batched_d2q5,decay,serving_saturated,serving",
-                    help="comma list of plain (always), mallfree, philox7, exchange, d2q5, "
-                         "batched, batched_specs, batched_d2q5, decay, serving_saturated, "
+    ap.add_argument("--forms", default="plain,probes,mallfree,philox7,exchange,d2q5,batched,batched_specs,batched_d2q5,decay,serving_saturated,serving",
+                    help="comma list of plain (always), probes, mallfree, philox7, exchange, "
+                         "d2q5, batched, batched_specs, batched_d2q5, decay, serving_saturated, "
                          "serving")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-step-nodes", type=int, default=0,
@@ -502,9 +600,17 @@ def main():
                     help="after timing, one plain device copy of 768 MiB (counter scale)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter traffic record from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-sq", metavar="SQ_CSV",
+                    help="write the SQ counter record of the step kernel from a rocprofv3 --pmc "
+                         "run and exit")
+    ap.add_argument("--sq-skip", type=int, default=100,
+                    help="with --summarize-sq: step dispatches to leave out at the start")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, args.length)
+        return
+    if args.summarize_sq:
+        summarize_sq(args.summarize_sq, args.length, args.sq_skip)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -522,6 +628,13 @@ def main():
     spec, init = W.workload_d1q3_big(length=args.length, steps=args.steps)
     mass0 = int(init.astype(np.int64).sum())
     lat = ilg.Lattice(spec.q, spec.length, spec.count_bytes, spec.omega, spec.seed, init)
+    # The probes run between the upload of the headline lattice and its
+    # warm-up steps, back to back: after host-side set-up the GPU clock ramps
+    # up over tens of launches (2.3 -> 2.5 GHz, profiles/
+    # step_d1q3_u16_l2p24_clock_ramp.md), so the timed steps follow
+    # continuous GPU work as they would in a long run.
+    say("probes: streaming only, draws only")
+    probes = bench_probes(ilg, stream, args.warmup)
     say(f"warmup {args.warmup} steps")
     lat.step(args.warmup)
     say(f"timing {args.steps} steps")
@@ -536,11 +649,11 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    ms_per_step = sec * 1e3 / args.steps
+    ms_per_step = sec * 1e3 / args.steps       # one step kernel launch per step
     value = spec.length * args.steps / sec
     alg_bytes = 2 * spec.q * spec.count_bytes * spec.length   # per launch
+    assert alg_bytes == ALG_BYTES_PER_NODE_UPDATE * spec.length
     gbs = alg_bytes / (ms_per_step / 1e3) / 1e9
-    tops = ALG_INT_OPS_PER_NODE * spec.length / (ms_per_step / 1e3) / 1e12
     out = {
         "metric": "node-updates/s",
         "value": value,
@@ -559,13 +672,14 @@ def main():
                                "Philox seed 1",
                    "q": spec.q, "length": spec.length, "count_bytes": spec.count_bytes,
                    "omega": spec.omega, "form": "plain"},
-        "roofline": {"bound": "alu", "achieved": tops, "peak": INT_VALU_PEAK_TOPS,
-                     "unit": "TOP/s", "frac": tops / INT_VALU_PEAK_TOPS,
-                     "traffic": counter_traffic(spec.length),
-                     "alg_ops_per_node_update": ALG_INT_OPS_PER_NODE},
-        "hbm_roofline": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs / HBM_PEAK_GBS, "alg_bytes_per_node_update": 12},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": counter_traffic(spec.length),
+                     "alg_bytes_per_node_update": ALG_BYTES_PER_NODE_UPDATE,
+                     "limiter": "integer VALU (alu_roofline; probes)"},
+        "alu_roofline": alu_roofline(ms_per_step, spec.length),
     }
+    if "probes" in forms:
+        out["probes"] = probes
     if "mallfree" in forms and spec.length != MALL_FREE_LENGTH:
         say("plain step at 2^26 nodes")
         out["plain_l2p26"] = bench_plain_mall_free(ilg, W, stream, args.warmup)

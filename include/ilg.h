@@ -154,10 +154,15 @@ int ilg_binomial_table(uint64_t p, uint32_t *out);
 uint64_t ilg_state_bytes(const ilg_config *cfg);
 uint64_t ilg_state_pitch(const ilg_config *cfg);
 
-/* Create a lattice; init_host is [q][nodes] counts (compact, count_bytes
- * each; D2Q5 [5][Ly][Lx]),
- * copied before return, or NULL for an all-zero state (to be replaced by
- * ilg_init_poisson_sine).  Device buffers are owned by the handle. */
+/* Create a lattice: the integer occupation numbers n_i(x, t0) of the
+ * Integer Lattice Gas section (one count per node and velocity) and the
+ * configuration's collision fraction and flip (Over-relaxation section).
+ * init_host is [q][nodes] counts (compact, count_bytes each; D2Q5
+ * [5][Ly][Lx]), copied before return, or NULL for an all-zero state (to be
+ * replaced by ilg_init_poisson_sine).  Device buffers, tables and the error
+ * word are owned by the handle.  *out is NULL on failure.  ILG_E_INVALID for
+ * a bad configuration, ILG_E_NOMEM / ILG_E_DEVICE if device memory or a copy
+ * fails. */
 int ilg_create(const ilg_config *cfg, const void *init_host, void *stream, ilg_handle **out);
 
 /* Create a lattice on caller-owned device buffers of ilg_state_bytes(cfg)
@@ -169,10 +174,20 @@ int ilg_create_on(const ilg_config *cfg, void *buf0, void *buf1, void *stream, i
 /* Device address of the buffer holding the current state (device layout). */
 void *ilg_state_device(const ilg_handle *h);
 
-/* Enqueue nsteps time steps (flip, collide, stream) on the handle's stream. */
+/* Enqueue nsteps time steps on the handle's stream (asynchronous): each is
+ * Eq. LGflip at every node (the flip of Eq. flip, then the sampling collision
+ * of the Integer Lattice Gas section with fraction omega*), followed by the
+ * streaming of Eq. ilgeq, n_i(x + v_i, t + 1) <- c_i(x).  Draws use the
+ * absolute step index, so the split of steps over calls does not matter.
+ * ILG_E_RANGE (nothing enqueued) if the step index would pass 2^32 - 1;
+ * ILG_E_DEVICE if a launch fails; a count overflow is reported later by a
+ * syncing call. */
 int ilg_step(ilg_handle *h, uint64_t nsteps);
 
-/* Copy the current state to host [q][L] (compact).  Syncs. */
+/* Copy the current occupations n_i(x, t) (Integer Lattice Gas section) to
+ * host_out, [q][nodes] compact counts of count_bytes each (D2Q5
+ * [5][Ly][Lx]); caller-owned.  Syncs; ILG_E_OVERFLOW if an earlier step
+ * overflowed (the copied state is then undefined). */
 int ilg_get_state(ilg_handle *h, void *host_out);
 
 /* Replace the state by host [q][nodes] counts and set the absolute step index of
@@ -201,13 +216,22 @@ int ilg_init_poisson_sine(ilg_handle *h, double nave, double amp, uint64_t init_
 int ilg_moments(ilg_handle *h, int64_t *rho, int64_t *j, int64_t *e, uint32_t nk,
                 ilg_summary *out);
 
-/* Order-independent 64-bit hash of the current state.  Syncs. */
+/* Order-independent 64-bit fingerprint of the current occupations (the
+ * state of Eq. ilgeq): the sum over nodes x and velocities i of
+ * splitmix64(((x q + i) << 32) ^ n_i(x)) modulo 2^64, with the SplitMix64
+ * finaliser of Steele, Lea & Flood.  Equal states give equal hashes, so runs
+ * can be compared step by step without copying states.  Syncs; sticky errors
+ * as ilg_get_state. */
 int ilg_state_hash(ilg_handle *h, uint64_t *out);
 
 /* Absolute index of the next step. */
 uint64_t ilg_current_step(const ilg_handle *h);
 
-/* Wait for the handle's work, report sticky errors, free what it owns. */
+/* End a lattice run (the evolution of Eq. LGflip stops): wait for the
+ * handle's work, report a sticky overflow (ILG_E_OVERFLOW) of the steps not
+ * yet checked, and free what the handle owns (borrowed buffers of
+ * ilg_create_on are left to the caller).  h is invalid afterwards, whatever
+ * the return value; NULL is accepted. */
 int ilg_destroy(ilg_handle *h);
 
 
@@ -341,7 +365,11 @@ int ilg_server_submit(ilg_server *s, const ilg_config *cfg, const void *init_hos
 int ilg_server_submit_poisson_sine(ilg_server *s, const ilg_config *cfg, double nave, double amp,
                                    uint64_t init_seed, uint64_t nsteps, uint64_t *id);
 
-/* One scheduling round (admit, advance one quantum, retire).  Syncs. */
+/* One scheduling round: admit what fits free memory, wait for the quantum
+ * launched by the previous poll and retire the requests it finished (or
+ * that failed), admit again, then launch the next quantum and return while
+ * it runs on the device (the caller's host work overlaps it).  After a poll
+ * that reports no active and no queued request nothing is in flight. */
 int ilg_server_poll(ilg_server *s, ilg_poll_info *info);
 
 /* State and timestamps of a request that has not been collected. */
@@ -357,6 +385,28 @@ int ilg_server_cancel(ilg_server *s, uint64_t id);
 
 /* Wait for the server's work and free everything it owns. */
 int ilg_server_destroy(ilg_server *s);
+
+/* ------------------------------------------------------------------------
+ * Measurement probes (not part of the method): each runs one of the two
+ * costs the fused step combines, with the step kernel's launch shape, so
+ * that a benchmark can place the step between them.  Both are asynchronous
+ * on `stream` and write only their output buffer.
+ * ---------------------------------------------------------------------- */
+
+/* Streaming only: the memory pattern of one uint16 step of a q = 2 or 3
+ * lattice of `length` nodes (the streaming of Eq. ilgeq without the flip or
+ * the collision): out_i[(x + v_i) mod L] = in_i[x].  in_dev and out_dev are
+ * distinct device buffers of ilg_state_bytes() for that lattice ([q][pitch]
+ * uint16).  ILG_E_INVALID for other q or lengths outside [1, 2^31). */
+int ilg_probe_stream(uint32_t q, uint64_t length, const void *in_dev, void *out_dev,
+                     void *stream);
+
+/* Draws only: for every node x < length the Philox4x32 blocks with counter
+ * (x, t, 0, b), b < blocks, key = seed, with `rounds` rounds (10 or 7), as
+ * the step draws them; out_dev[x] (device, length uint32) receives the xor of
+ * all their words.  blocks in [1, 64]. */
+int ilg_probe_philox(uint64_t length, uint32_t blocks, uint32_t rounds, uint32_t t, uint64_t seed,
+                     void *out_dev, void *stream);
 
 #ifdef __cplusplus
 }

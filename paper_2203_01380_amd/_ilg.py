@@ -127,6 +127,8 @@ def _load():
         "ilg_server_result": ([hp, u64, vp], i32),
         "ilg_server_cancel": ([hp, u64], i32),
         "ilg_server_destroy": ([hp], i32),
+        "ilg_probe_stream": ([u32, u64, vp, vp, vp], i32),
+        "ilg_probe_philox": ([u64, u32, u32, u32, u64, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -486,3 +488,21 @@ class Server:
                 lib.ilg_server_destroy(self._h)
         except Exception:
             pass
+
+
+def probe_stream(q: int, length: int, src, dst, stream=None):
+    """Streaming-only probe (ilg_probe_stream): src and dst are torch uint16
+    CUDA tensors of at least q * pitch elements; enqueued on `stream` (torch's
+    current stream by default)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    check(lib.ilg_probe_stream(q, length, src.data_ptr(), dst.data_ptr(), st.cuda_stream))
+
+
+def probe_philox(length: int, blocks: int, out, rounds: int = 10, t: int = 0, seed: int = 1,
+                 stream=None):
+    """Draws-only probe (ilg_probe_philox): out is a torch uint32 (or int32)
+    CUDA tensor of at least `length` elements."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    check(lib.ilg_probe_philox(length, blocks, rounds, t, seed, out.data_ptr(), st.cuda_stream))

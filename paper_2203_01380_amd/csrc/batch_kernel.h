@@ -321,12 +321,6 @@ __device__ __forceinline__ double amp_sample(const T *st, uint32_t L, uint64_t p
     return td > 0.0 ? tn / td : 0.0;
 }
 
-// SK: the launch samples S(k).  Those FP64 accumulators need about twice
-// the registers of the step loop, so the S(k) variant carries an occupancy
-// attribute that caps the register count (the rare diagnostic code spills
-// instead of the step loop losing waves); launches without S(k) use the
-// variant without it.  kMinWaves(BLOCK) is the waves per SIMD needed for two
-// workgroups of 1024 threads (8) or enough smaller ones (6).
 // A member's descriptor read through the constant address space (scalar
 // loads at a uniform index); it is rewritten only after the member's steps.
 __device__ __forceinline__ BatchMeta read_meta(const BatchMeta *p)
@@ -351,6 +345,12 @@ __device__ __forceinline__ BatchMeta read_meta(const BatchMeta *p)
 template <int BLOCK>
 constexpr int kMinWaves = BLOCK >= 1024 ? 8 : 6;
 
+// SK: the launch samples S(k).  Every instantiation carries an occupancy
+// attribute: kMinWaves(BLOCK) waves per SIMD, what two workgroups of 1024
+// threads (8) or enough smaller ones (6) need, which caps the register
+// count.  The S(k) variant's FP64 accumulators need about twice the
+// registers of the step loop; under the cap that rare diagnostic code
+// spills instead of the step loop losing waves.
 // NR: Philox rounds of the draws (10, or 7 for draw specification v2); EX:
 // the D1Q2 exchange form (specification v3).  Both are batch-wide.
 template <int Q, typename T, int BLOCK, int GB, bool SK, int NR, bool EX>
@@ -375,7 +375,10 @@ void batch_kernel(BatchArgs a)
     __shared__ unsigned long long s_redu[kWaves];
     __shared__ double s_twr[Twiddles<BLOCK>::kSize], s_twi[Twiddles<BLOCK>::kSize];
 
-    sampler::stage_row_offsets();
+    const uint32_t *tab_p = s_tab, *tab_half = s_tab + kDevTableEntries;
+    const uint32_t *tab_rest = s_tab + 2 * kDevTableEntries;
+    const sampler::Tabs tb = sampler::make_tabs(tab_p, s_guide, kG);
+    sampler::stage_row_offsets(tab_p, tab_half, tab_rest);
     // Shared tables (P = 2^31 and, for q = 3, P_rest) and their guides, once.
     for (int i = threadIdx.x; i < (kTabs - 1) * kDevTableEntries; i += BLOCK)
         s_tab[kDevTableEntries + i] = a.tabs_shared[i];
@@ -383,9 +386,6 @@ void batch_kernel(BatchArgs a)
     for (int s = 1; s < kTabs; ++s)
         build_guide_lds<GB, BLOCK>(s_tab + s * kDevTableEntries, s_guide + s * kG);
 
-    const uint32_t *tab_p = s_tab, *tab_half = s_tab + kDevTableEntries;
-    const uint32_t *tab_rest = s_tab + 2 * kDevTableEntries;
-    const uint8_t *g_p = s_guide, *g_half = s_guide + kG, *g_rest = s_guide + 2 * kG;
     constexpr W kMax = (W)(T)~(T)0;
     W ovf = 0;
 
@@ -444,11 +444,10 @@ void batch_kernel(BatchArgs a)
                 if constexpr (EX) {
                     static_assert(Q == 2, "the exchange form is defined for D1Q2");
                     sampler::node_exchange<W, NB, GB, NR>(av, cn, x, t, m.realization, m.key0,
-                                                          m.key1, tab_p, g_p, p_zero);
+                                                          m.key1, tb, p_zero);
                 } else {
                     sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, t, m.realization, m.key0,
-                                                           m.key1, tab_p, g_p, tab_half, g_half,
-                                                           tab_rest, g_rest, p_zero);
+                                                           m.key1, tb, p_zero);
                 }
                 ovf |= sampler::or_all<Q, W>(cn);
                 if constexpr (Q == 5) {

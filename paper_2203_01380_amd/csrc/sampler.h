@@ -155,63 +155,130 @@ __device__ __forceinline__ uint32_t draw_word(const Draws<NB, NR> &d, uint32_t j
     return r;
 }
 
-// Byte offset of row m in a padded device table, 4 dev_row_offset(m), for
-// m = 1..64 (entry 0 unused): one LDS word read in place of the multiply
-// and shifts, issued alongside the guide read.  Every kernel that runs the
-// sampler fills it with stage_row_offsets() before its first barrier.
-static __shared__ uint32_t s_row_bytes[kChunk + 1];
-
-__device__ __forceinline__ void stage_row_offsets()
+// LDS addresses as 32-bit integers: ds instructions take them directly, so
+// an address read from LDS needs no base added before the next read.
+using lds_u32 = const __attribute__((address_space(3))) uint32_t;
+__device__ __forceinline__ uint32_t lds_address(const void *p)
 {
-    for (uint32_t m = threadIdx.x; m <= (uint32_t)kChunk; m += blockDim.x)
-        s_row_bytes[m] = m == 0 ? 0u : dev_row_offset(m) * 4u;
+    return (uint32_t)(uintptr_t)((const __attribute__((address_space(3))) void *)p);
+}
+__device__ __forceinline__ uint32_t lds_load(uint32_t addr)
+{
+    return *(lds_u32 *)(uintptr_t)addr;
 }
 
-// Inverse-CDF count of one chunk of m >= 1 trials, #{j < m : row[j] <= u},
-// before its final clamp to m.  The guide gives the count g <= m at the
-// lower edge of u's bucket; rows are nondecreasing, so counting continues
-// from there to the first entry above u.  Tables are in the padded device
-// layout: entries g and g + 1 always exist (past the row they are all-ones
-// sentinels), so the two probes need no bound test, and entry g + 1 <= u
-// implies entry g <= u.  A sentinel compares <= u only for u = 2^32 - 1,
-// where the result may exceed m; the callers' clamp then gives the count.
+// Table ids of a kernel's table set: removal (P), half (2^31), rest (P_rest).
+enum : int { kTidP = 0, kTidHalf = 1, kTidRest = 2 };
+
+// LDS address of row m (m = 1..64, entry 0 unused) of each table of the
+// kernel's set, in the padded device layout: one LDS word read in place of
+// the multiply and shifts and of the table's base address, issued alongside
+// the guide read.  Every kernel that runs the sampler fills it with
+// stage_row_offsets() before its first barrier; the rows stay valid when a
+// kernel restages a table at the same place.
+static __shared__ uint32_t s_row_addr[3][kChunk + 1];
+
+__device__ __forceinline__ void stage_row_offsets(const uint32_t *tab_p, const uint32_t *tab_half,
+                                                  const uint32_t *tab_rest)
+{
+    for (uint32_t i = threadIdx.x; i < 3u * (kChunk + 1); i += blockDim.x) {
+        const uint32_t t = i / (kChunk + 1), m = i % (kChunk + 1);
+        const uint32_t *tab = t == 0 ? tab_p : (t == 1 ? tab_half : tab_rest);
+        s_row_addr[t][m] = m == 0 ? 0u : lds_address(tab + dev_row_offset(m));
+    }
+}
+
+// The table set of a kernel (LDS): the tables' guides, and the LDS address
+// of the removal table's full-chunk row (m = 64), a constant of the kernel.
+struct Tabs {
+    const uint8_t *g_p, *g_half, *g_rest;
+    uint32_t full_p;
+};
+
+// Table set of tables laid out at tab_p, tab_p + kDevTableEntries, tab_p +
+// 2 kDevTableEntries with their guides at g, g + kG, g + 2 kG.
+__device__ __forceinline__ Tabs make_tabs(const uint32_t *tab_p, const uint8_t *g, int kG)
+{
+    return Tabs{g, g + kG, g + 2 * kG, lds_address(tab_p + dev_row_offset(kChunk))};
+}
+
+// First phase of the inverse-CDF count of one chunk of m >= 1 trials,
+// #{j < m : row[j] <= u}: the guide gives the count g <= m at the lower edge
+// of u's bucket; rows are nondecreasing, so counting continues from there.
+// Tables are in the padded device layout: entries g and g + 1 always exist
+// (past the row they are all-ones sentinels), so the two probes need no
+// bound test, and entry g + 1 <= u implies entry g <= u.  A sentinel
+// compares <= u only for u = 2^32 - 1, where the count may exceed m; the
+// callers' clamp to m then gives the count.  Lanes past both probes finish
+// the count in a second phase (finish()), so that the probes of the
+// independent chunks of a node can all be issued before any scan.
+struct Probe {
+    uint32_t c;     // g plus the probes at or below u
+    uint32_t next;  // LDS address of the entry after the probes
+    bool more;      // both probes were <= u: the count may go on
+};
+
 template <int GB>
-__device__ __forceinline__ uint32_t chunk_count_unclamped(const uint32_t *tab,
-                                                          const uint8_t *guide, uint32_t m,
-                                                          uint32_t u)
+__device__ __forceinline__ Probe probe_at(uint32_t row_addr, uint32_t g, uint32_t u)
+{
+    const uint32_t a = row_addr + (g << 2);
+    const uint32_t t0 = lds_load(a), t1 = lds_load(a + 4u);
+    Probe p;
+    p.more = t1 <= u;
+    p.c = g + (t0 <= u ? 1u : 0u) + (p.more ? 1u : 0u);
+    p.next = a + 8u;
+    return p;
+}
+
+// Probe of a row given at run time (m = 1..64) of table TID.
+template <int TID, int GB>
+__device__ __forceinline__ Probe probe_row(const uint8_t *guide, uint32_t m, uint32_t u)
 {
     const uint32_t g = guide[((m - 1u) << GB) + (u >> (32 - GB))];
-    const uint32_t *pg = reinterpret_cast<const uint32_t *>(
-        reinterpret_cast<const uint8_t *>(tab) + (s_row_bytes[m] + (g << 2)));
-    const uint32_t t0 = pg[0], t1 = pg[1];
-    const bool s1 = t1 <= u;
-    uint32_t c = g + (t0 <= u ? 1u : 0u) + (s1 ? 1u : 0u);
-    // Lanes past both probes (c = g + 2) continue the scan from entry c,
-    // under their own lane mask, so a wave without such lanes skips it.
-    bool go = s1;
-    const uint32_t *next = pg + 2;
+    return probe_at<GB>(s_row_addr[TID][m], g, u);
+}
+
+// Probe of the full chunk (m = 64) of the removal table, whose row address
+// is a constant.
+template <int GB>
+__device__ __forceinline__ Probe probe_full(const Tabs &tb, uint32_t u)
+{
+    const uint32_t g = tb.g_p[((uint32_t)(kChunk - 1) << GB) + (u >> (32 - GB))];
+    return probe_at<GB>(tb.full_p, g, u);
+}
+
+// Second phase: lanes whose probes were both <= u continue the count from
+// the probed entry, under their own lane mask.
+__device__ __forceinline__ uint32_t finish(const Probe &p, uint32_t m, uint32_t u)
+{
+    uint32_t c = p.c, next = p.next;
+    bool go = p.more;
     while (go) {
-        go = (c < m) && (*next <= u);
+        go = (c < m) && (lds_load(next) <= u);
         c += go ? 1u : 0u;
-        ++next;
+        next += 4u;
     }
     return c;
 }
 
-// #{j < m : row[j] <= u} for a chunk of m >= 1 trials.
-template <int GB>
-__device__ __forceinline__ uint32_t chunk_count(const uint32_t *tab, const uint8_t *guide,
-                                                uint32_t m, uint32_t u)
+// #{j < m : row[j] <= u} for a chunk of m >= 1 trials of table TID.
+template <int TID, int GB>
+__device__ __forceinline__ uint32_t chunk_count(const uint8_t *guide, uint32_t m, uint32_t u)
 {
-    const uint32_t c = chunk_count_unclamped<GB>(tab, guide, m, u);
+    const uint32_t c = finish(probe_row<TID, GB>(guide, m, u), m, u);
     return c < m ? c : m;
 }
 
-// Bin(n, table) with the chunked rule, consuming draws from index j on.
+__device__ __forceinline__ uint32_t clamp_to(uint32_t c, uint32_t m)
+{
+    return c < m ? c : m;
+}
+
+// Bin(n, table TID) with the chunked rule, consuming draws from index j on.
 // p_zero: the probability is 0 (draws are still consumed).
-template <typename W, int NB, int GB, int NR>
-__device__ __forceinline__ W binomial(W n, uint32_t &j, const uint32_t *tab, const uint8_t *guide,
-                                      bool p_zero, const Draws<NB, NR> &d)
+template <int TID, typename W, int NB, int GB, int NR>
+__device__ __forceinline__ W binomial(W n, uint32_t &j, const uint8_t *guide, bool p_zero,
+                                      const Draws<NB, NR> &d)
 {
     if (!wave_any(n > (W)kChunk)) {
         // at most one chunk per lane
@@ -221,7 +288,7 @@ __device__ __forceinline__ W binomial(W n, uint32_t &j, const uint32_t *tab, con
         if (p_zero)
             return 0;
         const uint32_t m = has ? (uint32_t)n : 1u;
-        const uint32_t c = chunk_count<GB>(tab, guide, m, u);
+        const uint32_t c = chunk_count<TID, GB>(guide, m, u);
         return has ? (W)c : (W)0;
     }
     W total = 0;
@@ -230,38 +297,63 @@ __device__ __forceinline__ W binomial(W n, uint32_t &j, const uint32_t *tab, con
         const uint32_t u = draw_word(d, j);
         ++j;
         if (!p_zero)
-            total += chunk_count<GB>(tab, guide, m, u);
+            total += chunk_count<TID, GB>(guide, m, u);
         n -= m;
     }
     return total;
 }
 
-// One chunk whose draw word is known: m in [0, 64] trials.  m = 0 searches
+// One chunk whose draw word is known: m in [0, 64] trials.  m = 0 probes
 // row 1 and the clamp to m = 0 gives 0.
-template <int GB>
-__device__ __forceinline__ uint32_t chunk_or_zero(const uint32_t *tab, const uint8_t *guide,
-                                                  uint32_t m, uint32_t u)
+template <int TID, int GB>
+__device__ __forceinline__ Probe probe_or_zero(const uint8_t *guide, uint32_t m, uint32_t u)
 {
-    const uint32_t c = chunk_count_unclamped<GB>(tab, guide, m != 0 ? m : 1u, u);
-    return c < m ? c : m;
+    return probe_row<TID, GB>(guide, m != 0 ? m : 1u, u);
 }
 
-// Bin(n, table) for 0 <= n <= 64 K with the chunked rule when the words of
-// the chunks are known: chunk k (64 trials, the last one n - 64 k) uses u[k];
-// chunks past ceil(n / 64) add nothing, and chunks no lane of the wave needs
-// are skipped.
-template <int K, int GB>
-__device__ __forceinline__ uint32_t chunks_upto(const uint32_t *tab, const uint8_t *guide,
-                                                uint32_t n, const uint32_t (&u)[K])
+template <int TID, int GB>
+__device__ __forceinline__ uint32_t chunk_or_zero(const uint8_t *guide, uint32_t m, uint32_t u)
 {
-    uint32_t total = chunk_or_zero<GB>(tab, guide, n < (uint32_t)kChunk ? n : kChunk, u[0]);
+    const uint32_t row = m != 0 ? m : 1u;
+    return clamp_to(finish(probe_row<TID, GB>(guide, row, u), row, u), m);
+}
+
+// Second phase of K probes issued together: one wave-level test skips every
+// scan when no lane needs one (the common case).  rows[k] is the probed row
+// size, the bound of the scan.
+template <int K>
+__device__ __forceinline__ void finish_all(const Probe (&p)[K], const uint32_t (&rows)[K],
+                                           const uint32_t (&u)[K], uint32_t (&c)[K])
+{
+    bool more = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        c[k] = p[k].c;
+        more |= p[k].more;
+    }
+    if (wave_any(more)) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            c[k] = finish(p[k], rows[k], u[k]);
+    }
+}
+
+// Bin(n, table TID) for 0 <= n <= 64 K with the chunked rule when the words
+// of the chunks are known: chunk k (64 trials, the last one n - 64 k) uses
+// u[k]; chunks past ceil(n / 64) add nothing, and chunks no lane of the wave
+// needs are skipped.
+template <int TID, int K, int GB>
+__device__ __forceinline__ uint32_t chunks_upto(const uint8_t *guide, uint32_t n,
+                                                const uint32_t (&u)[K])
+{
+    uint32_t total = chunk_or_zero<TID, GB>(guide, n < (uint32_t)kChunk ? n : kChunk, u[0]);
     static_for<1, K>([&](auto kc) {
         constexpr uint32_t k = decltype(kc)::value;
         const bool need = n > k * kChunk;
         if (wave_any(need)) {
             const uint32_t rest = n - k * kChunk;
-            total += chunk_or_zero<GB>(tab, guide,
-                                       need ? (rest < (uint32_t)kChunk ? rest : kChunk) : 0u, u[k]);
+            total += chunk_or_zero<TID, GB>(
+                guide, need ? (rest < (uint32_t)kChunk ? rest : kChunk) : 0u, u[k]);
         }
     });
     return total;
@@ -274,18 +366,17 @@ __device__ __forceinline__ uint32_t chunks_upto(const uint32_t *tab, const uint8
 // (nothing written) if some lane has R > 64.
 template <typename W, int GB>
 __device__ __forceinline__ bool redistribute3(W M, const uint32_t (&u)[4], W (&mv)[3],
-                                              const uint32_t *tab_half, const uint8_t *g_half,
-                                              const uint32_t *tab_rest, const uint8_t *g_rest)
+                                              const Tabs &tb)
 {
     const uint32_t m = (uint32_t)M;
     const uint32_t um1[3] = {u[0], u[1], u[2]};
-    const W m1 = (W)chunks_upto<3, GB>(tab_rest, g_rest, m, um1);
+    const W m1 = (W)chunks_upto<kTidRest, 3, GB>(tb.g_rest, m, um1);
     const W R = M - m1;
     if (wave_any(R > (W)kChunk))
         return false;
     const uint32_t um0 = pick3(m > (uint32_t)kChunk, m > 2u * kChunk, u[1], u[2], u[3]);
     mv[1] = m1;
-    mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, um0);
+    mv[0] = chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)R, um0);
     mv[2] = R - mv[0];
     return true;
 }
@@ -293,17 +384,15 @@ __device__ __forceinline__ bool redistribute3(W M, const uint32_t (&u)[4], W (&m
 // Node update when the whole wave shares the common draw layout: every
 // removal binomial has 1..64 trials except the middle one (q = 3), which has
 // D1 chunks (1..64 or 65..128 trials).  Draw j then belongs to a fixed
-// binomial, so every word index is a compile-time constant.  The
+// binomial, so every word index is a compile-time constant.  The probes of
+// all removal chunks are issued together, before any scan.  The
 // redistribution may take up to two (q = 2) or three (q = 3, m_1) chunks, the
 // extra chunks masked per lane.  Returns false (nothing written) if the
 // redistribution needs more, or m_0 of q = 3 more than one chunk; the caller
 // then takes the generic path from scratch.
 template <int Q, int D1, typename W, int NB, int GB, int NR>
 __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Draws<NB, NR> &d,
-                                          const uint32_t *tab_p, const uint8_t *g_p,
-                                          const uint32_t *tab_half, const uint8_t *g_half,
-                                          const uint32_t *tab_rest, const uint8_t *g_rest,
-                                          bool p_zero)
+                                          const Tabs &tb, bool p_zero)
 {
     W kv[Q];
     if (p_zero) {
@@ -311,17 +400,40 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
         for (int i = 0; i < Q; ++i)
             kv[i] = 0;
     } else if constexpr (Q == 2) {
-        kv[0] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[0], d.w[0]);
-        kv[1] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[1], d.w[1]);
+        const uint32_t rows[2] = {(uint32_t)av[0], (uint32_t)av[1]};
+        const uint32_t u[2] = {d.w[0], d.w[1]};
+        const Probe p[2] = {probe_row<kTidP, GB>(tb.g_p, rows[0], u[0]),
+                            probe_row<kTidP, GB>(tb.g_p, rows[1], u[1])};
+        uint32_t cc[2];
+        finish_all<2>(p, rows, u, cc);
+        kv[0] = clamp_to(cc[0], rows[0]);
+        kv[1] = clamp_to(cc[1], rows[1]);
+    } else if constexpr (D1 == 1) {
+        const uint32_t rows[3] = {(uint32_t)av[0], (uint32_t)av[1], (uint32_t)av[2]};
+        const uint32_t u[3] = {d.w[0], d.w[1], d.w[2]};
+        const Probe p[3] = {probe_row<kTidP, GB>(tb.g_p, rows[0], u[0]),
+                            probe_row<kTidP, GB>(tb.g_p, rows[1], u[1]),
+                            probe_row<kTidP, GB>(tb.g_p, rows[2], u[2])};
+        uint32_t cc[3];
+        finish_all<3>(p, rows, u, cc);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            kv[i] = clamp_to(cc[i], rows[i]);
     } else {
-        kv[0] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[0], d.w[0]);
-        if constexpr (D1 == 1) {
-            kv[1] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[1], d.w[1]);
-        } else {
-            kv[1] = chunk_count<GB>(tab_p, g_p, (uint32_t)kChunk, d.w[1]) +
-                    chunk_count<GB>(tab_p, g_p, (uint32_t)av[1] - (uint32_t)kChunk, d.w[2]);
-        }
-        kv[2] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[2], d.w[1 + D1]);
+        // the middle binomial: a full chunk (word 1, constant row) and the
+        // remainder (word 2); the outer ones take words 0 and 3
+        const uint32_t rows[4] = {(uint32_t)av[0], (uint32_t)kChunk,
+                                  (uint32_t)av[1] - (uint32_t)kChunk, (uint32_t)av[2]};
+        const uint32_t u[4] = {d.w[0], d.w[1], d.w[2], d.w[3]};
+        const Probe p[4] = {probe_row<kTidP, GB>(tb.g_p, rows[0], u[0]),
+                            probe_full<GB>(tb, u[1]),
+                            probe_row<kTidP, GB>(tb.g_p, rows[2], u[2]),
+                            probe_row<kTidP, GB>(tb.g_p, rows[3], u[3])};
+        uint32_t cc[4];
+        finish_all<4>(p, rows, u, cc);
+        kv[0] = clamp_to(cc[0], rows[0]);
+        kv[1] = clamp_to(cc[1], rows[1]) + clamp_to(cc[2], rows[2]);
+        kv[2] = clamp_to(cc[3], rows[3]);
     }
     W M = 0;
 #pragma unroll
@@ -332,14 +444,14 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
     if (!wave_any(M > (W)kChunk)) {
         // the common case: every redistribution binomial takes one chunk
         if constexpr (Q == 2) {
-            mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)M, d.w[kFirst]);
+            mv[0] = chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)M, d.w[kFirst]);
             mv[1] = M - mv[0];
         } else {
             // m_0 uses the next word only if m_1 consumed one (M > 0); if M = 0
             // then R = 0 and m_0 consumes nothing, so the word is irrelevant.
-            mv[1] = chunk_or_zero<GB>(tab_rest, g_rest, (uint32_t)M, d.w[kFirst]);
+            mv[1] = chunk_or_zero<kTidRest, GB>(tb.g_rest, (uint32_t)M, d.w[kFirst]);
             const W R = M - mv[1];
-            mv[0] = chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, d.w[kFirst + 1]);
+            mv[0] = chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)R, d.w[kFirst + 1]);
             mv[2] = R - mv[0];
         }
     } else if constexpr (Q == 2) {
@@ -347,14 +459,14 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
         if (wave_any(M > (W)(2 * kChunk)))
             return false;
         const uint32_t u[2] = {d.w[2], d.w[3]};
-        mv[0] = (W)chunks_upto<2, GB>(tab_half, g_half, (uint32_t)M, u);
+        mv[0] = (W)chunks_upto<kTidHalf, 2, GB>(tb.g_half, (uint32_t)M, u);
         mv[1] = M - mv[0];
     } else {
         // M <= 192: words kFirst .. kFirst + 3 (at most 7 for D1 <= 2)
         if (wave_any(M > (W)(3 * kChunk)))
             return false;
         const uint32_t u[4] = {d.w[kFirst], d.w[kFirst + 1], d.w[kFirst + 2], d.w[kFirst + 3]};
-        if (!redistribute3<W, GB>(M, u, mv, tab_half, g_half, tab_rest, g_rest))
+        if (!redistribute3<W, GB>(M, u, mv, tb))
             return false;
     }
 #pragma unroll
@@ -366,15 +478,13 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
 // q = 3 node update when the outer removal binomials have 1..64 trials but
 // the middle one's chunk count D1 = ceil(a_1 / 64) in {1, 2, 3} differs
 // between lanes: chunks past the first are masked per lane, and the words of
-// the later binomials (draws 1 + D1 on) are selected per lane.  The
-// redistribution is as in node_fast.  Returns false (nothing written) where
-// node_fast would, or if a needed word lies beyond the eight computed.
+// the later binomials (draws 1 + D1 on) are selected per lane.  The first two
+// chunks of the middle binomial and the outer binomials are probed together.
+// The redistribution is as in node_fast.  Returns false (nothing written)
+// where node_fast would, or if a needed word lies beyond the eight computed.
 template <typename W, int NB, int GB, int NR>
 __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Draws<NB, NR> &d,
-                                          const uint32_t *tab_p, const uint8_t *g_p,
-                                          const uint32_t *tab_half, const uint8_t *g_half,
-                                          const uint32_t *tab_rest, const uint8_t *g_rest,
-                                          bool p_zero)
+                                          const Tabs &tb, bool p_zero)
 {
     static_assert(NB >= 2, "draws 0..6 must be computed up front");
     const uint32_t a1 = (uint32_t)av[1];
@@ -383,17 +493,25 @@ __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Dra
     if (p_zero) {
         kv[0] = kv[1] = kv[2] = 0;
     } else {
-        kv[0] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[0], d.w[0]);
-        uint32_t k1 = chunk_count<GB>(tab_p, g_p, c2 ? (uint32_t)kChunk : a1, d.w[1]);
-        if (wave_any(c2)) {
-            const uint32_t m2 = c3 ? (uint32_t)kChunk : (c2 ? a1 - kChunk : 0u);
-            k1 += chunk_or_zero<GB>(tab_p, g_p, m2, d.w[2]);
-        }
+        // chunk sizes: a_0; the middle's first chunk; its second (0 where the
+        // lane has one chunk; a zero-trial chunk probes row 1, clamped to 0);
+        // a_2 at the word after the middle's chunks
+        const uint32_t m1b = c3 ? (uint32_t)kChunk : (c2 ? a1 - kChunk : 0u);
+        const uint32_t rows[4] = {(uint32_t)av[0], c2 ? (uint32_t)kChunk : a1,
+                                  m1b != 0 ? m1b : 1u, (uint32_t)av[2]};
+        const uint32_t u[4] = {d.w[0], d.w[1], d.w[2], pick3(c2, c3, d.w[2], d.w[3], d.w[4])};
+        const Probe p[4] = {probe_row<kTidP, GB>(tb.g_p, rows[0], u[0]),
+                            probe_row<kTidP, GB>(tb.g_p, rows[1], u[1]),
+                            probe_row<kTidP, GB>(tb.g_p, rows[2], u[2]),
+                            probe_row<kTidP, GB>(tb.g_p, rows[3], u[3])};
+        uint32_t cc[4];
+        finish_all<4>(p, rows, u, cc);
+        kv[0] = clamp_to(cc[0], rows[0]);
+        uint32_t k1 = clamp_to(cc[1], rows[1]) + clamp_to(cc[2], m1b);
         if (wave_any(c3))
-            k1 += chunk_or_zero<GB>(tab_p, g_p, c3 ? a1 - 2u * kChunk : 0u, d.w[3]);
+            k1 += chunk_or_zero<kTidP, GB>(tb.g_p, c3 ? a1 - 2u * kChunk : 0u, d.w[3]);
         kv[1] = (W)k1;
-        const uint32_t u2 = pick3(c2, c3, d.w[2], d.w[3], d.w[4]);
-        kv[2] = chunk_count<GB>(tab_p, g_p, (uint32_t)av[2], u2);
+        kv[2] = clamp_to(cc[3], rows[3]);
     }
     const W M = kv[0] + kv[1] + kv[2];
     // Redistribution words start at 2 + D1; the fourth of them would be draw
@@ -405,7 +523,7 @@ __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Dra
                            pick3(c2, c3, d.w[5], d.w[6], d.w[7]),
                            pick3(c2, c3, d.w[6], d.w[7], 0u)};
     W mv[3];
-    if (!redistribute3<W, GB>(M, u, mv, tab_half, g_half, tab_rest, g_rest))
+    if (!redistribute3<W, GB>(M, u, mv, tb))
         return false;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -436,13 +554,12 @@ __device__ __forceinline__ W or_all(const W (&c)[Q])
 // theta) at 5, the x/y split Bin(R, 1/2) at 6, Bin(m_x, 1/2) for -x at 7 and
 // Bin(m_y, 1/2) for -y at the next draw (8 if the -x split took one, else 7).
 // Earlier zero counts make the later words irrelevant (M = 0 or R = 0 leaves
-// nothing to split).  Returns false (nothing written) if some lane has M > 64.
+// nothing to split).  The removal chunks are probed together, and so are
+// the two last splits.  Returns false (nothing written) if some lane has
+// M > 64.
 template <typename W, int NB, int GB, int NR>
 __device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Draws<NB, NR> &d,
-                                           const uint32_t *tab_p, const uint8_t *g_p,
-                                           const uint32_t *tab_half, const uint8_t *g_half,
-                                           const uint32_t *tab_rest, const uint8_t *g_rest,
-                                           bool p_zero)
+                                           const Tabs &tb, bool p_zero)
 {
     static_assert(NB >= 3, "draws 0..9 must be computed up front");
     const uint32_t a2 = (uint32_t)av[2];
@@ -458,28 +575,46 @@ __device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Dr
         for (int i = 0; i < 5; ++i)
             kv[i] = 0;
     } else {
-        kv[0] = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[0], d.w[0]);
-        kv[1] = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[1], d.w[1]);
-        uint32_t k2 = chunk_count<GB>(tab_p, g_p, two ? (uint32_t)kChunk : a2, d.w[2]);
-        if (wave_any(two))
-            k2 += chunk_or_zero<GB>(tab_p, g_p, two ? a2 - kChunk : 0u, d.w[3]);
-        kv[2] = (W)k2;
-        kv[3] = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[3], wk(std::integral_constant<int, 3>{}));
-        kv[4] = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[4], wk(std::integral_constant<int, 4>{}));
+        const uint32_t m2b = two ? a2 - kChunk : 0u;
+        const uint32_t rows[6] = {(uint32_t)av[0], (uint32_t)av[1],
+                                  two ? (uint32_t)kChunk : a2, m2b != 0 ? m2b : 1u,
+                                  (uint32_t)av[3], (uint32_t)av[4]};
+        const uint32_t u[6] = {d.w[0], d.w[1], d.w[2], d.w[3],
+                               wk(std::integral_constant<int, 3>{}),
+                               wk(std::integral_constant<int, 4>{})};
+        Probe p[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            p[k] = probe_row<kTidP, GB>(tb.g_p, rows[k], u[k]);
+        uint32_t cc[6];
+        finish_all<6>(p, rows, u, cc);
+        kv[0] = (W)clamp_to(cc[0], rows[0]);
+        kv[1] = (W)clamp_to(cc[1], rows[1]);
+        kv[2] = (W)(clamp_to(cc[2], rows[2]) + clamp_to(cc[3], m2b));
+        kv[3] = (W)clamp_to(cc[4], rows[4]);
+        kv[4] = (W)clamp_to(cc[5], rows[5]);
     }
     const W M = kv[0] + kv[1] + kv[2] + kv[3] + kv[4];
     if (wave_any(M > (W)kChunk))
         return false;
     W mv[5];
-    mv[2] = (W)chunk_or_zero<GB>(tab_rest, g_rest, (uint32_t)M, wk(std::integral_constant<int, 5>{}));
+    mv[2] = (W)chunk_or_zero<kTidRest, GB>(tb.g_rest, (uint32_t)M,
+                                           wk(std::integral_constant<int, 5>{}));
     const W R = M - mv[2];
-    const W mx = (W)chunk_or_zero<GB>(tab_half, g_half, (uint32_t)R, wk(std::integral_constant<int, 6>{}));
+    const W mx = (W)chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)R,
+                                                wk(std::integral_constant<int, 6>{}));
     const W my = R - mx;
     const uint32_t u7 = wk(std::integral_constant<int, 7>{});
-    mv[0] = (W)chunk_or_zero<GB>(tab_half, g_half, (uint32_t)mx, u7);
-    mv[4] = mx - mv[0];
     const uint32_t uy = mx > 0 ? wk(std::integral_constant<int, 8>{}) : u7;
-    mv[1] = (W)chunk_or_zero<GB>(tab_half, g_half, (uint32_t)my, uy);
+    const uint32_t rows[2] = {mx != 0 ? (uint32_t)mx : 1u, my != 0 ? (uint32_t)my : 1u};
+    const uint32_t u[2] = {u7, uy};
+    const Probe p[2] = {probe_row<kTidHalf, GB>(tb.g_half, rows[0], u[0]),
+                        probe_row<kTidHalf, GB>(tb.g_half, rows[1], u[1])};
+    uint32_t cc[2];
+    finish_all<2>(p, rows, u, cc);
+    mv[0] = (W)clamp_to(cc[0], (uint32_t)mx);
+    mv[4] = mx - mv[0];
+    mv[1] = (W)clamp_to(cc[1], (uint32_t)my);
     mv[3] = my - mv[1];
 #pragma unroll
     for (int i = 0; i < 5; ++i)
@@ -492,16 +627,12 @@ template <> struct Wide<uint16_t> { using type = uint32_t; };
 template <> struct Wide<uint32_t> { using type = uint64_t; };
 
 // Full node update: av holds the (already flipped) occupations; cn receives
-// the post-collision counts.  Table pointers are LDS addresses.  NR: Philox
-// rounds of the draws (10 or 7).
+// the post-collision counts.  NR: Philox rounds of the draws (10 or 7).
 // The generic path: every binomial chunk by chunk in the draw order, in
 // the arithmetic type WW (wide enough for every count, sum and result).
 template <int Q, typename WW, int NB, int GB, int NR>
 __device__ __forceinline__ void node_generic(const WW (&av)[Q], WW (&cn)[Q], Draws<NB, NR> &d,
-                                             const uint32_t *tab_p, const uint8_t *g_p,
-                                             const uint32_t *tab_half, const uint8_t *g_half,
-                                             const uint32_t *tab_rest, const uint8_t *g_rest,
-                                             bool p_zero)
+                                             const Tabs &tb, bool p_zero)
 {
     using W = WW;
     W kv[Q], mv[Q];
@@ -509,26 +640,26 @@ __device__ __forceinline__ void node_generic(const WW (&av)[Q], WW (&cn)[Q], Dra
     W M = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        kv[i] = binomial<W, NB, GB>(av[i], j, tab_p, g_p, p_zero, d);
+        kv[i] = binomial<kTidP, W, NB, GB>(av[i], j, tb.g_p, p_zero, d);
         M += kv[i];
     }
     if constexpr (Q == 2) {
-        mv[0] = binomial<W, NB, GB>(M, j, tab_half, g_half, false, d);
+        mv[0] = binomial<kTidHalf, W, NB, GB>(M, j, tb.g_half, false, d);
         mv[1] = M - mv[0];
     } else if constexpr (Q == 5) {
         // rest, then the x/y pair split, then -x within x, -y within y
-        mv[2] = binomial<W, NB, GB>(M, j, tab_rest, g_rest, false, d);
+        mv[2] = binomial<kTidRest, W, NB, GB>(M, j, tb.g_rest, false, d);
         const W R = M - mv[2];
-        const W mx = binomial<W, NB, GB>(R, j, tab_half, g_half, false, d);
+        const W mx = binomial<kTidHalf, W, NB, GB>(R, j, tb.g_half, false, d);
         const W my = R - mx;
-        mv[0] = binomial<W, NB, GB>(mx, j, tab_half, g_half, false, d);
+        mv[0] = binomial<kTidHalf, W, NB, GB>(mx, j, tb.g_half, false, d);
         mv[4] = mx - mv[0];
-        mv[1] = binomial<W, NB, GB>(my, j, tab_half, g_half, false, d);
+        mv[1] = binomial<kTidHalf, W, NB, GB>(my, j, tb.g_half, false, d);
         mv[3] = my - mv[1];
     } else {
-        mv[1] = binomial<W, NB, GB>(M, j, tab_rest, g_rest, false, d);
+        mv[1] = binomial<kTidRest, W, NB, GB>(M, j, tb.g_rest, false, d);
         const W R = M - mv[1];
-        mv[0] = binomial<W, NB, GB>(R, j, tab_half, g_half, false, d);
+        mv[0] = binomial<kTidHalf, W, NB, GB>(R, j, tb.g_half, false, d);
         mv[2] = R - mv[0];
     }
 #pragma unroll
@@ -539,10 +670,7 @@ __device__ __forceinline__ void node_generic(const WW (&av)[Q], WW (&cn)[Q], Dra
 template <int Q, typename W, int NB, int GB, int NR = 10>
 __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32_t x, uint32_t t,
                                             uint32_t r, uint32_t key0, uint32_t key1,
-                                            const uint32_t *tab_p, const uint8_t *g_p,
-                                            const uint32_t *tab_half, const uint8_t *g_half,
-                                            const uint32_t *tab_rest, const uint8_t *g_rest,
-                                            bool p_zero)
+                                            const Tabs &tb, bool p_zero)
 {
     Draws<NB, NR> d;
     d.init(x, t, r, key0, key1);
@@ -576,18 +704,14 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
         for (int i = 0; i < Q; ++i)
             a32[i] = (uint32_t)av[i];
         if constexpr (Q == 5)
-            done = node_fast5<uint32_t, NB, GB>(a32, c32, d, tab_p, g_p, tab_half, g_half,
-                                                tab_rest, g_rest, p_zero);
+            done = node_fast5<uint32_t, NB, GB>(a32, c32, d, tb, p_zero);
         else if (two_mask == 0ull)
-            done = node_fast<Q, 1, uint32_t, NB, GB>(a32, c32, d, tab_p, g_p, tab_half, g_half,
-                                                     tab_rest, g_rest, p_zero);
+            done = node_fast<Q, 1, uint32_t, NB, GB>(a32, c32, d, tb, p_zero);
         else if constexpr (Q == 3) {
             if (two_mask == lanes && three_mask == 0ull)
-                done = node_fast<Q, 2, uint32_t, NB, GB>(a32, c32, d, tab_p, g_p, tab_half,
-                                                         g_half, tab_rest, g_rest, p_zero);
+                done = node_fast<Q, 2, uint32_t, NB, GB>(a32, c32, d, tb, p_zero);
             else
-                done = node_var3<uint32_t, NB, GB>(a32, c32, d, tab_p, g_p, tab_half, g_half,
-                                                   tab_rest, g_rest, p_zero);
+                done = node_var3<uint32_t, NB, GB>(a32, c32, d, tb, p_zero);
         }
         if (done) {
 #pragma unroll
@@ -608,29 +732,27 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
                     a32[i] = (uint32_t)av[i];
-                node_generic<Q, uint32_t, NB, GB>(a32, c32, d, tab_p, g_p, tab_half, g_half,
-                                                  tab_rest, g_rest, p_zero);
+                node_generic<Q, uint32_t, NB, GB>(a32, c32, d, tb, p_zero);
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
                     cn[i] = (W)c32[i];
                 return;
             }
         }
-        node_generic<Q, W, NB, GB>(av, cn, d, tab_p, g_p, tab_half, g_half, tab_rest, g_rest,
-                                   p_zero);
+        node_generic<Q, W, NB, GB>(av, cn, d, tb, p_zero);
     }
 }
 
 // D1Q2 exchange form (draw specification v3): av holds the (flipped)
 // occupations a_-, a_+; X = Bin(a_-, p_x) particles cross to +1, then
-// Y = Bin(a_+, p_x) cross to -1 (tab_p/g_p are the crossing probability's
-// table and guide).  When every lane has both counts in 1..64 the two draws
-// are words 0 and 1; otherwise the generic chunked binomials.
+// Y = Bin(a_+, p_x) cross to -1 (the P table slot holds the crossing
+// probability's table and guide).  When every lane has both counts in 1..64
+// the two draws are words 0 and 1, probed together; otherwise the generic
+// chunked binomials.
 template <typename W, int NB, int GB, int NR = 10>
 __device__ __forceinline__ void node_exchange(const W (&av)[2], W (&cn)[2], uint32_t x, uint32_t t,
                                               uint32_t r, uint32_t key0, uint32_t key1,
-                                              const uint32_t *tab_p, const uint8_t *g_p,
-                                              bool p_zero)
+                                              const Tabs &tb, bool p_zero)
 {
     Draws<NB, NR> d;
     d.init(x, t, r, key0, key1);
@@ -640,13 +762,19 @@ __device__ __forceinline__ void node_exchange(const W (&av)[2], W (&cn)[2], uint
         if (p_zero) {
             X = Y = 0;
         } else {
-            X = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[0], d.w[0]);
-            Y = (W)chunk_count<GB>(tab_p, g_p, (uint32_t)av[1], d.w[1]);
+            const uint32_t rows[2] = {(uint32_t)av[0], (uint32_t)av[1]};
+            const uint32_t u[2] = {d.w[0], d.w[1]};
+            const Probe p[2] = {probe_row<kTidP, GB>(tb.g_p, rows[0], u[0]),
+                                probe_row<kTidP, GB>(tb.g_p, rows[1], u[1])};
+            uint32_t cc[2];
+            finish_all<2>(p, rows, u, cc);
+            X = (W)clamp_to(cc[0], rows[0]);
+            Y = (W)clamp_to(cc[1], rows[1]);
         }
     } else {
         uint32_t j = 0;
-        X = binomial<W, NB, GB>(av[0], j, tab_p, g_p, p_zero, d);
-        Y = binomial<W, NB, GB>(av[1], j, tab_p, g_p, p_zero, d);
+        X = binomial<kTidP, W, NB, GB>(av[0], j, tb.g_p, p_zero, d);
+        Y = binomial<kTidP, W, NB, GB>(av[1], j, tb.g_p, p_zero, d);
     }
     cn[0] = av[0] - X + Y;
     cn[1] = av[1] - Y + X;

@@ -70,7 +70,10 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     uint32_t *s_tab = reinterpret_cast<uint32_t *>(s_lds);
     uint8_t *s_guide = s_lds + kTabBytes;
 
-    sampler::stage_row_offsets();
+    const uint32_t *tab_p = s_tab, *tab_half = s_tab + kDevTableEntries;
+    const uint32_t *tab_rest = s_tab + 2 * kDevTableEntries;
+    const sampler::Tabs tb = sampler::make_tabs(tab_p, s_guide, kG);
+    sampler::stage_row_offsets(tab_p, tab_half, tab_rest);
     // shared half table (slot 1 in LDS) and its guide
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.shared);
@@ -83,9 +86,6 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         for (int i = threadIdx.x; i < kG / 16; i += kBlock)
             gdst[i] = gsrc[i];
     }
-    const uint32_t *tab_p = s_tab, *tab_half = s_tab + kDevTableEntries;
-    const uint32_t *tab_rest = s_tab + 2 * kDevTableEntries;
-    const uint8_t *g_p = s_guide, *g_half = s_guide + kG, *g_rest = s_guide + 2 * kG;
     constexpr W kMax = (W)(T)~(T)0;
     W ovf = 0;
 
@@ -165,11 +165,10 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         if constexpr (EX) {
             static_assert(Q == 2, "the exchange form is defined for D1Q2");
             sampler::node_exchange<W, NB, GB, NR>(av, cn, x, sl.t0 + a.j, sl.realization, key0,
-                                                  key1, tab_p, g_p, sl.p_zero != 0);
+                                                  key1, tb, sl.p_zero != 0);
         } else {
             sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, sl.t0 + a.j, sl.realization, key0,
-                                                   key1, tab_p, g_p, tab_half, g_half, tab_rest,
-                                                   g_rest, sl.p_zero != 0);
+                                                   key1, tb, sl.p_zero != 0);
         }
         ovf |= sampler::or_all<Q, W>(cn);
         if constexpr (Q == 5) {

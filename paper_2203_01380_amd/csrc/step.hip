@@ -45,8 +45,13 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     uint32_t *s_tab = reinterpret_cast<uint32_t *>(s_lds);
     uint8_t *s_guide = s_lds + kTabBytes;
 
+    const uint32_t *tab_p = s_tab;
+    const uint32_t *tab_half = s_tab + kDevTableEntries;
+    const uint32_t *tab_rest = s_tab + 2 * kDevTableEntries;  // q = 3, 5 only
+    constexpr int kG = kChunk * kRowGuide;
+    const sampler::Tabs tb = sampler::make_tabs(tab_p, s_guide, kG);
     // Stage tables (16-byte copies) and the 2^GB-bucket view of the guides.
-    sampler::stage_row_offsets();
+    sampler::stage_row_offsets(tab_p, tab_half, tab_rest);
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.tables);
         uint4 *dst = reinterpret_cast<uint4 *>(s_tab);
@@ -68,13 +73,6 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
     }
     __syncthreads();
 
-    const uint32_t *tab_p = s_tab;
-    const uint32_t *tab_half = s_tab + kDevTableEntries;
-    const uint32_t *tab_rest = s_tab + 2 * kDevTableEntries;  // q = 3 only
-    constexpr int kG = kChunk * kRowGuide;
-    const uint8_t *g_p = s_guide;
-    const uint8_t *g_half = s_guide + kG;
-    const uint8_t *g_rest = s_guide + 2 * kG;
     const uint32_t L = a.length;
     const uint64_t pitch = a.pitch;
     const T *in = reinterpret_cast<const T *>(a.in);
@@ -118,11 +116,10 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
         if constexpr (EX) {
             static_assert(Q == 2, "the exchange form is defined for D1Q2");
             sampler::node_exchange<W, NB, GB, NR>(av, cn, x, a.t, a.realization, a.key0, a.key1,
-                                                  tab_p, g_p, PZ);
+                                                  tb, PZ);
         } else {
             sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, a.t, a.realization, a.key0, a.key1,
-                                                   tab_p, g_p, tab_half, g_half, tab_rest, g_rest,
-                                                   PZ);
+                                                   tb, PZ);
         }
         ovf |= sampler::or_all<Q, W>(cn);
         if constexpr (Q == 5) {
