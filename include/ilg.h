@@ -235,6 +235,32 @@ uint64_t ilg_current_step(const ilg_handle *h);
 int ilg_destroy(ilg_handle *h);
 
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the steps
+ * of ilg_step on caller-owned state buffers, with no handle.  The fixed-point
+ * table set the step kernel stages into LDS and the sticky error word live
+ * in a fixed device array of the library, ILG_NOALLOC_SCRATCH_BYTES on each
+ * device the library runs on, held until the process ends; its use does not
+ * grow with the lattice (nodes < 2^31, as ilg_create).
+ *   cfg: as ilg_create; cfg->t0 is the absolute index of the first step.
+ *   buf0, buf1: distinct device buffers of ilg_state_bytes(cfg) each in the
+ *     device layout; buf0 holds the state at t0 and both are rewritten; after
+ *     nsteps steps the state is in buf0 if nsteps is even, else in buf1.
+ *   stream: hipStream_t (NULL: the legacy default stream); the copy of the
+ *     call's tables and the steps are enqueued on it.
+ *   sync = 0: return after enqueueing (a count overflow stays recorded in the
+ *     error word); sync != 0: wait, then return ILG_E_OVERFLOW if a count
+ *     exceeded its type in this or an earlier call since the last report,
+ *     which clears the word.
+ * Calls no allocating routine.  Every call on one device shares its array
+ * and rewrites its tables: calls that overlap on one device (concurrent
+ * streams or threads) race.  Results equal ilg_create_on + ilg_step.
+ * ILG_E_INVALID / ILG_E_RANGE as ilg_create and ilg_step. */
+#define ILG_NOALLOC_SCRATCH_BYTES 76032u
+int ilg_step_noalloc(const ilg_config *cfg, void *buf0, void *buf1, uint64_t nsteps, void *stream,
+                     uint32_t sync);
+
+
 /* ------------------------------------------------------------------------
  * Batched ensembles: many independent realizations (the ensemble average of
  * the Integer Lattice Gas section), each with its own length, relaxation

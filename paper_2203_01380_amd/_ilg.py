@@ -127,6 +127,7 @@ def _load():
         "ilg_server_result": ([hp, u64, vp], i32),
         "ilg_server_cancel": ([hp, u64], i32),
         "ilg_server_destroy": ([hp], i32),
+        "ilg_step_noalloc": ([cfgp, vp, vp, u64, vp, u32], i32),
         "ilg_probe_stream": ([u32, u64, vp, vp, vp], i32),
         "ilg_probe_philox": ([u64, u32, u32, u32, u64, vp, vp], i32),
     }

@@ -20,6 +20,7 @@ LIB = os.path.join(HERE, "libilg.so")
 ARCH = os.environ.get("ILG_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["runtime.cpp", "tables.cpp", "batch_runtime.cpp", "scheduler.cpp", "serve_runtime.cpp",
+           "noalloc.cpp",
            "step.hip", "diag.hip", "batch.hip", "batch_p7.hip", "batch_ex.hip", "serve.hip", "init.hip",
            "probes.hip"]
 
