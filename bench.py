@@ -632,9 +632,12 @@ def main():
     # warm-up steps, back to back: after host-side set-up the GPU clock ramps
     # up over tens of launches (2.3 -> 2.5 GHz, profiles/
     # step_d1q3_u16_l2p24_clock_ramp.md), so the timed steps follow
-    # continuous GPU work as they would in a long run.
-    say("probes: streaming only, draws only")
-    probes = bench_probes(ilg, stream, args.warmup)
+    # continuous GPU work as they would in a long run.  Without the probes
+    # form the timed steps follow the upload directly.
+    probes = None
+    if "probes" in forms:
+        say("probes: streaming only, draws only")
+        probes = bench_probes(ilg, stream, args.warmup)
     say(f"warmup {args.warmup} steps")
     lat.step(args.warmup)
     say(f"timing {args.steps} steps")

@@ -514,17 +514,29 @@ __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Dra
         kv[2] = clamp_to(cc[3], rows[3]);
     }
     const W M = kv[0] + kv[1] + kv[2];
-    // Redistribution words start at 2 + D1; the fourth of them would be draw
-    // 8 (a third Philox block) when D1 = 3 and M > 128: left to the generic path.
-    if (wave_any(M > (W)(3 * kChunk) || (c3 && M > (W)(2 * kChunk))))
-        return false;
-    const uint32_t u[4] = {pick3(c2, c3, d.w[3], d.w[4], d.w[5]),
-                           pick3(c2, c3, d.w[4], d.w[5], d.w[6]),
-                           pick3(c2, c3, d.w[5], d.w[6], d.w[7]),
-                           pick3(c2, c3, d.w[6], d.w[7], 0u)};
     W mv[3];
-    if (!redistribute3<W, GB>(M, u, mv, tb))
-        return false;
+    if (!wave_any(M > (W)kChunk)) {
+        // the common case: m_1 and m_0 take one chunk each, at draws 2 + D1
+        // and 3 + D1 (for M = 0 neither consumes a word)
+        mv[1] = chunk_or_zero<kTidRest, GB>(tb.g_rest, (uint32_t)M,
+                                            pick3(c2, c3, d.w[3], d.w[4], d.w[5]));
+        const W R = M - mv[1];
+        mv[0] = chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)R,
+                                            pick3(c2, c3, d.w[4], d.w[5], d.w[6]));
+        mv[2] = R - mv[0];
+    } else {
+        // Redistribution words start at 2 + D1; the fourth of them would be
+        // draw 8 (a third Philox block) when D1 = 3 and M > 128: left to the
+        // generic path.
+        if (wave_any(M > (W)(3 * kChunk) || (c3 && M > (W)(2 * kChunk))))
+            return false;
+        const uint32_t u[4] = {pick3(c2, c3, d.w[3], d.w[4], d.w[5]),
+                               pick3(c2, c3, d.w[4], d.w[5], d.w[6]),
+                               pick3(c2, c3, d.w[5], d.w[6], d.w[7]),
+                               pick3(c2, c3, d.w[6], d.w[7], 0u)};
+        if (!redistribute3<W, GB>(M, u, mv, tb))
+            return false;
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i)
         c[i] = av[i] - kv[i] + mv[i];
@@ -674,26 +686,25 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
 {
     Draws<NB, NR> d;
     d.init(x, t, r, key0, key1);
-    // Common draw layout, decided once per wave for this node slot.  The
-    // per-lane tests are combined bitwise (no short-circuit branches) and
-    // read as lane masks: a count a lies in 1..n exactly when a - 1 < n as
-    // an unsigned number.
-    auto in_1_to = [](W a, uint32_t n) { return (uint32_t)(a - (W)1) < n; };
-    bool ok, two = false, three = false;
+    // Common draw layout, decided once per wave for this node slot, from
+    // lane masks of compares (no short-circuit branches): a count a lies in
+    // 1..n exactly when a - 1 < n as an unsigned number, and several counts
+    // lie in 1..64 exactly when the OR of their a - 1 is below 64.
+    auto m1 = [](W a) { return (uint32_t)(a - (W)1); };
+    auto ballot = [](bool p) { return __builtin_amdgcn_ballot_w64(p); };
+    const uint64_t lanes = ballot(true);
+    uint64_t ok_mask, two_mask = 0, three_mask = 0;
     if constexpr (Q == 2) {
-        ok = in_1_to(av[0], kChunk) & in_1_to(av[1], kChunk);
+        ok_mask = ballot((m1(av[0]) | m1(av[1])) < (uint32_t)kChunk);
     } else if constexpr (Q == 5) {
-        ok = in_1_to(av[0], kChunk) & in_1_to(av[1], kChunk) & in_1_to(av[2], 2 * kChunk) &
-             in_1_to(av[3], kChunk) & in_1_to(av[4], kChunk);
+        ok_mask = ballot((m1(av[0]) | m1(av[1]) | m1(av[3]) | m1(av[4])) < (uint32_t)kChunk) &
+                  ballot(m1(av[2]) < 2u * kChunk);
     } else {
-        ok = in_1_to(av[0], kChunk) & in_1_to(av[2], kChunk) & in_1_to(av[1], 3 * kChunk);
-        two = av[1] > (W)kChunk;
-        three = av[1] > (W)(2 * kChunk);
+        ok_mask = ballot((m1(av[0]) | m1(av[2])) < (uint32_t)kChunk) &
+                  ballot(m1(av[1]) < 3u * kChunk);
+        two_mask = ballot(av[1] > (W)kChunk);
+        three_mask = ballot(av[1] > (W)(2 * kChunk));
     }
-    const uint64_t lanes = __builtin_amdgcn_ballot_w64(true);
-    const uint64_t ok_mask = __builtin_amdgcn_ballot_w64(ok);
-    const uint64_t two_mask = __builtin_amdgcn_ballot_w64(two);
-    const uint64_t three_mask = __builtin_amdgcn_ballot_w64(three);
     bool done = false;
     if (ok_mask == lanes) {
         // Every count is at most three chunks here, so every intermediate and
