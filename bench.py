@@ -431,15 +431,14 @@ def bench_batched_decay(ilg, W, stream, steps: int):
 def bench_serving_saturated(ilg, W, stream, steps: int = 1000, nreq: int = 64):
     """Serving capacity: nreq requests of 2^20 nodes submitted at once (the
     first nreq requests of the stream's rates and seeds), all D1Q2, all D1Q3,
-    then mixed, against plain 2^22-node lattices stepped at the first 16 of
-    the same rates (the comparison the server's per-tile overhead is read
-    from)."""
+    then mixed, against plain 2^22-node lattices stepped at each of the same
+    rates (the comparison the server's per-tile overhead is read from)."""
     import torch
     base = W.request_stream(rate_per_s=200, duration_s=2.0)[:nreq]
     pool = W.RequestInitPool()
     out = {"workload": f"{nreq} requests of 2^20 nodes, uint16, Poisson(40), omega ~ U[1, 1.95], "
-                       f"{steps} steps each, submitted at once; plain: 16 lattices of 2^22 at "
-                       f"the same rates"}
+                       f"{steps} steps each, submitted at once; plain: one lattice of 2^22 at "
+                       f"each of the same rates"}
     for label, qfun in (("d1q2", lambda rq: 2), ("d1q3", lambda rq: 3),
                         ("mixed", lambda rq: rq.spec.q)):
         srv = ilg.Server(16 << 30, 100)
@@ -456,16 +455,22 @@ def bench_serving_saturated(ilg, W, stream, steps: int = 1000, nreq: int = 64):
         sec = time.perf_counter() - t0
         srv.close()
         out[label] = {"node_updates_per_s": len(base) * (1 << 20) * steps / sec, "seconds": sec}
+    # The plain form at every one of the same rates (the work per node
+    # depends strongly on the collision fraction), one 2^22-node lattice per
+    # rate, 100 timed steps each.
     for q in (2, 3):
         tot, work, L = 0.0, 0, 1 << 22
-        for i, rq in enumerate(base[:16]):
-            lat = ilg.Lattice(q, L, 2, rq.spec.omega, rq.spec.seed,
-                              W.init_poisson_iid(q, L, 40.0, 2, init_seed=5 + i))
-            lat.step(20)
-            tot += timed(stream, lambda: lat.step(300))
-            work += L * 300
+        init = W.init_poisson_iid(q, L, 40.0, 2, init_seed=5)
+        for i, rq in enumerate(base):
+            lat = ilg.Lattice(q, L, 2, rq.spec.omega, rq.spec.seed, init)
+            lat.step(10)
+            tot += timed(stream, lambda: lat.step(100))
+            work += L * 100
             lat.close()
-        out[f"plain_d1q{q}_same_rates"] = {"node_updates_per_s": work / tot}
+        out[f"plain_d1q{q}_same_rates"] = {"node_updates_per_s": work / tot,
+                                           "lattices": len(base), "length": L, "steps": 100}
+        out[f"serving_over_plain_d1q{q}"] = (out[f"d1q{q}"]["node_updates_per_s"] /
+                                             out[f"plain_d1q{q}_same_rates"]["node_updates_per_s"])
     return out
 
 

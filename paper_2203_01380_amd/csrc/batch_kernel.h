@@ -443,11 +443,11 @@ void batch_kernel(BatchArgs a)
                 }
                 if constexpr (EX) {
                     static_assert(Q == 2, "the exchange form is defined for D1Q2");
-                    sampler::node_exchange<W, NB, GB, NR>(av, cn, x, t, m.realization, m.key0,
-                                                          m.key1, tb, p_zero);
+                    sampler::node_exchange<W, NB, GB, NR>(av, cn, x, t, m.realization,
+                                                          PhiloxKey{m.key0, m.key1}, tb, p_zero);
                 } else {
-                    sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, t, m.realization, m.key0,
-                                                           m.key1, tb, p_zero);
+                    sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, t, m.realization,
+                                                           PhiloxKey{m.key0, m.key1}, tb, p_zero);
                 }
                 ovf |= sampler::or_all<Q, W>(cn);
                 if constexpr (Q == 5) {

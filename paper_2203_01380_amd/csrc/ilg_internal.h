@@ -178,17 +178,24 @@ hipError_t launch_batch_ex(int q, int count_bytes, int shape, const BatchArgs &a
                            hipStream_t stream);
 
 // ---------------------------------------------------------------- serving
-// One active request of the server: its buffer pair and table set in the
-// server's arena and its draw keys; steps is this quantum's advance.
+// One active request of the server in one launch group's quantum: where its
+// state and tables are and its draw keys, in the form the kernel uses them
+// directly (row addresses and round keys formed on the host, so that a tile
+// of the request costs only a few scalar loads).
 struct ServeSlot {
-    uint64_t state_off;    // element offset of buffer 0 (buffer 1 at q*pitch)
-    uint64_t table_off;    // byte offset of the slot's table set
-    uint32_t length, pitch;  // nodes (Lx Ly for D2Q5) and row pitch
-    uint32_t width;          // D2Q5: nodes per lattice row (Lx); 1D: L
-    uint32_t t0;           // absolute index of the quantum's first step
-    uint32_t steps;        // steps in this quantum
-    uint32_t realization, key0, key1;
-    uint32_t flip, p_zero, cur0;
+    // Row addresses for the quantum's step j, by j & 1 (the buffers swap every
+    // step): rows[j & 1][i], i < q, the rows read, with the flip applied
+    // (the row of index i holds n_{q-1-i} when the flip is on, and for D2Q5
+    // also the y pair swapped); rows[j & 1][5 + i] the rows written.
+    uint64_t rows[2][10];
+    uint32_t ka[10], kb[10];   // Philox round keys k0 + i W0, k1 + i W1
+    uint64_t table_off;        // byte offset of the slot's table set
+    uint32_t length;           // nodes (Lx Ly for D2Q5)
+    uint32_t width;            // D2Q5: nodes per lattice row (Lx); 1D: L
+    uint32_t t0;               // absolute index of the quantum's first step
+    uint32_t steps;            // steps in this quantum
+    uint32_t realization;
+    uint32_t p_zero;
     uint32_t tile_begin, tile_end;  // the slot's tiles in the launch's tile list
 };
 constexpr int kServeGuideBits = 8;
@@ -205,11 +212,15 @@ struct ServeArgs {
     void *arena;
     const ServeSlot *slots;      // in tile order: slot s owns tiles [tile_begin, tile_end)
     const uint32_t *tile_slot;   // slot of each tile
+    const uint32_t *wg_tiles;    // workgroup w walks tiles [wg_tiles[w], wg_tiles[w + 1])
     uint32_t ntiles;
+    uint32_t grid;               // workgroups of the launch
     uint32_t j;             // step index within the quantum
     const void *shared;     // half table then its guide
     uint32_t *slot_err;     // one sticky error word per slot (bit 0: overflow)
 };
+// Workgroups of a serving launch over ntiles tiles (two per CU at most).
+uint32_t serve_grid(uint32_t ntiles);
 
 hipError_t launch_serve(int q, int count_bytes, int rounds, bool exchange, const ServeArgs &a,
                         hipStream_t stream);

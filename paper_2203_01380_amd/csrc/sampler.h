@@ -74,18 +74,27 @@ __device__ __forceinline__ bool wave_any(bool p)
     return __builtin_amdgcn_ballot_w64(p) != 0ull;
 }
 
-template <int NB, int NR>
+// K: the key as two words (PhiloxKey) or with its round keys formed
+// beforehand (PhiloxSchedule); both give the same draws.
+template <int NB, int NR, typename K = PhiloxKey>
 struct Draws {
     uint32_t w[4 * NB];
-    uint32_t x, t, r, k0, k1;
+    uint32_t x, t, r;
+    K key;
 
-    __device__ __forceinline__ void init(uint32_t x_, uint32_t t_, uint32_t r_, uint32_t k0_,
-                                         uint32_t k1_)
+    __device__ __forceinline__ void init(uint32_t x_, uint32_t t_, uint32_t r_, const K &key_)
     {
-        x = x_; t = t_; r = r_; k0 = k0_; k1 = k1_;
+        x = x_; t = t_; r = r_; key = key_;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const uint4 o = philox4x32<NR>(x, t, r, (uint32_t)b, k0, k1);
+            // with a precomputed schedule (serving slots) the uniform words
+            // of the first rounds are per tile, so they are written for the
+            // scalar unit; elsewhere the compiler hoists them anyway
+            uint4 o;
+            if constexpr (std::is_same<K, PhiloxSchedule>::value)
+                o = philox4x32_x<NR>(x, t, r, (uint32_t)b, key);
+            else
+                o = philox4x32<NR>(x, t, r, (uint32_t)b, key);
             w[4 * b + 0] = o.x; w[4 * b + 1] = o.y; w[4 * b + 2] = o.z; w[4 * b + 3] = o.w;
         }
     }
@@ -108,8 +117,8 @@ __device__ __forceinline__ uint32_t pick3(bool c2, bool c3, uint32_t a, uint32_t
 }
 
 // Word j of the lane's draw stream (lanes may ask for different j).
-template <int NB, int NR>
-__device__ __forceinline__ uint32_t draw_word(const Draws<NB, NR> &d, uint32_t j)
+template <int NB, int NR, typename K>
+__device__ __forceinline__ uint32_t draw_word(const Draws<NB, NR, K> &d, uint32_t j)
 {
     constexpr uint32_t kEager = 4 * NB;
     const uint32_t j0 = __builtin_amdgcn_readfirstlane(j);
@@ -147,7 +156,7 @@ __device__ __forceinline__ uint32_t draw_word(const Draws<NB, NR> &d, uint32_t j
         }
         if (wave_any(j >= kEager)) {
             if (j >= kEager) {
-                const uint4 o = philox4x32<NR>(d.x, d.t, d.r, j >> 2, d.k0, d.k1);
+                const uint4 o = philox4x32<NR>(d.x, d.t, d.r, j >> 2, d.key);
                 r = pick4(o.x, o.y, o.z, o.w, j & 3u);
             }
         }
@@ -276,9 +285,9 @@ __device__ __forceinline__ uint32_t clamp_to(uint32_t c, uint32_t m)
 
 // Bin(n, table TID) with the chunked rule, consuming draws from index j on.
 // p_zero: the probability is 0 (draws are still consumed).
-template <int TID, typename W, int NB, int GB, int NR>
+template <int TID, typename W, int NB, int GB, int NR, typename K>
 __device__ __forceinline__ W binomial(W n, uint32_t &j, const uint8_t *guide, bool p_zero,
-                                      const Draws<NB, NR> &d)
+                                      const Draws<NB, NR, K> &d)
 {
     if (!wave_any(n > (W)kChunk)) {
         // at most one chunk per lane
@@ -390,8 +399,8 @@ __device__ __forceinline__ bool redistribute3(W M, const uint32_t (&u)[4], W (&m
 // extra chunks masked per lane.  Returns false (nothing written) if the
 // redistribution needs more, or m_0 of q = 3 more than one chunk; the caller
 // then takes the generic path from scratch.
-template <int Q, int D1, typename W, int NB, int GB, int NR>
-__device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Draws<NB, NR> &d,
+template <int Q, int D1, typename W, int NB, int GB, int NR, typename K>
+__device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Draws<NB, NR, K> &d,
                                           const Tabs &tb, bool p_zero)
 {
     W kv[Q];
@@ -482,8 +491,8 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
 // chunks of the middle binomial and the outer binomials are probed together.
 // The redistribution is as in node_fast.  Returns false (nothing written)
 // where node_fast would, or if a needed word lies beyond the eight computed.
-template <typename W, int NB, int GB, int NR>
-__device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Draws<NB, NR> &d,
+template <typename W, int NB, int GB, int NR, typename K>
+__device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Draws<NB, NR, K> &d,
                                           const Tabs &tb, bool p_zero)
 {
     static_assert(NB >= 2, "draws 0..6 must be computed up front");
@@ -569,8 +578,8 @@ __device__ __forceinline__ W or_all(const W (&c)[Q])
 // nothing to split).  The removal chunks are probed together, and so are
 // the two last splits.  Returns false (nothing written) if some lane has
 // M > 64.
-template <typename W, int NB, int GB, int NR>
-__device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Draws<NB, NR> &d,
+template <typename W, int NB, int GB, int NR, typename K>
+__device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Draws<NB, NR, K> &d,
                                            const Tabs &tb, bool p_zero)
 {
     static_assert(NB >= 3, "draws 0..9 must be computed up front");
@@ -642,8 +651,9 @@ template <> struct Wide<uint32_t> { using type = uint64_t; };
 // the post-collision counts.  NR: Philox rounds of the draws (10 or 7).
 // The generic path: every binomial chunk by chunk in the draw order, in
 // the arithmetic type WW (wide enough for every count, sum and result).
-template <int Q, typename WW, int NB, int GB, int NR>
-__device__ __forceinline__ void node_generic(const WW (&av)[Q], WW (&cn)[Q], Draws<NB, NR> &d,
+template <int Q, typename WW, int NB, int GB, int NR, typename K>
+__device__ __forceinline__ void node_generic(const WW (&av)[Q], WW (&cn)[Q],
+                                             const Draws<NB, NR, K> &d,
                                              const Tabs &tb, bool p_zero)
 {
     using W = WW;
@@ -679,13 +689,12 @@ __device__ __forceinline__ void node_generic(const WW (&av)[Q], WW (&cn)[Q], Dra
         cn[i] = av[i] - kv[i] + mv[i];
 }
 
-template <int Q, typename W, int NB, int GB, int NR = 10>
+template <int Q, typename W, int NB, int GB, int NR = 10, typename K = PhiloxKey>
 __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32_t x, uint32_t t,
-                                            uint32_t r, uint32_t key0, uint32_t key1,
-                                            const Tabs &tb, bool p_zero)
+                                            uint32_t r, const K &key, const Tabs &tb, bool p_zero)
 {
-    Draws<NB, NR> d;
-    d.init(x, t, r, key0, key1);
+    Draws<NB, NR, K> d;
+    d.init(x, t, r, key);
     // Common draw layout, decided once per wave for this node slot, from
     // lane masks of compares (no short-circuit branches): a count a lies in
     // 1..n exactly when a - 1 < n as an unsigned number, and several counts
@@ -760,13 +769,13 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
 // probability's table and guide).  When every lane has both counts in 1..64
 // the two draws are words 0 and 1, probed together; otherwise the generic
 // chunked binomials.
-template <typename W, int NB, int GB, int NR = 10>
+template <typename W, int NB, int GB, int NR = 10, typename K = PhiloxKey>
 __device__ __forceinline__ void node_exchange(const W (&av)[2], W (&cn)[2], uint32_t x, uint32_t t,
-                                              uint32_t r, uint32_t key0, uint32_t key1,
-                                              const Tabs &tb, bool p_zero)
+                                              uint32_t r, const K &key, const Tabs &tb,
+                                              bool p_zero)
 {
-    Draws<NB, NR> d;
-    d.init(x, t, r, key0, key1);
+    Draws<NB, NR, K> d;
+    d.init(x, t, r, key);
     const bool ok = av[0] >= 1 && av[0] <= (W)kChunk && av[1] >= 1 && av[1] <= (W)kChunk;
     W X, Y;
     if (!wave_any(!ok)) {

@@ -21,6 +21,22 @@ namespace {
 
 using sampler::Wide;
 
+// Element x of a velocity row given by its address in the descriptor, read
+// and written as global memory (a bare 64-bit address would make flat
+// accesses).  16-bit rows: 32-bit lane offset (fewer than 2^31 nodes).
+template <typename T>
+using GlobalT = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ GlobalT<T> *global_elem(uint64_t row, uint32_t x)
+{
+    using B = GlobalT<uint8_t>;
+    B *base = (B *)(uintptr_t)row;
+    if constexpr (sizeof(T) == 2)
+        return reinterpret_cast<GlobalT<T> *>(base + (uint32_t)(x * 2u));
+    else
+        return reinterpret_cast<GlobalT<T> *>(base) + x;
+}
+
 constexpr int kBlock = kServeTile;  // one node per thread per tile
 
 // The slot descriptors are read-only during a launch: read through the
@@ -29,28 +45,6 @@ using ConstSlot = const __attribute__((address_space(4))) ServeSlot;
 __device__ __forceinline__ ConstSlot *const_space(const ServeSlot *p)
 {
     return (ConstSlot *)p;
-}
-
-__device__ __forceinline__ ServeSlot read_slot(const ServeSlot *p)
-{
-    ConstSlot *q = const_space(p);
-    ServeSlot s;
-    s.state_off = q->state_off;
-    s.table_off = q->table_off;
-    s.length = q->length;
-    s.pitch = q->pitch;
-    s.width = q->width;
-    s.t0 = q->t0;
-    s.steps = q->steps;
-    s.realization = q->realization;
-    s.key0 = q->key0;
-    s.key1 = q->key1;
-    s.flip = q->flip;
-    s.p_zero = q->p_zero;
-    s.cur0 = q->cur0;
-    s.tile_begin = q->tile_begin;
-    s.tile_end = q->tile_end;
-    return s;
 }
 
 // NR: Philox rounds of the draws (10, or 7 for draw specification v2); EX:
@@ -91,14 +85,19 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
 
     __syncthreads();  // the shared half table is visible to every wave
 
-    const uint32_t lo = (uint32_t)((uint64_t)a.ntiles * blockIdx.x / gridDim.x);
-    const uint32_t hi = (uint32_t)((uint64_t)a.ntiles * (blockIdx.x + 1) / gridDim.x);
+    // The host splits the tile list into contiguous ranges of equal
+    // estimated work (the work per node grows with a slot's collision
+    // fraction), so a launch does not wait on the workgroups of its most
+    // expensive requests.
+    const uint32_t lo = a.wg_tiles[blockIdx.x];
+    const uint32_t hi = a.wg_tiles[blockIdx.x + 1];
     if (lo >= hi)
         return;
     // Only the slot index is carried from tile to tile: the descriptor is a
     // scalar-cache read with no dependence on a per-tile lookup.  (Carrying
     // the descriptor itself measured slower: the compiler keeps it in vector
-    // registers.)
+    // registers.)  The descriptor holds the rows' addresses and the round
+    // keys, so a tile reads them instead of forming them.
     uint32_t slot = __builtin_amdgcn_readfirstlane(a.tile_slot[lo]);  // uniform
     uint32_t staged = 0xFFFFFFFFu;
     for (uint32_t tile = lo; tile < hi; ++tile) {
@@ -111,15 +110,15 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
                 ++slot;
             while (tile >= const_space(a.slots)[slot].tile_end);
         }
-        const ServeSlot sl = read_slot(a.slots + slot);
-        if (a.j >= sl.steps)
+        ConstSlot *sl = const_space(a.slots) + slot;
+        if (a.j >= sl->steps)
             continue;
         if (slot != staged) {
             // Barriers only where the walk enters a new slot: before the
             // restage (readers of the previous slot's tables are done) and
             // after it (the new tables are visible).
             __syncthreads();
-            const uint8_t *set = reinterpret_cast<const uint8_t *>(a.arena) + sl.table_off;
+            const uint8_t *set = reinterpret_cast<const uint8_t *>(a.arena) + sl->table_off;
             const int nt = (Q == 2) ? 1 : 2;  // removal (+ rest) tables
             for (int t = 0; t < nt; ++t) {
                 const uint4 *src = reinterpret_cast<const uint4 *>(set + t * kServeTableBytes);
@@ -135,59 +134,52 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
             staged = slot;
             __syncthreads();
         }
-        const uint32_t x = (tile - sl.tile_begin) * (uint32_t)kBlock + threadIdx.x;
-        const uint32_t L = sl.length;
+        const uint32_t x0 = (tile - sl->tile_begin) * (uint32_t)kBlock;  // uniform
+        const uint32_t x = x0 + threadIdx.x;
+        const uint32_t L = sl->length;
         if (x >= L)
             continue;
-        const uint64_t pitch = sl.pitch, qp = (uint64_t)Q * sl.pitch;
-        const uint32_t cur = sl.cur0 ^ (a.j & 1u);
-        const T *in = reinterpret_cast<const T *>(a.arena) + sl.state_off + cur * qp;
-        T *out = reinterpret_cast<T *>(a.arena) + sl.state_off + (cur ^ 1u) * qp;
-        // Flipped loads (a_i = n_{q-1-i}) by swapping the outer row pointers,
-        // a scalar choice per slot.
-        const uint64_t outer = (uint64_t)(Q - 1) * pitch;
-        const T *row_lo = in + (sl.flip ? outer : 0), *row_hi = in + (sl.flip ? 0 : outer);
+        // Row addresses of this step's buffers (flip applied on the host).
+        const uint32_t par = a.j & 1u;
+        uint64_t out_row[Q];
         W av[Q], cn[Q];
-        av[0] = (W)*sampler::row_elem(row_lo, x);
-        av[Q - 1] = (W)*sampler::row_elem(row_hi, x);
-        if constexpr (Q == 3)
-            av[1] = (W)*sampler::row_elem(in + pitch, x);
-        if constexpr (Q == 5) {
-            // the flip also swaps the y pair (rows 1 and 3)
-            av[1] = (W)*sampler::row_elem(in + (sl.flip ? 3 : 1) * pitch, x);
-            av[2] = (W)*sampler::row_elem(in + 2 * pitch, x);
-            av[3] = (W)*sampler::row_elem(in + (sl.flip ? 1 : 3) * pitch, x);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            av[i] = (W)*global_elem<T>(sl->rows[par][i], x);
+            out_row[i] = sl->rows[par][5 + i];
         }
-        // The key words are uniform; saying so keeps their round schedule in
-        // scalar registers (as operands of the Philox xors).
-        const uint32_t key0 = __builtin_amdgcn_readfirstlane(sl.key0);
-        const uint32_t key1 = __builtin_amdgcn_readfirstlane(sl.key1);
+        PhiloxSchedule key;
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            key.ka[i] = sl->ka[i];
+            key.kb[i] = sl->kb[i];
+        }
+        const uint32_t t = sl->t0 + a.j;
         if constexpr (EX) {
             static_assert(Q == 2, "the exchange form is defined for D1Q2");
-            sampler::node_exchange<W, NB, GB, NR>(av, cn, x, sl.t0 + a.j, sl.realization, key0,
-                                                  key1, tb, sl.p_zero != 0);
+            sampler::node_exchange<W, NB, GB, NR>(av, cn, x, t, sl->realization, key, tb,
+                                                  sl->p_zero != 0);
         } else {
-            sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, sl.t0 + a.j, sl.realization, key0,
-                                                   key1, tb, sl.p_zero != 0);
+            sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, t, sl->realization, key, tb,
+                                                   sl->p_zero != 0);
         }
         ovf |= sampler::or_all<Q, W>(cn);
         if constexpr (Q == 5) {
             // D2Q5 on the node index x + Lx y: -x, -y, rest, +y, +x
             uint32_t dxm, dym, dyp, dxp;
-            sampler::d2q5_neighbours<kBlock>(x, (tile - sl.tile_begin) * (uint32_t)kBlock,
-                                             sl.width, L, dxm, dym, dyp, dxp);
-            *sampler::row_elem(out, dxm) = (T)cn[0];
-            *sampler::row_elem(out + pitch, dym) = (T)cn[1];
-            *sampler::row_elem(out + 2 * pitch, x) = (T)cn[2];
-            *sampler::row_elem(out + 3 * pitch, dyp) = (T)cn[3];
-            *sampler::row_elem(out + 4 * pitch, dxp) = (T)cn[4];
+            sampler::d2q5_neighbours<kBlock>(x, x0, sl->width, L, dxm, dym, dyp, dxp);
+            *global_elem<T>(out_row[0], dxm) = (T)cn[0];
+            *global_elem<T>(out_row[1], dym) = (T)cn[1];
+            *global_elem<T>(out_row[2], x) = (T)cn[2];
+            *global_elem<T>(out_row[3], dyp) = (T)cn[3];
+            *global_elem<T>(out_row[4], dxp) = (T)cn[4];
         } else {
             const uint32_t xm = (x == 0) ? L - 1 : x - 1;
             const uint32_t xp = (x + 1 == L) ? 0 : x + 1;
-            *sampler::row_elem(out, xm) = (T)cn[0];
-            *sampler::row_elem(out + (uint64_t)(Q - 1) * pitch, xp) = (T)cn[Q - 1];
+            *global_elem<T>(out_row[0], xm) = (T)cn[0];
+            *global_elem<T>(out_row[Q - 1], xp) = (T)cn[Q - 1];
             if constexpr (Q == 3)
-                *sampler::row_elem(out + pitch, x) = (T)cn[1];
+                *global_elem<T>(out_row[1], x) = (T)cn[1];
         }
     }
     if (ovf > kMax)
@@ -197,13 +189,9 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
 template <int Q, typename T, int NR, bool EX>
 hipError_t launch_qt(const ServeArgs &a, hipStream_t stream)
 {
-    const uint32_t cus = (uint32_t)device_cu_count();
-    uint32_t grid = cus * 2;  // two 1024-thread workgroups per CU
-    if (grid > a.ntiles)
-        grid = a.ntiles;
-    if (grid == 0)
+    if (a.grid == 0)
         return hipSuccess;
-    hipLaunchKernelGGL((serve_kernel<Q, T, NR, EX>), dim3(grid), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL((serve_kernel<Q, T, NR, EX>), dim3(a.grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -228,6 +216,12 @@ hipError_t launch_spec(int q, int count_bytes, const ServeArgs &a, hipStream_t s
 }
 
 }  // namespace
+
+uint32_t serve_grid(uint32_t ntiles)
+{
+    const uint32_t grid = (uint32_t)device_cu_count() * 2;  // two 1024-thread workgroups per CU
+    return grid < ntiles ? grid : ntiles;
+}
 
 hipError_t launch_serve(int q, int count_bytes, int rounds, bool exchange, const ServeArgs &a,
                         hipStream_t stream)

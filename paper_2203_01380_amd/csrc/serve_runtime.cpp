@@ -16,6 +16,7 @@
 
 #include "ilg.h"
 #include "ilg_internal.h"
+#include "philox.h"
 #include "scheduler.h"
 
 namespace {
@@ -97,7 +98,7 @@ public:
     hipStream_t streams[kGroups] = {};
     ilg::ServeSlot *d_slots[kGroups] = {};
     uint32_t *d_err[kGroups] = {};    // error word of each slot of the last launch
-    uint32_t *d_tiles[kGroups] = {};  // slot of each tile
+    uint32_t *d_tiles[kGroups] = {};  // slot of each tile, then the workgroup ranges
     size_t cap_slots[kGroups] = {}, cap_tiles[kGroups] = {};
     hipStream_t io = nullptr;  // copies in and out
 
@@ -205,7 +206,8 @@ public:
     // Host copies of the last launch's slot and tile lists (kept alive until
     // the copies from them have completed).
     std::vector<ilg::ServeSlot> h_slots[kGroups];
-    std::vector<uint32_t> h_tiles[kGroups];
+    std::vector<uint32_t> h_tiles[kGroups];   // slot of each tile, then wg ranges
+    std::vector<double> h_weight[kGroups];     // estimated work of each tile
     std::vector<uint32_t> h_err[kGroups];
     std::vector<Req *> launched;
     std::vector<uint32_t> launched_steps;
@@ -218,6 +220,7 @@ public:
         for (int g = 0; g < kGroups; ++g) {
             slots[g].clear();
             tiles[g].clear();
+            h_weight[g].clear();
         }
         launched = active;
         launched_steps = steps;
@@ -230,19 +233,32 @@ public:
             const int g = group(c.q, c.count_bytes, p->fx);
             ilg::ServeSlot s;
             std::memset(&s, 0, sizeof(s));
-            s.state_off = r.mem_off / c.count_bytes;
+            // rows of both buffers: buffer b starts at the request's block
+            // plus b q pitch counts; step j reads buffer cur ^ (j & 1)
+            const uint64_t pitch = pitch_of(nodes_of(c)), cb = c.count_bytes;
+            const uint64_t base = reinterpret_cast<uint64_t>(arena) + r.mem_off;
+            for (uint32_t par = 0; par < 2; ++par) {
+                const uint64_t in = base + (uint64_t)(p->cur ^ par) * c.q * pitch * cb;
+                const uint64_t out = base + (uint64_t)(p->cur ^ par ^ 1u) * c.q * pitch * cb;
+                for (uint32_t i = 0; i < c.q; ++i) {
+                    // a_i = n_{q-1-i} under the flip (Eq. flip)
+                    const uint32_t src = p->fx.flip ? c.q - 1 - i : i;
+                    s.rows[par][i] = in + (uint64_t)src * pitch * cb;
+                    s.rows[par][5 + i] = out + (uint64_t)i * pitch * cb;
+                }
+            }
+            const uint32_t k0 = (uint32_t)(c.seed & 0xFFFFFFFFu), k1 = (uint32_t)(c.seed >> 32);
+            for (uint32_t k = 0; k < 10; ++k) {
+                s.ka[k] = k0 + k * ilg::kPhiloxW0;
+                s.kb[k] = k1 + k * ilg::kPhiloxW1;
+            }
             s.table_off = r.mem_off + state_bytes(c);
             s.length = (uint32_t)nodes_of(c);
             s.width = (uint32_t)c.length;
-            s.pitch = (uint32_t)pitch_of(nodes_of(c));
             s.t0 = (uint32_t)p->t;
             s.steps = steps[i];
             s.realization = c.realization;
-            s.key0 = (uint32_t)(c.seed & 0xFFFFFFFFu);
-            s.key1 = (uint32_t)(c.seed >> 32);
-            s.flip = (uint32_t)p->fx.flip;
             s.p_zero = p->fx.p == 0 ? 1u : 0u;
-            s.cur0 = p->cur;
             const uint32_t idx = (uint32_t)slots[g].size();
             launched_slot.emplace_back(g, idx);
             const uint32_t nt = (uint32_t)((nodes_of(c) + ilg::kServeTile - 1) / ilg::kServeTile);
@@ -250,6 +266,16 @@ public:
             s.tile_end = s.tile_begin + nt;
             slots[g].push_back(s);
             tiles[g].insert(tiles[g].end(), nt, idx);
+            // Work estimate of a tile: its nodes times 1 + omega*, the
+            // measured growth of the step's cost with the collision fraction
+            // (more collided particles, larger redistribution binomials).
+            const double w = 1.0 + p->fx.omega_star;
+            const uint64_t n = nodes_of(c);
+            for (uint32_t k = 0; k < nt; ++k) {
+                const uint64_t first = (uint64_t)k * ilg::kServeTile;
+                const uint64_t cnt = std::min<uint64_t>(ilg::kServeTile, n - first);
+                h_weight[g].push_back(w * (double)cnt);
+            }
             maxsteps[g] = std::max(maxsteps[g], steps[i]);
         }
         for (int g = 0; g < kGroups; ++g) {
@@ -257,6 +283,22 @@ public:
                 continue;
             if (!streams[g])
                 SHIP(hipStreamCreateWithFlags(&streams[g], hipStreamNonBlocking));
+            // contiguous tile ranges of equal estimated work, one per workgroup
+            const uint32_t ntiles = (uint32_t)tiles[g].size();
+            const uint32_t grid = ilg::serve_grid(ntiles);
+            double total = 0.0;
+            for (double w : h_weight[g])
+                total += w;
+            tiles[g].push_back(0);
+            double acc = 0.0;
+            uint32_t t = 0;
+            for (uint32_t b = 1; b < grid; ++b) {
+                const double target = total * b / grid;
+                while (t < ntiles && acc + 0.5 * h_weight[g][t] < target)
+                    acc += h_weight[g][t++];
+                tiles[g].push_back(t);
+            }
+            tiles[g].push_back(ntiles);
             int rc = ensure(g, slots[g].size(), tiles[g].size());
             if (rc != ILG_OK)
                 return rc;
@@ -269,7 +311,9 @@ public:
             a.arena = arena;
             a.slots = d_slots[g];
             a.tile_slot = d_tiles[g];
-            a.ntiles = (uint32_t)tiles[g].size();
+            a.wg_tiles = d_tiles[g] + ntiles;
+            a.ntiles = ntiles;
+            a.grid = grid;
             a.shared = shared;
             a.slot_err = d_err[g];
             const int q = g >= 16 ? 5 : (g & 8) ? 3 : 2, cb = (g & 4) ? 4 : 2;

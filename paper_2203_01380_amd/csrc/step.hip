@@ -115,11 +115,11 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
             av[i] = FLIP ? n[Q - 1 - i] : n[i];
         if constexpr (EX) {
             static_assert(Q == 2, "the exchange form is defined for D1Q2");
-            sampler::node_exchange<W, NB, GB, NR>(av, cn, x, a.t, a.realization, a.key0, a.key1,
-                                                  tb, PZ);
+            sampler::node_exchange<W, NB, GB, NR>(av, cn, x, a.t, a.realization,
+                                                  PhiloxKey{a.key0, a.key1}, tb, PZ);
         } else {
-            sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, a.t, a.realization, a.key0, a.key1,
-                                                   tb, PZ);
+            sampler::node_update<Q, W, NB, GB, NR>(av, cn, x, a.t, a.realization,
+                                                   PhiloxKey{a.key0, a.key1}, tb, PZ);
         }
         ovf |= sampler::or_all<Q, W>(cn);
         if constexpr (Q == 5) {
