@@ -363,8 +363,25 @@ typedef struct ilg_poll_info {
 double ilg_server_clock(void);
 
 /* Server owning a device arena of budget_bytes; every poll advances active
- * requests by up to quantum_steps steps. */
+ * requests by up to quantum_steps steps (small requests by up to 16 quanta,
+ * see ilg_server_set_resident). */
 int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server **out);
+
+#define ILG_RESIDENT_DEFAULT_NODES 4096u
+#define ILG_RESIDENT_MAX_NODES 65536u
+/* Small requests: those of at most max_nodes nodes (default
+ * ILG_RESIDENT_DEFAULT_NODES; 0: none; ILG_E_INVALID above
+ * ILG_RESIDENT_MAX_NODES) are advanced by a workgroup of their own in each
+ * step launch, with a workgroup barrier per step, by as many steps per
+ * launch as fit in the time of the launch's work on the other requests, and
+ * by up to max_steps steps per poll (at least the quantum; default 16
+ * quanta).  A small request's steps then do not each wait for a launch, so
+ * its latency falls; the request is accounted with the steps it took.  At
+ * most 128 small requests per launch group are resident; the others are
+ * advanced like large ones.  Results do not depend on this setting (every
+ * step is the same map with the same draws).  Takes effect from the next
+ * poll. */
+int ilg_server_set_resident(ilg_server *s, uint64_t max_nodes, uint32_t max_steps);
 
 /* Scheduling policy of the polls that follow.  max_nodes = 0 (the default):
  * every poll advances every active request.  max_nodes > 0: a poll advances

@@ -119,6 +119,7 @@ def _load():
         "ilg_server_clock": ([], ctypes.c_double),
         "ilg_server_create": ([u64, u32, ctypes.POINTER(hp)], i32),
         "ilg_server_set_step_nodes": ([hp, u64], i32),
+        "ilg_server_set_resident": ([hp, u64, u32], i32),
         "ilg_server_submit": ([hp, cfgp, vp, u64, ctypes.POINTER(u64)], i32),
         "ilg_server_submit_poisson_sine": ([hp, cfgp, ctypes.c_double, ctypes.c_double, u64, u64,
                                             ctypes.POINTER(u64)], i32),
@@ -402,12 +403,23 @@ REQ_STATES = {0: "queued", 1: "active", 2: "done", 3: "cancelled", 4: "failed"}
 class Server:
     """Continuous-batching request server (ilg_server_*)."""
 
-    def __init__(self, budget_bytes: int, quantum_steps: int = 100, step_nodes: int = 0):
+    def __init__(self, budget_bytes: int, quantum_steps: int = 100, step_nodes: int = 0,
+                 resident: Optional[tuple] = None):
+        """resident: (max_nodes, max_steps) for ilg_server_set_resident, or
+        None for the library's default (small requests of up to 4096 nodes,
+        up to 16 quanta per poll)."""
         self._h = ctypes.c_void_p()
         check(lib.ilg_server_create(budget_bytes, quantum_steps, ctypes.byref(self._h)))
         if step_nodes:
             self.set_step_nodes(step_nodes)
+        if resident is not None:
+            self.set_resident(*resident)
         self._shapes = {}
+
+    def set_resident(self, max_nodes: int, max_steps: int = 0):
+        """Requests of at most max_nodes nodes advance inside one workgroup,
+        by up to max_steps steps per poll (at least the quantum); 0: none."""
+        check(lib.ilg_server_set_resident(self._h, max_nodes, max_steps))
 
     def set_step_nodes(self, max_nodes: int):
         """Advance at most max_nodes nodes per quantum, least remaining work

@@ -197,6 +197,10 @@ struct ServeSlot {
     uint32_t realization;
     uint32_t p_zero;
     uint32_t tile_begin, tile_end;  // the slot's tiles in the launch's tile list
+    // Resident slot (a small request advanced by its own workgroup): steps
+    // per launch; launch j takes steps [j per_launch, (j + 1) per_launch)
+    // of the `steps`.  0 for a slot of the tile walk.
+    uint32_t per_launch;
 };
 constexpr int kServeGuideBits = 8;
 constexpr int kServeTile = 1024;  // nodes per tile (one workgroup pass)
@@ -213,16 +217,26 @@ struct ServeArgs {
     const ServeSlot *slots;      // in tile order: slot s owns tiles [tile_begin, tile_end)
     const uint32_t *tile_slot;   // slot of each tile
     const uint32_t *wg_tiles;    // workgroup w walks tiles [wg_tiles[w], wg_tiles[w + 1])
+    const uint32_t *wg_slot;     // slot of tile wg_tiles[w]
     uint32_t ntiles;
     uint32_t grid;               // workgroups of the launch
     uint32_t j;             // step index within the quantum
     const void *shared;     // half table then its guide
     uint32_t *slot_err;     // one sticky error word per slot (bit 0: overflow)
+    // Workgroups grid .. grid + nres - 1 each advance one resident slot,
+    // slots res_first .. res_first + nres - 1.
+    uint32_t nres;
+    uint32_t res_first;
 };
-// Workgroups of a serving launch over ntiles tiles (two per CU at most).
-uint32_t serve_grid(uint32_t ntiles);
+// Most resident slots in one launch.
+constexpr uint32_t kResidentMaxWg = 128;
+// Workgroups of the tile walk of a serving launch over ntiles tiles: two per
+// CU at most, less `reserved` for the launch's resident slots (at least one
+// per CU).
+uint32_t serve_grid(uint32_t ntiles, uint32_t reserved);
 
 hipError_t launch_serve(int q, int count_bytes, int rounds, bool exchange, const ServeArgs &a,
                         hipStream_t stream);
+
 
 }  // namespace ilg

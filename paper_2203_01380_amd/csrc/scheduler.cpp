@@ -92,7 +92,7 @@ int Scheduler::settle(Executor &ex, double (*clock)(), uint32_t *finished, uint3
 {
     uint32_t nfin = 0, nfail = 0;
     if (!inflight_.empty()) {
-        int rc = ex.wait();
+        int rc = ex.wait(&inflight_steps_);
         const double now = clock();
         for (size_t i = 0; i < inflight_.size() && rc == 0; ++i) {
             Req *r = inflight_[i];
@@ -209,7 +209,8 @@ int Scheduler::poll(Executor &ex, PollStats *st, double (*clock)())
         inflight_steps_.resize(inflight_.size());
         for (size_t i = 0; i < inflight_.size(); ++i) {
             const uint64_t left = inflight_[i]->total - inflight_[i]->done;
-            inflight_steps_[i] = (uint32_t)std::min<uint64_t>(left, quantum_);
+            const uint32_t cap = resident(*inflight_[i]) ? resident_steps_ : quantum_;
+            inflight_steps_[i] = (uint32_t)std::min<uint64_t>(left, cap);
             s.quantum_steps = std::max(s.quantum_steps, inflight_steps_[i]);
         }
         rc = ex.launch(inflight_, inflight_steps_);

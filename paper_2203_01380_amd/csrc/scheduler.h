@@ -11,9 +11,14 @@
 // fit the cap together, at least one: shortest-remaining-work first, which
 // shortens the typical latency while the device is near saturation, since
 // every launch advances its requests by one step and costs time in
-// proportion to the nodes it holds.  It returns while the device works, so
-// the caller's host work overlaps the quantum.  The executor does the device work; the scheduler only
-// does bookkeeping, so it is tested on the CPU with a counting executor.
+// proportion to the nodes it holds.  Small requests (set_resident) are
+// planned up to a longer step count per poll: the executor advances each of
+// them inside one workgroup, several steps per launch, and may take fewer
+// steps than planned (at least one), reporting the steps it took.  It
+// returns while the device
+// works, so the caller's host work overlaps the quantum.  The executor does
+// the device work; the scheduler only does bookkeeping, so it is tested on
+// the CPU with a counting executor.
 #pragma once
 
 #include <cstdint>
@@ -73,9 +78,12 @@ public:
     // work is done).
     virtual int launch(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) = 0;
     // Wait for the work of the last launch and account for it; sets failed on
-    // each launched request whose own work reported an error.  A nonzero
-    // return is a failure of the device (every launched request is then lost).
-    virtual int wait() = 0;
+    // each launched request whose own work reported an error.  `steps` holds
+    // the steps launched per request (the order of the launch); the executor
+    // lowers an entry, to no less than 1, where that request's advance ended
+    // early.  A nonzero return is a failure of the device (every launched
+    // request is then lost).
+    virtual int wait(std::vector<uint32_t> *steps) = 0;
     // Copy a finished request's final state out of the device.
     virtual int unload(Req &r) = 0;
 };
@@ -111,6 +119,16 @@ public:
     size_t active() const { return active_.size(); }
     // At most this many nodes advanced per quantum (0: every active request).
     void set_step_nodes(uint64_t nodes) { step_nodes_ = nodes; }
+    // Requests of at most max_nodes nodes are advanced by up to max_steps
+    // steps per poll (at least the quantum) instead of the quantum; 0 nodes:
+    // none.
+    void set_resident(uint64_t max_nodes, uint32_t max_steps)
+    {
+        resident_nodes_ = max_nodes;
+        resident_steps_ = max_steps > quantum_ ? max_steps : quantum_;
+    }
+    bool resident(const Req &r) const { return r.nodes != 0 && r.nodes <= resident_nodes_; }
+    uint64_t resident_nodes() const { return resident_nodes_; }
 
 private:
     int admit(Executor &ex, double (*clock)(), uint32_t *admitted, uint32_t *failed);
@@ -120,6 +138,8 @@ private:
     uint64_t budget_;
     uint32_t quantum_;
     uint64_t step_nodes_ = 0;
+    uint64_t resident_nodes_ = 0;
+    uint32_t resident_steps_ = 0;
     Arena arena_;
     uint64_t next_id_ = 1;
     std::deque<Req *> queue_;

@@ -5,6 +5,9 @@
 // quantum with the multi-slot step kernel (one launch per step and per
 // (q, count type, draw specification) group, groups on their own streams so
 // their work overlaps), and copies finished states back to host memory.
+// Small requests are resident slots of those launches: each has a workgroup
+// of its own that advances it by as many steps per launch as fit in the time
+// of the launch's tile walk.
 // Every slot of a launch has its own error word, so a request whose counts
 // overflow is retired alone (ILG_REQ_FAILED) and the others go on.
 #include <algorithm>
@@ -98,9 +101,13 @@ public:
     hipStream_t streams[kGroups] = {};
     ilg::ServeSlot *d_slots[kGroups] = {};
     uint32_t *d_err[kGroups] = {};    // error word of each slot of the last launch
-    uint32_t *d_tiles[kGroups] = {};  // slot of each tile, then the workgroup ranges
+    uint32_t *d_tiles[kGroups] = {};  // as h_tiles
     size_t cap_slots[kGroups] = {}, cap_tiles[kGroups] = {};
     hipStream_t io = nullptr;  // copies in and out
+    // Small requests (at most resident_nodes nodes, 0: none) are advanced
+    // as resident slots, several steps per launch; quantum: the scheduler's.
+    uint64_t resident_nodes = 0;
+    uint32_t quantum = 1;
 
     static int group(uint32_t q, uint32_t cb, const ilg::Fixed &fx)
     {
@@ -206,17 +213,82 @@ public:
     // Host copies of the last launch's slot and tile lists (kept alive until
     // the copies from them have completed).
     std::vector<ilg::ServeSlot> h_slots[kGroups];
-    std::vector<uint32_t> h_tiles[kGroups];   // slot of each tile, then wg ranges
+    // slot of each tile, then the workgroups' tile ranges, then the slot of
+    // each workgroup's first tile
+    std::vector<uint32_t> h_tiles[kGroups];
     std::vector<double> h_weight[kGroups];     // estimated work of each tile
     std::vector<uint32_t> h_err[kGroups];
     std::vector<Req *> launched;
-    std::vector<uint32_t> launched_steps;
+    std::vector<uint32_t> launched_steps;  // planned by the scheduler
+    std::vector<uint32_t> taken_steps;     // what the launches take (resident: may be fewer)
     std::vector<std::pair<int, uint32_t>> launched_slot;  // (group, slot) of launched[i]
+
+    // Descriptor of request r for an advance of `steps` steps from its
+    // current state.
+    ilg::ServeSlot make_slot(const Req &r, const Payload *p, uint32_t steps) const
+    {
+        const ilg_config &c = p->cfg;
+        ilg::ServeSlot s;
+        std::memset(&s, 0, sizeof(s));
+        // rows of both buffers: buffer b starts at the request's block plus
+        // b q pitch counts; step j reads buffer cur ^ (j & 1)
+        const uint64_t pitch = pitch_of(nodes_of(c)), cb = c.count_bytes;
+        const uint64_t base = reinterpret_cast<uint64_t>(arena) + r.mem_off;
+        for (uint32_t par = 0; par < 2; ++par) {
+            const uint64_t in = base + (uint64_t)(p->cur ^ par) * c.q * pitch * cb;
+            const uint64_t out = base + (uint64_t)(p->cur ^ par ^ 1u) * c.q * pitch * cb;
+            for (uint32_t i = 0; i < c.q; ++i) {
+                // a_i = n_{q-1-i} under the flip (Eq. flip)
+                const uint32_t src = p->fx.flip ? c.q - 1 - i : i;
+                s.rows[par][i] = in + (uint64_t)src * pitch * cb;
+                s.rows[par][5 + i] = out + (uint64_t)i * pitch * cb;
+            }
+        }
+        const uint32_t k0 = (uint32_t)(c.seed & 0xFFFFFFFFu), k1 = (uint32_t)(c.seed >> 32);
+        for (uint32_t k = 0; k < 10; ++k) {
+            s.ka[k] = k0 + k * ilg::kPhiloxW0;
+            s.kb[k] = k1 + k * ilg::kPhiloxW1;
+        }
+        s.table_off = r.mem_off + state_bytes(c);
+        s.length = (uint32_t)nodes_of(c);
+        s.width = (uint32_t)c.length;
+        s.t0 = (uint32_t)p->t;
+        s.steps = steps;
+        s.realization = c.realization;
+        s.p_zero = p->fx.p == 0 ? 1u : 0u;
+        return s;
+    }
+
+    static void spec_of(int g, int *q, int *cb, int *rounds, bool *exchange)
+    {
+        *q = g >= 16 ? 5 : (g & 8) ? 3 : 2;
+        *cb = (g & 4) ? 4 : 2;
+        *rounds = (g & 2) ? 7 : 10;
+        *exchange = (g & 1) != 0;
+    }
+
+    // Cost model of a launch, in units of one full tile of the tile walk at
+    // omega* = 0 (about 2 us): a tile costs 1 + omega* (more collided
+    // particles, larger redistribution binomials; a partial tile about as
+    // much as a full one, its waves being latency bound), and a workgroup
+    // entering a slot pays about half a tile to stage the slot's tables.  A
+    // resident step of a request of n tiles costs n (1 + omega*) plus half a
+    // tile (the step's barrier and latency-bound waves).  A launch also
+    // spends about 4 units beyond its busiest workgroup's tiles (the gap
+    // between launches, the shared table's staging, the tail), which a
+    // resident workgroup can use.
+    static constexpr double kStage = 0.5, kResidentStep = 0.5, kLaunch = 4.0;
 
     int launch(const std::vector<Req *> &active, const std::vector<uint32_t> &steps) override
     {
         std::vector<ilg::ServeSlot> *slots = h_slots;
         std::vector<uint32_t> *tiles = h_tiles;
+        struct Res {
+            size_t i;
+            ilg::ServeSlot s;
+            double w;  // cost of one step
+        };
+        std::vector<Res> res[kGroups];
         for (int g = 0; g < kGroups; ++g) {
             slots[g].clear();
             tiles[g].clear();
@@ -224,81 +296,108 @@ public:
         }
         launched = active;
         launched_steps = steps;
-        launched_slot.clear();
+        taken_steps = steps;
+        launched_slot.assign(active.size(), {0, 0});
         uint32_t maxsteps[kGroups] = {};
         for (size_t i = 0; i < active.size(); ++i) {
             Req &r = *active[i];
             Payload *p = payload_of(r);
             const ilg_config &c = p->cfg;
             const int g = group(c.q, c.count_bytes, p->fx);
-            ilg::ServeSlot s;
-            std::memset(&s, 0, sizeof(s));
-            // rows of both buffers: buffer b starts at the request's block
-            // plus b q pitch counts; step j reads buffer cur ^ (j & 1)
-            const uint64_t pitch = pitch_of(nodes_of(c)), cb = c.count_bytes;
-            const uint64_t base = reinterpret_cast<uint64_t>(arena) + r.mem_off;
-            for (uint32_t par = 0; par < 2; ++par) {
-                const uint64_t in = base + (uint64_t)(p->cur ^ par) * c.q * pitch * cb;
-                const uint64_t out = base + (uint64_t)(p->cur ^ par ^ 1u) * c.q * pitch * cb;
-                for (uint32_t i = 0; i < c.q; ++i) {
-                    // a_i = n_{q-1-i} under the flip (Eq. flip)
-                    const uint32_t src = p->fx.flip ? c.q - 1 - i : i;
-                    s.rows[par][i] = in + (uint64_t)src * pitch * cb;
-                    s.rows[par][5 + i] = out + (uint64_t)i * pitch * cb;
-                }
-            }
-            const uint32_t k0 = (uint32_t)(c.seed & 0xFFFFFFFFu), k1 = (uint32_t)(c.seed >> 32);
-            for (uint32_t k = 0; k < 10; ++k) {
-                s.ka[k] = k0 + k * ilg::kPhiloxW0;
-                s.kb[k] = k1 + k * ilg::kPhiloxW1;
-            }
-            s.table_off = r.mem_off + state_bytes(c);
-            s.length = (uint32_t)nodes_of(c);
-            s.width = (uint32_t)c.length;
-            s.t0 = (uint32_t)p->t;
-            s.steps = steps[i];
-            s.realization = c.realization;
-            s.p_zero = p->fx.p == 0 ? 1u : 0u;
-            const uint32_t idx = (uint32_t)slots[g].size();
-            launched_slot.emplace_back(g, idx);
             const uint32_t nt = (uint32_t)((nodes_of(c) + ilg::kServeTile - 1) / ilg::kServeTile);
-            s.tile_begin = (uint32_t)tiles[g].size();
-            s.tile_end = s.tile_begin + nt;
-            slots[g].push_back(s);
-            tiles[g].insert(tiles[g].end(), nt, idx);
-            // Work estimate of a tile: its nodes times 1 + omega*, the
-            // measured growth of the step's cost with the collision fraction
-            // (more collided particles, larger redistribution binomials).
             const double w = 1.0 + p->fx.omega_star;
-            const uint64_t n = nodes_of(c);
-            for (uint32_t k = 0; k < nt; ++k) {
-                const uint64_t first = (uint64_t)k * ilg::kServeTile;
-                const uint64_t cnt = std::min<uint64_t>(ilg::kServeTile, n - first);
-                h_weight[g].push_back(w * (double)cnt);
-            }
-            maxsteps[g] = std::max(maxsteps[g], steps[i]);
-        }
-        for (int g = 0; g < kGroups; ++g) {
-            if (slots[g].empty())
+            if (resident_nodes != 0 && nodes_of(c) <= resident_nodes &&
+                res[g].size() < ilg::kResidentMaxWg) {
+                res[g].push_back({i, make_slot(r, p, steps[i]), nt * w + kResidentStep});
                 continue;
-            if (!streams[g])
-                SHIP(hipStreamCreateWithFlags(&streams[g], hipStreamNonBlocking));
-            // contiguous tile ranges of equal estimated work, one per workgroup
+            }
+            // the tile walk advances a request by at most the quantum (a
+            // small request beyond the launch's resident slots included)
+            taken_steps[i] = std::min(steps[i], quantum);
+            const uint32_t idx = (uint32_t)slots[g].size();
+            launched_slot[i] = {g, idx};
+            slots[g].push_back(make_slot(r, p, taken_steps[i]));
+            slots[g].back().tile_begin = (uint32_t)tiles[g].size();
+            slots[g].back().tile_end = (uint32_t)tiles[g].size() + nt;
+            tiles[g].insert(tiles[g].end(), nt, idx);
+            for (uint32_t k = 0; k < nt; ++k)
+                h_weight[g].push_back(w + (k == 0 ? kStage : 0.0));
+            maxsteps[g] = std::max(maxsteps[g], taken_steps[i]);
+        }
+        // Tile walk of each group: contiguous tile ranges of equal estimated
+        // work, one per workgroup, beside the group's resident workgroups.
+        uint32_t grid[kGroups] = {};
+        double per_wg[kGroups] = {}, longest = 0.0;
+        for (int g = 0; g < kGroups; ++g) {
             const uint32_t ntiles = (uint32_t)tiles[g].size();
-            const uint32_t grid = ilg::serve_grid(ntiles);
+            if (ntiles == 0)
+                continue;
+            grid[g] = ilg::serve_grid(ntiles, (uint32_t)res[g].size());
             double total = 0.0;
             for (double w : h_weight[g])
                 total += w;
+            per_wg[g] = total / grid[g];
+            longest = std::max(longest, per_wg[g] * maxsteps[g]);
             tiles[g].push_back(0);
             double acc = 0.0;
             uint32_t t = 0;
-            for (uint32_t b = 1; b < grid; ++b) {
-                const double target = total * b / grid;
+            for (uint32_t b = 1; b < grid[g]; ++b) {
+                const double target = total * b / grid[g];
                 while (t < ntiles && acc + 0.5 * h_weight[g][t] < target)
                     acc += h_weight[g][t++];
                 tiles[g].push_back(t);
             }
             tiles[g].push_back(ntiles);
+            // then the slot of each workgroup's first tile
+            for (uint32_t b = 0; b < grid[g]; ++b) {
+                const uint32_t first = tiles[g][ntiles + b];
+                tiles[g].push_back(first < ntiles ? tiles[g][first] : 0u);
+            }
+        }
+        // Resident slots: as many steps per launch as fit in the time of the
+        // group's tile walk (at least one); a group without a tile walk takes
+        // one launch about as long as the longest quantum of the other
+        // groups (at least the quantum's steps), or all the planned steps
+        // when no group has a tile walk.
+        for (int g = 0; g < kGroups; ++g) {
+            const uint32_t walk_steps = maxsteps[g];  // launches of the group's tile walk
+            for (Res &x : res[g]) {
+                const uint32_t planned = x.s.steps;
+                uint64_t per;
+                uint32_t take;
+                if (walk_steps > 0) {
+                    per = (uint64_t)std::max(1.0,
+                                             std::floor((per_wg[g] + kLaunch - kStage) / x.w));
+                    take = (uint32_t)std::min<uint64_t>(planned, per * walk_steps);
+                } else if (longest > 0.0) {
+                    // one launch, at least the quantum (what the tile walk
+                    // would have given it)
+                    per = std::max<uint64_t>((uint64_t)std::floor(longest / x.w), quantum);
+                    take = (uint32_t)std::min<uint64_t>(planned, per);
+                } else {
+                    per = planned;
+                    take = planned;
+                }
+                x.s.steps = take;
+                x.s.per_launch = (uint32_t)std::min<uint64_t>(per, take);
+                taken_steps[x.i] = take;
+                const uint32_t launches = (take + x.s.per_launch - 1) / x.s.per_launch;
+                maxsteps[g] = std::max(maxsteps[g], launches);
+            }
+        }
+        for (int g = 0; g < kGroups; ++g) {
+            if (slots[g].empty() && res[g].empty())
+                continue;
+            if (!streams[g])
+                SHIP(hipStreamCreateWithFlags(&streams[g], hipStreamNonBlocking));
+            const uint32_t ntiles = (uint32_t)h_weight[g].size();
+            const uint32_t res_first = (uint32_t)slots[g].size();
+            for (const Res &x : res[g]) {
+                launched_slot[x.i] = {g, (uint32_t)slots[g].size()};
+                slots[g].push_back(x.s);
+            }
+            if (tiles[g].empty())
+                tiles[g].push_back(0);  // no tile walk: nothing reads the list
             int rc = ensure(g, slots[g].size(), tiles[g].size());
             if (rc != ILG_OK)
                 return rc;
@@ -312,10 +411,13 @@ public:
             a.slots = d_slots[g];
             a.tile_slot = d_tiles[g];
             a.wg_tiles = d_tiles[g] + ntiles;
+            a.wg_slot = d_tiles[g] + ntiles + grid[g] + 1;
             a.ntiles = ntiles;
-            a.grid = grid;
+            a.grid = grid[g];
             a.shared = shared;
             a.slot_err = d_err[g];
+            a.nres = (uint32_t)res[g].size();
+            a.res_first = res_first;
             const int q = g >= 16 ? 5 : (g & 8) ? 3 : 2, cb = (g & 4) ? 4 : 2;
             const int rounds = (g & 2) ? 7 : 10;
             const bool exchange = (g & 1) != 0;
@@ -329,15 +431,8 @@ public:
         return ILG_OK;
     }
 
-    int wait() override
+    int wait(std::vector<uint32_t> *steps) override
     {
-        // Every launched request's step count and buffer parity advance with
-        // the launch, also when its own work overflowed (it is then retired).
-        for (size_t i = 0; i < launched.size(); ++i) {
-            Payload *p = payload_of(*launched[i]);
-            p->t += launched_steps[i];
-            p->cur ^= (launched_steps[i] & 1u);
-        }
         int rc = ILG_OK;
         for (int g = 0; g < kGroups && rc == ILG_OK; ++g) {
             if (h_slots[g].empty())
@@ -350,8 +445,17 @@ public:
             if (e != hipSuccess)
                 rc = shfail(e, "serve quantum");
         }
-        if (rc == ILG_OK) {
-            for (size_t i = 0; i < launched.size(); ++i) {
+        // Every launched request's step count and buffer parity advance with
+        // the steps its launches took (a resident request's may be fewer
+        // than planned), also when its own work overflowed (it is then
+        // retired).
+        for (size_t i = 0; i < launched.size(); ++i) {
+            const uint32_t k = taken_steps[i];
+            (*steps)[i] = k;
+            Payload *p = payload_of(*launched[i]);
+            p->t += k;
+            p->cur ^= (k & 1u);
+            if (rc == ILG_OK) {
                 const auto gs = launched_slot[i];
                 if (h_err[gs.first][gs.second] & 1u)
                     launched[i]->failed = true;
@@ -359,6 +463,7 @@ public:
         }
         launched.clear();
         launched_steps.clear();
+        taken_steps.clear();
         launched_slot.clear();
         return rc;
     }
@@ -460,7 +565,24 @@ int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server 
         delete s;
         return sfail(code, msg);
     }
+    // Small requests advance as resident slots, by up to 16 quanta per poll.
+    const uint64_t rsteps = std::min<uint64_t>(16ull * quantum_steps, 1u << 30);
+    s->sched->set_resident(ILG_RESIDENT_DEFAULT_NODES, (uint32_t)rsteps);
+    ex.resident_nodes = ILG_RESIDENT_DEFAULT_NODES;
+    ex.quantum = quantum_steps;
     *out = s;
+    return ILG_OK;
+}
+
+int ilg_server_set_resident(ilg_server *s, uint64_t max_nodes, uint32_t max_steps)
+{
+    if (!s)
+        return sfail(ILG_E_INVALID, "null server");
+    if (max_nodes > ILG_RESIDENT_MAX_NODES)
+        return sfail(ILG_E_INVALID, "resident requests hold at most " +
+                                        std::to_string(ILG_RESIDENT_MAX_NODES) + " nodes");
+    s->sched->set_resident(max_nodes, max_steps);
+    s->ex.resident_nodes = max_nodes;
     return ILG_OK;
 }
 
@@ -610,9 +732,10 @@ int ilg_server_destroy(ilg_server *s)
     if (!s)
         return ILG_OK;
     (void)s->sched->settle(s->ex, &steady_now, nullptr);
-    for (int g = 0; g < DeviceExecutor::kGroups; ++g)
+    for (int g = 0; g < DeviceExecutor::kGroups; ++g) {
         if (s->ex.streams[g])
             (void)hipStreamSynchronize(s->ex.streams[g]);
+    }
     delete s;
     return ILG_OK;
 }

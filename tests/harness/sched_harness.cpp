@@ -1,9 +1,11 @@
 // Test harness: the serving scheduler (paper_2203_01380_amd/csrc/scheduler.cpp)
 // driven by a counting executor on the CPU, behind a small C API for ctypes.
 // The executor checks the scheduler's contract: a request is loaded once,
-// advanced only while active, never by more than the quantum or past its
-// step count, unloaded once when done; and the arena never exceeds the
-// budget while the sum of active footprints matches the arena's use.
+// advanced only while active, never by more than the quantum (the resident
+// step count for a small request) or past its step count, unloaded once when
+// done; and the arena never exceeds the budget while the sum of active
+// footprints matches the arena's use.  It can end a small request's advance
+// early, as the device executor does, and counts the steps it reports.
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -24,6 +26,10 @@ struct Counting : Executor {
     std::vector<uint64_t> load_order;
     std::vector<uint64_t> last_launch;  // ids of the last launch, in order
     uint64_t step_nodes = 0;            // node cap the scheduler was given
+    uint64_t resident_nodes = 0;        // small requests: up to resident_steps a poll
+    uint32_t resident_steps = 0;
+    uint32_t resident_stop = 0;         // end a small request's advance after this many (0: never)
+    std::vector<uint32_t> planned;      // steps of the last launch
     uint64_t active_bytes = 0;
     int violations = 0;
     // failure injection: requests whose admission fails, and requests whose
@@ -64,16 +70,29 @@ struct Counting : Executor {
             ++violations;  // more nodes than the cap in a multi-request quantum
         for (size_t i = 0; i < active.size(); ++i) {
             Req *r = active[i];
-            if (r->state != ReqState::Active || steps[i] == 0 || steps[i] > quantum ||
+            const bool small = r->nodes != 0 && r->nodes <= resident_nodes;
+            const uint32_t cap = small ? resident_steps : quantum;
+            if (r->state != ReqState::Active || steps[i] == 0 || steps[i] > cap ||
                 r->done + steps[i] > r->total)
                 ++violations;
-            steps_seen[r->id] += steps[i];
         }
+        planned = steps;
         return 0;
     }
-    int wait() override
+    int wait(std::vector<uint32_t> *steps) override
     {
         in_flight = false;
+        if (steps->size() != launched.size() || *steps != planned)
+            ++violations;  // not the steps of the launch being waited for
+        for (size_t i = 0; i < launched.size() && i < steps->size(); ++i) {
+            const Req *r = launched[i];
+            uint32_t k = (*steps)[i];
+            if (resident_stop != 0 && r->nodes != 0 && r->nodes <= resident_nodes &&
+                k > resident_stop)
+                k = resident_stop;
+            (*steps)[i] = k;
+            steps_seen[r->id] += k;
+        }
         for (Req *r : launched) {
             if (fail_wait.count(r->id)) {
                 if (r->failed)
@@ -145,6 +164,24 @@ void h_set_step_nodes(void *hv, uint64_t nodes)
     Harness *h = static_cast<Harness *>(hv);
     h->sched.set_step_nodes(nodes);
     h->ex.step_nodes = nodes;
+}
+
+void h_set_resident(void *hv, uint64_t nodes, uint32_t steps, uint32_t stop_after)
+{
+    Harness *h = static_cast<Harness *>(hv);
+    h->sched.set_resident(nodes, steps);
+    h->ex.resident_nodes = nodes;
+    h->ex.resident_steps = steps > h->ex.quantum ? steps : h->ex.quantum;
+    h->ex.resident_stop = stop_after;
+}
+
+int h_last_steps(void *hv, uint32_t *out, int cap)
+{
+    Harness *h = static_cast<Harness *>(hv);
+    int n = (int)h->ex.planned.size();
+    for (int i = 0; i < n && i < cap; ++i)
+        out[i] = h->ex.planned[i];
+    return n;
 }
 
 int h_last_launch(void *hv, uint64_t *out, int cap)

@@ -51,11 +51,18 @@ def _alone(ilg, m, init, nsteps):
     return out
 
 
-def test_mixed_requests_equal_alone_and_oracle(ilg, oracle_lib):
+# Small requests advanced in one workgroup per request (the default), or all
+# requests by the per-step launches.
+RESIDENT = [None, (0, 0)]
+RESIDENT_IDS = ["resident", "steps-only"]
+
+
+@pytest.mark.parametrize("resident", RESIDENT, ids=RESIDENT_IDS)
+def test_mixed_requests_equal_alone_and_oracle(ilg, oracle_lib, resident):
     """40 requests of both velocity sets and count types, lengths from 1 to
     5000, 1..300 steps, submitted in three waves while earlier ones run."""
     reqs = _requests(40, seed=1)
-    srv = ilg.Server(64 << 20, quantum_steps=37)
+    srv = ilg.Server(64 << 20, quantum_steps=37, resident=resident)
     ids = {}
     for k, (m, init, ns) in enumerate(reqs):
         ids[k] = srv.submit(m, init, ns)
@@ -82,7 +89,8 @@ def test_mixed_requests_equal_alone_and_oracle(ilg, oracle_lib):
     srv.close()
 
 
-def test_draw_specifications_in_one_server(ilg, oracle_lib):
+@pytest.mark.parametrize("resident", RESIDENT, ids=RESIDENT_IDS)
+def test_draw_specifications_in_one_server(ilg, oracle_lib, resident):
     """Requests under draw specifications v1, v2 (7 rounds) and v3 (D1Q2
     exchange form, 10 or 7 rounds) share one server (one launch group per
     specification): each result equals the same configuration run alone and,
@@ -95,7 +103,7 @@ def test_draw_specifications_in_one_server(ilg, oracle_lib):
         if exchange and m["q"] != 2:
             exchange = False
         reqs.append((dict(m, rounds=rounds, exchange=exchange), init, ns))
-    srv = ilg.Server(64 << 20, quantum_steps=29)
+    srv = ilg.Server(64 << 20, quantum_steps=29, resident=resident)
     ids = [srv.submit(m, init, ns) for m, init, ns in reqs]
     polls = 0
     while True:
@@ -115,7 +123,8 @@ def test_draw_specifications_in_one_server(ilg, oracle_lib):
     srv.close()
 
 
-def test_d2q5_requests_with_1d_ones(ilg, oracle_lib):
+@pytest.mark.parametrize("resident", RESIDENT, ids=RESIDENT_IDS)
+def test_d2q5_requests_with_1d_ones(ilg, oracle_lib, resident):
     """D2Q5 requests (shapes from one node to rows wider than a tile, both
     count types, 10- and 7-round draws, a device-drawn initial state) served
     beside D1Q2/D1Q3 requests: each equals the configuration run alone and,
@@ -134,7 +143,7 @@ def test_d2q5_requests_with_1d_ones(ilg, oracle_lib):
                            size=(5, ly, lx)).astype(dt)
         reqs.append((m, init, int(rng.integers(5, 90))))
     reqs += _requests(12, seed=22)
-    srv = ilg.Server(64 << 20, quantum_steps=23)
+    srv = ilg.Server(64 << 20, quantum_steps=23, resident=resident)
     ids = [srv.submit(m, init, ns) for m, init, ns in reqs]
     drawn = dict(q=5, length=96, height=40, count_bytes=2, omega=1.5, seed=77, realization=3,
                  t0=0)
@@ -344,4 +353,82 @@ def test_stream_sized_requests_equal_alone_and_oracle(ilg, oracle_lib):
                                         t0=m["t0"])
             assert not ov
             np.testing.assert_array_equal(got, ref, err_msg=f"request {k} vs oracle")
+    srv.close()
+
+
+def test_resident_advances_beside_large(ilg, oracle_lib):
+    """Small requests with long step counts beside a large one: each advances
+    by several steps per launch of the large request's quantum (at least one
+    per launch, so at least the quantum per poll, and fewer than all of its
+    steps); every result equals its run alone and, for a sample, the
+    oracle."""
+    big = (dict(q=3, length=1 << 20, count_bytes=2, omega=1.6, seed=61, realization=0, t0=0),
+           W.init_poisson_iid(3, 1 << 20, 40.0, 2, init_seed=62), 120)
+    small = []
+    for i, (q, L) in enumerate([(2, 1), (3, 100), (2, 1024), (3, 1025), (3, 4096), (2, 3000)]):
+        m = dict(q=q, length=L, count_bytes=2, omega=1.1 + 0.15 * i, seed=70 + i,
+                 realization=i, t0=3 * i)
+        small.append((m, W.init_poisson_iid(q, L, 40.0, 2, init_seed=80 + i), 4000))
+    srv = ilg.Server(256 << 20, quantum_steps=20, resident=(4096, 4000))
+    bid = srv.submit(*big)
+    sids = [srv.submit(m, init, ns) for m, init, ns in small]
+    srv.poll()  # admits all, launches the first quantum
+    srv.poll()  # accounts for it
+    taken = [srv.info(rid)["steps_done"] for rid in sids]
+    _say(f"[serve] small requests' steps after the first quantum: {taken}")
+    assert srv.info(bid)["steps_done"] == 20
+    assert all(20 <= k < 4000 for k in taken)
+    assert _drain(srv) == 0
+    np.testing.assert_array_equal(srv.result(bid), _alone(ilg, *big))
+    for k, (rid, (m, init, ns)) in enumerate(zip(sids, small)):
+        got = srv.result(rid)
+        np.testing.assert_array_equal(got, _alone(ilg, m, init, ns), err_msg=f"small {k}")
+        if k % 2 == 0:
+            p = oracle_lib.Params(m["q"], m["omega"])
+            ref, _, _ = oracle_lib.run(p, init, ns, seed=m["seed"], realization=m["realization"],
+                                       t0=m["t0"])
+            np.testing.assert_array_equal(got, ref, err_msg=f"small {k} vs oracle")
+    srv.close()
+
+
+def test_resident_only_take_full_advances(ilg):
+    """With only small requests active, each resident request takes
+    min(steps left, the resident step count) in the poll's single launch.
+    With more than a group's 128 resident slots, the others go to the tile
+    walk (the quantum per poll) and the resident ones then take at least the
+    quantum.  All finish bit-identical to their runs alone."""
+    reqs = []
+    for i in range(300):
+        q = 2 + i % 2
+        L = 1 + (i * 37) % 4096
+        m = dict(q=q, length=L, count_bytes=2, omega=1.05 + 0.003 * i, seed=900 + i,
+                 realization=i, t0=0)
+        reqs.append((m, W.init_poisson_iid(q, L, 40.0, 2, init_seed=1900 + i), 50 + 3 * i))
+    srv = ilg.Server(256 << 20, quantum_steps=10, resident=(4096, 300))
+    for part, n in ((reqs[:200], 200), (reqs, 300)):
+        ids = [srv.submit(m, init, ns) for m, init, ns in part]
+        srv.poll()
+        srv.poll()
+        taken = [srv.info(rid)["steps_done"] for rid in ids]
+        if n == 200:
+            assert taken == [min(ns, 300) for _, _, ns in part]
+        else:
+            walk = sum(1 for k in taken if k == 10)
+            _say(f"[serve] tile-walk advances {walk} of {n}")
+            assert walk >= 44
+            assert all(10 <= k <= min(ns, 300) for k, (_, _, ns) in zip(taken, part))
+        assert _drain(srv) == 0
+        for k, (rid, (m, init, ns)) in enumerate(zip(ids, part)):
+            np.testing.assert_array_equal(srv.result(rid), _alone(ilg, m, init, ns),
+                                          err_msg=f"request {k}")
+    srv.close()
+
+
+def test_resident_setting_checked(ilg):
+    srv = ilg.Server(1 << 20, quantum_steps=10)
+    with pytest.raises(ilg.IlgError) as e:
+        srv.set_resident(65537, 100)
+    assert e.value.code == -1
+    srv.set_resident(0, 0)
+    srv.set_resident(65536, 5)
     srv.close()

@@ -46,6 +46,9 @@ def H(tmp_path_factory):
     L.h_fail_load.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
     L.h_fail_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
     L.h_poll5.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]
+    L.h_set_resident.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                 ctypes.c_uint32]
+    L.h_last_steps.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int]
     return L
 
 
@@ -77,6 +80,11 @@ class Sched:
     def last_launch(self):
         buf = (ctypes.c_uint64 * 4096)()
         n = self.H.h_last_launch(self.h, buf, 4096)
+        return list(buf[:n])
+
+    def last_steps(self):
+        buf = (ctypes.c_uint32 * 4096)()
+        n = self.H.h_last_steps(self.h, buf, 4096)
         return list(buf[:n])
 
     def load_order(self):
@@ -318,3 +326,77 @@ def test_failed_admission_retired_alone(H):
     assert H.h_used(s.h) == 0
     assert H.h_violations(s.h) == 0
     H.h_free(s.h)
+
+
+def test_resident_requests_take_longer_advances(H):
+    """Requests of at most the resident node count are advanced by up to the
+    resident step count per poll, the others by the quantum; both finish
+    with exactly their steps."""
+    s = Sched(H, 1 << 20, 10)
+    H.h_set_resident(s.h, 100, 50, 0)
+    small = s.submit_nodes(64, 120)
+    edge = s.submit_nodes(100, 70)
+    big = s.submit_nodes(101, 45)
+    s.poll()
+    assert s.last_launch() == [small, edge, big]
+    assert s.last_steps() == [50, 50, 10]
+    polls = 1
+    while True:
+        st = s.poll()
+        polls += 1
+        if st["active"] == 0 and st["queued"] == 0:
+            break
+    # big: 45 steps at 10 per poll, so 5 launches, then one poll that retires
+    assert polls == 6
+    for rid, n in ((small, 120), (edge, 70), (big, 45)):
+        st, done, _, _ = s.state(rid)
+        assert st == 2 and done == n
+    assert H.h_violations(s.h) == 0
+    s.close()
+
+
+def test_resident_advance_ended_early(H):
+    """The executor may end a small request's advance early (here after 7 of
+    up to 50 steps): the scheduler counts the steps taken, plans the next
+    advance from them, and the request still finishes with exactly its
+    steps."""
+    s = Sched(H, 1 << 20, 10)
+    H.h_set_resident(s.h, 100, 50, 7)
+    small = s.submit_nodes(64, 120)
+    big = s.submit_nodes(1000, 30)
+    s.poll()
+    assert s.last_steps() == [50, 10]
+    s.poll()
+    assert s.state(small)[1] == 7
+    assert s.last_steps() == [50, 10]
+    drain(s)
+    st, done, _, _ = s.state(small)
+    assert st == 2 and done == 120
+    assert s.state(big)[:2] == (2, 30)
+    assert H.h_violations(s.h) == 0
+    s.close()
+
+
+def test_resident_random_stress(H):
+    """Random small and large requests with resident advances ended early at
+    random points, cancellations and the node cap."""
+    rng = np.random.default_rng(11)
+    budget = 300_000
+    s = Sched(H, budget, 16)
+    H.h_set_resident(s.h, 500, 200, 0)
+    live = []
+    for it in range(500):
+        if it % 50 == 0:
+            H.h_set_resident(s.h, 500, 200, int(rng.integers(0, 40)))
+        if it == 250:
+            H.h_set_step_nodes(s.h, 3000)
+        if rng.random() < 0.6:
+            nodes = int(rng.integers(1, 1000))
+            live.append(s.submit_nodes(nodes, int(rng.integers(1, 400)),
+                                       int(rng.integers(1, 40_000))))
+        if live and rng.random() < 0.05:
+            H.h_cancel(s.h, live.pop(int(rng.integers(len(live)))))
+        s.poll()
+    drain(s)
+    assert H.h_violations(s.h) == 0 and H.h_used(s.h) == 0
+    s.close()
