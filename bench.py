@@ -409,9 +409,30 @@ def bench_batched_d2q5(ilg, stream, steps: int = 2000, n: int = 2048, side: int 
     sec = timed(stream, lambda: b.run(steps))
     b.close()
     nu = n * side * side * steps
+    # The cost of a node grows steeply with the collision fraction omega*
+    # (more than 64 collided particles take the chunked redistribution), so
+    # the plain form is timed at the same rates: one 1024 x 1024 lattice at
+    # each of 16 evenly spaced quantiles of the members' omega, 100 steps.
+    oms = np.sort([m["omega"] for m in members])
+    tot, work, side_p = 0.0, 0, 1024
+    per_omega = []
+    for q in np.linspace(0, len(oms) - 1, 16).astype(int):
+        init = rng.poisson(means, size=(5, side_p, side_p)).astype(np.uint16)
+        lat = ilg.Lattice(5, side_p, 2, float(oms[q]), 7, init, height=side_p)
+        lat.step(10)
+        sec_q = timed(stream, lambda: lat.step(100))
+        tot += sec_q
+        work += side_p * side_p * 100
+        per_omega.append([round(float(oms[q]), 4), side_p * side_p * 100 / sec_q])
+        lat.close()
+    plain = work / tot
     return {"workload": f"{n} D2Q5 lattices of {side} x {side}, uint16, Poisson means "
                         f"(25, 25, 50, 25, 25), omega ~ U[1, 1.95], own seeds, {steps} steps",
-            "node_updates_per_s": nu / sec, "seconds": sec, "node_updates": nu, "shape": shape}
+            "node_updates_per_s": nu / sec, "seconds": sec, "node_updates": nu, "shape": shape,
+            "plain_same_rates": {"node_updates_per_s": plain, "lattices": 16,
+                                 "side": side_p, "steps": 100,
+                                 "omega_and_node_updates_per_s": per_omega},
+            "batched_over_plain_same_rates": (nu / sec) / plain}
 
 
 def bench_batched_decay(ilg, W, stream, steps: int):

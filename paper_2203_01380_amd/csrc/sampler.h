@@ -567,6 +567,35 @@ __device__ __forceinline__ W or_all(const W (&c)[Q])
     return any;
 }
 
+// The redistribution of M collided particles (the multinomial as
+// conditional binomials), chunk by chunk in the draw order from draw j on:
+// q = 2: Bin(M, 1/2) to -1; q = 3: the rest Bin(M, P_rest), then the movers'
+// split Bin(R, 1/2) to -1; q = 5: the rest, then the x/y pair split
+// Bin(R, 1/2), then -x within x and -y within y, Bin(., 1/2) each.
+template <int Q, typename W, int NB, int GB, int NR, typename K>
+__device__ __forceinline__ void redistribute_generic(W M, uint32_t j, W (&mv)[Q],
+                                                     const Draws<NB, NR, K> &d, const Tabs &tb)
+{
+    if constexpr (Q == 2) {
+        mv[0] = binomial<kTidHalf, W, NB, GB>(M, j, tb.g_half, false, d);
+        mv[1] = M - mv[0];
+    } else if constexpr (Q == 5) {
+        mv[2] = binomial<kTidRest, W, NB, GB>(M, j, tb.g_rest, false, d);
+        const W R = M - mv[2];
+        const W mx = binomial<kTidHalf, W, NB, GB>(R, j, tb.g_half, false, d);
+        const W my = R - mx;
+        mv[0] = binomial<kTidHalf, W, NB, GB>(mx, j, tb.g_half, false, d);
+        mv[4] = mx - mv[0];
+        mv[1] = binomial<kTidHalf, W, NB, GB>(my, j, tb.g_half, false, d);
+        mv[3] = my - mv[1];
+    } else {
+        mv[1] = binomial<kTidRest, W, NB, GB>(M, j, tb.g_rest, false, d);
+        const W R = M - mv[1];
+        mv[0] = binomial<kTidHalf, W, NB, GB>(R, j, tb.g_half, false, d);
+        mv[2] = R - mv[0];
+    }
+}
+
 // D2Q5 node update when every lane has the movers' counts in 1..64 and the
 // rest count in 1..128 (one or two chunks: D = 1 or 2 by lane) and the
 // redistribution fits one chunk per binomial (M <= 64).  Draws: movers -x
@@ -576,8 +605,10 @@ __device__ __forceinline__ W or_all(const W (&c)[Q])
 // Bin(m_y, 1/2) for -y at the next draw (8 if the -x split took one, else 7).
 // Earlier zero counts make the later words irrelevant (M = 0 or R = 0 leaves
 // nothing to split).  The removal chunks are probed together, and so are
-// the two last splits.  Returns false (nothing written) if some lane has
-// M > 64.
+// the two last splits.  Where some lane of the wave has M > 64 (most waves
+// at high collision fractions: M is about omega* times the density), the
+// redistribution goes on chunk by chunk from the word after the removal
+// draws, as the generic path takes it; the removal is not repeated.
 template <typename W, int NB, int GB, int NR, typename K>
 __device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Draws<NB, NR, K> &d,
                                            const Tabs &tb, bool p_zero)
@@ -616,9 +647,15 @@ __device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Dr
         kv[4] = (W)clamp_to(cc[5], rows[5]);
     }
     const W M = kv[0] + kv[1] + kv[2] + kv[3] + kv[4];
-    if (wave_any(M > (W)kChunk))
-        return false;
     W mv[5];
+    if (wave_any(M > (W)kChunk)) {
+        // the removal took draws 0..4, and 5 with a two-chunk rest count
+        redistribute_generic<5, W, NB, GB>(M, two ? 6u : 5u, mv, d, tb);
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            c[i] = av[i] - kv[i] + mv[i];
+        return true;
+    }
     mv[2] = (W)chunk_or_zero<kTidRest, GB>(tb.g_rest, (uint32_t)M,
                                            wk(std::integral_constant<int, 5>{}));
     const W R = M - mv[2];
@@ -665,25 +702,7 @@ __device__ __forceinline__ void node_generic(const WW (&av)[Q], WW (&cn)[Q],
         kv[i] = binomial<kTidP, W, NB, GB>(av[i], j, tb.g_p, p_zero, d);
         M += kv[i];
     }
-    if constexpr (Q == 2) {
-        mv[0] = binomial<kTidHalf, W, NB, GB>(M, j, tb.g_half, false, d);
-        mv[1] = M - mv[0];
-    } else if constexpr (Q == 5) {
-        // rest, then the x/y pair split, then -x within x, -y within y
-        mv[2] = binomial<kTidRest, W, NB, GB>(M, j, tb.g_rest, false, d);
-        const W R = M - mv[2];
-        const W mx = binomial<kTidHalf, W, NB, GB>(R, j, tb.g_half, false, d);
-        const W my = R - mx;
-        mv[0] = binomial<kTidHalf, W, NB, GB>(mx, j, tb.g_half, false, d);
-        mv[4] = mx - mv[0];
-        mv[1] = binomial<kTidHalf, W, NB, GB>(my, j, tb.g_half, false, d);
-        mv[3] = my - mv[1];
-    } else {
-        mv[1] = binomial<kTidRest, W, NB, GB>(M, j, tb.g_rest, false, d);
-        const W R = M - mv[1];
-        mv[0] = binomial<kTidHalf, W, NB, GB>(R, j, tb.g_half, false, d);
-        mv[2] = R - mv[0];
-    }
+    redistribute_generic<Q, W, NB, GB>(M, j, mv, d, tb);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         cn[i] = av[i] - kv[i] + mv[i];

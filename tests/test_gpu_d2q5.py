@@ -70,6 +70,18 @@ def test_special_rates(ilg, omega, flip, theta):
     _run_both(ilg, 50, 40, 4, omega, init, steps=6, seed=9, flip=flip, theta=theta)
 
 
+@pytest.mark.parametrize("omega", [1.0, 1.3, 1.5, 1.62])
+def test_collided_beyond_one_chunk(ilg, omega):
+    """Movers' counts in one chunk, rest counts in one or two, and more than
+    64 collided particles in some or all lanes of a wave (M is about omega*
+    times the density 150): the redistribution continues chunk by chunk
+    after the straight-line removal."""
+    rng = np.random.default_rng(int(omega * 100))
+    means = np.array([25.0, 25.0, 50.0, 25.0, 25.0])[:, None, None]
+    init = rng.poisson(means, size=(5, 80, 96)).astype(np.uint16)
+    _run_both(ilg, 96, 80, 2, omega, init, steps=8, seed=21, r=5)
+
+
 def test_multi_chunk_counts(ilg):
     """Counts above 64 (several chunks, draws past the eager blocks)."""
     rng = np.random.default_rng(4)
