@@ -109,12 +109,12 @@ __device__ __forceinline__ void serve_load(ConstSlot *sl, uint32_t j, uint32_t x
 
 // Node x of one slot at step index j (absolute step sl->t0 + j), its counts
 // av loaded: update, push to the neighbours.  x0: the first node of the
-// thread's tile (uniform).
-template <int Q, typename T, int NR, bool EX, typename W>
+// thread's tile (uniform).  NB: Philox blocks drawn up front.
+template <int Q, typename T, int NR, bool EX, int NB, typename W, typename K>
 __device__ __forceinline__ void serve_update(ConstSlot *sl, uint32_t j, uint32_t x0, uint32_t x,
-                                             const W (&av)[Q], const sampler::Tabs &tb, W &ovf)
+                                             const W (&av)[Q], const K &key,
+                                             const sampler::Tabs &tb, W &ovf)
 {
-    constexpr int NB = (Q == 5) ? 3 : (Q == 3) ? 2 : 1;  // Philox blocks drawn up front
     constexpr int GB = kServeGuideBits;
     const uint32_t L = sl->length;
     const uint32_t par = j & 1u;
@@ -123,12 +123,6 @@ __device__ __forceinline__ void serve_update(ConstSlot *sl, uint32_t j, uint32_t
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         out_row[i] = sl->rows[par][5 + i];
-    PhiloxSchedule key;
-#pragma unroll
-    for (int i = 0; i < 10; ++i) {
-        key.ka[i] = sl->ka[i];
-        key.kb[i] = sl->kb[i];
-    }
     const uint32_t t = sl->t0 + j;
     if constexpr (EX) {
         static_assert(Q == 2, "the exchange form is defined for D1Q2");
@@ -158,10 +152,17 @@ __device__ __forceinline__ void serve_update(ConstSlot *sl, uint32_t j, uint32_t
     }
 }
 
+// Philox blocks drawn up front per node.
+template <int Q>
+constexpr int kNB = (Q == 5) ? 3 : (Q == 3) ? 2 : 1;
+
 // NR: Philox rounds of the draws (10, or 7 for draw specification v2); EX:
 // the D1Q2 exchange form (specification v3).  The server launches one group
-// of requests per (q, count type, specification).
-template <int Q, typename T, int NR, bool EX>
+// of requests per (q, count type, specification).  RES: the launch has
+// resident slots.  A group without them runs the kernel without that path:
+// compiled with it (more scalar registers, 82 against 70 for D1Q2) the tile
+// walk ran a quarter slower (D1Q2, saturated).
+template <int Q, typename T, int NR, bool EX, bool RES>
 __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
 {
     using W = typename Wide<T>::type;
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     constexpr W kMax = (W)(T)~(T)0;
     W ovf = 0;
 
-    if (blockIdx.x >= a.grid) {
+    if (RES && blockIdx.x >= a.grid) {
         // A resident slot: a small request advanced by this workgroup alone,
         // its steps of this launch back to back, a workgroup barrier after
         // each (it makes the step's stores visible to every wave, which read
@@ -200,7 +201,13 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
                     continue;
                 W av[Q];
                 serve_load<Q, T>(sl, j, x, av);
-                serve_update<Q, T, NR, EX>(sl, j, x0, x, av, tb, ovf);
+                PhiloxSchedule key;
+#pragma unroll
+                for (int i = 0; i < 10; ++i) {
+                    key.ka[i] = sl->ka[i];
+                    key.kb[i] = sl->kb[i];
+                }
+                serve_update<Q, T, NR, EX, kNB<Q>>(sl, j, x0, x, av, key, tb, ovf);
             }
             if (j + 1 < last)
                 __syncthreads();
@@ -257,7 +264,13 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
             continue;
         W av[Q];
         serve_load<Q, T>(sl, a.j, x, av);
-        serve_update<Q, T, NR, EX>(sl, a.j, x0, x, av, tb, ovf);
+        PhiloxSchedule key;
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            key.ka[i] = sl->ka[i];
+            key.kb[i] = sl->kb[i];
+        }
+        serve_update<Q, T, NR, EX, kNB<Q>>(sl, a.j, x0, x, av, key, tb, ovf);
     }
     if (ovf > kMax)
         atomicOr(a.slot_err + slot, 1u);
@@ -268,8 +281,12 @@ hipError_t launch_qt(const ServeArgs &a, hipStream_t stream)
 {
     if (a.grid + a.nres == 0)
         return hipSuccess;
-    hipLaunchKernelGGL((serve_kernel<Q, T, NR, EX>), dim3(a.grid + a.nres), dim3(kBlock), 0,
-                       stream, a);
+    if (a.nres != 0)
+        hipLaunchKernelGGL((serve_kernel<Q, T, NR, EX, true>), dim3(a.grid + a.nres),
+                           dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL((serve_kernel<Q, T, NR, EX, false>), dim3(a.grid), dim3(kBlock), 0,
+                           stream, a);
     return hipGetLastError();
 }
 
