@@ -235,8 +235,15 @@ constexpr uint32_t kResidentMaxWg = 128;
 // per CU).
 uint32_t serve_grid(uint32_t ntiles, uint32_t reserved);
 
-hipError_t launch_serve(int q, int count_bytes, int rounds, bool exchange, const ServeArgs &a,
-                        hipStream_t stream);
+// One step launch of a group: the kernel reads its arguments from argp
+// (device memory the host writes before the launches; its field j is
+// ignored) and takes the step index j of the quantum; res: the arguments
+// have resident slots.  Every launch has serve_launch_grid() workgroups
+// (those beyond the arguments' grid + nres return at once), so a quantum's
+// launches can be captured in a graph once and replayed.
+uint32_t serve_launch_grid();
+hipError_t launch_serve(int q, int count_bytes, int rounds, bool exchange, bool res,
+                        const ServeArgs *argp, uint32_t j, hipStream_t stream);
 
 
 }  // namespace ilg

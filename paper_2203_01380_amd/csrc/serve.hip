@@ -162,10 +162,18 @@ constexpr int kNB = (Q == 5) ? 3 : (Q == 3) ? 2 : 1;
 // resident slots.  A group without them runs the kernel without that path:
 // compiled with it (more scalar registers, 82 against 70 for D1Q2) the tile
 // walk ran a quarter slower (D1Q2, saturated).
+using ConstArgs = const __attribute__((address_space(4))) ServeArgs;
+
 template <int Q, typename T, int NR, bool EX, bool RES>
-__global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
+__global__ __launch_bounds__(kBlock) void serve_kernel(const ServeArgs *argp, uint32_t j)
 {
     using W = typename Wide<T>::type;
+    // The launch's arguments from device memory (scalar loads): the grid is
+    // the same for every launch, so that a quantum's launches can be
+    // captured once and replayed; workgroups beyond this launch's return.
+    ConstArgs *a = (ConstArgs *)argp;
+    if (blockIdx.x >= a->grid + (RES ? a->nres : 0u))
+        return;
     __shared__ __align__(16) uint8_t s_lds[ServeLds<Q>::kBytes];
     uint32_t *s_tab = reinterpret_cast<uint32_t *>(s_lds);
     uint8_t *s_guide = s_lds + ServeLds<Q>::kTabBytes;
@@ -176,44 +184,44 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     sampler::stage_row_offsets(tab_p, tab_half, tab_rest);
     // The shared half table and the first slot's tables are staged together,
     // before one barrier.
-    stage_half(a.shared, s_tab, s_guide);
+    stage_half(a->shared, s_tab, s_guide);
     constexpr W kMax = (W)(T)~(T)0;
     W ovf = 0;
 
-    if (RES && blockIdx.x >= a.grid) {
+    if (RES && blockIdx.x >= a->grid) {
         // A resident slot: a small request advanced by this workgroup alone,
         // its steps of this launch back to back, a workgroup barrier after
         // each (it makes the step's stores visible to every wave, which read
         // them in the next step).
-        const uint32_t slot = a.res_first + (blockIdx.x - a.grid);
-        ConstSlot *sl = const_space(a.slots) + slot;
-        const uint32_t first = a.j * sl->per_launch;
+        const uint32_t slot = a->res_first + (blockIdx.x - a->grid);
+        ConstSlot *sl = const_space(a->slots) + slot;
+        const uint32_t first = j * sl->per_launch;
         if (first >= sl->steps)
             return;  // uniform: this slot's advance is complete
         const uint32_t last = min(first + sl->per_launch, sl->steps);
         const uint32_t L = sl->length;
-        stage_slot<Q>(a.arena, sl->table_off, s_tab, s_guide);
+        stage_slot<Q>(a->arena, sl->table_off, s_tab, s_guide);
         __syncthreads();  // every table is visible to every wave
-        for (uint32_t j = first; j < last; ++j) {
+        for (uint32_t js = first; js < last; ++js) {
             for (uint32_t x0 = 0; x0 < L; x0 += kBlock) {
                 const uint32_t x = x0 + threadIdx.x;
                 if (x >= L)
                     continue;
                 W av[Q];
-                serve_load<Q, T>(sl, j, x, av);
+                serve_load<Q, T>(sl, js, x, av);
                 PhiloxSchedule key;
 #pragma unroll
                 for (int i = 0; i < 10; ++i) {
                     key.ka[i] = sl->ka[i];
                     key.kb[i] = sl->kb[i];
                 }
-                serve_update<Q, T, NR, EX, kNB<Q>>(sl, j, x0, x, av, key, tb, ovf);
+                serve_update<Q, T, NR, EX, kNB<Q>>(sl, js, x0, x, av, key, tb, ovf);
             }
-            if (j + 1 < last)
+            if (js + 1 < last)
                 __syncthreads();
         }
         if (ovf > kMax)
-            atomicOr(a.slot_err + slot, 1u);
+            atomicOr(a->slot_err + slot, 1u);
         return;
     }
 
@@ -221,8 +229,8 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     // estimated work (the work per node grows with a slot's collision
     // fraction), so a launch does not wait on the workgroups of its most
     // expensive requests.
-    const uint32_t lo = a.wg_tiles[blockIdx.x];
-    const uint32_t hi = a.wg_tiles[blockIdx.x + 1];
+    const uint32_t lo = a->wg_tiles[blockIdx.x];
+    const uint32_t hi = a->wg_tiles[blockIdx.x + 1];
     if (lo >= hi)
         return;
     // The first tile's slot (from its own list, so that its read does not
@@ -232,29 +240,29 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
     // the descriptor itself measured slower: the compiler keeps it in vector
     // registers.)  The descriptor holds the rows' addresses and the round
     // keys, so a tile reads them instead of forming them.
-    uint32_t slot = __builtin_amdgcn_readfirstlane(a.wg_slot[blockIdx.x]);  // uniform
-    stage_slot<Q>(a.arena, const_space(a.slots)[slot].table_off, s_tab, s_guide);
+    uint32_t slot = __builtin_amdgcn_readfirstlane(a->wg_slot[blockIdx.x]);  // uniform
+    stage_slot<Q>(a->arena, const_space(a->slots)[slot].table_off, s_tab, s_guide);
     uint32_t staged = slot;
     __syncthreads();  // every table is visible to every wave
     for (uint32_t tile = lo; tile < hi; ++tile) {
-        if (tile >= const_space(a.slots)[slot].tile_end) {
+        if (tile >= const_space(a->slots)[slot].tile_end) {
             // leaving a slot: its overflow is reported in its own error word
             if (ovf > kMax)
-                atomicOr(a.slot_err + slot, 1u);
+                atomicOr(a->slot_err + slot, 1u);
             ovf = 0;
             do
                 ++slot;
-            while (tile >= const_space(a.slots)[slot].tile_end);
+            while (tile >= const_space(a->slots)[slot].tile_end);
         }
-        ConstSlot *sl = const_space(a.slots) + slot;
-        if (a.j >= sl->steps)
+        ConstSlot *sl = const_space(a->slots) + slot;
+        if (j >= sl->steps)
             continue;
         if (slot != staged) {
             // Barriers only where the walk enters a new slot: before the
             // restage (readers of the previous slot's tables are done) and
             // after it (the new tables are visible).
             __syncthreads();
-            stage_slot<Q>(a.arena, sl->table_off, s_tab, s_guide);
+            stage_slot<Q>(a->arena, sl->table_off, s_tab, s_guide);
             staged = slot;
             __syncthreads();
         }
@@ -263,62 +271,67 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(ServeArgs a)
         if (x >= sl->length)
             continue;
         W av[Q];
-        serve_load<Q, T>(sl, a.j, x, av);
+        serve_load<Q, T>(sl, j, x, av);
         PhiloxSchedule key;
 #pragma unroll
         for (int i = 0; i < 10; ++i) {
             key.ka[i] = sl->ka[i];
             key.kb[i] = sl->kb[i];
         }
-        serve_update<Q, T, NR, EX, kNB<Q>>(sl, a.j, x0, x, av, key, tb, ovf);
+        serve_update<Q, T, NR, EX, kNB<Q>>(sl, j, x0, x, av, key, tb, ovf);
     }
     if (ovf > kMax)
-        atomicOr(a.slot_err + slot, 1u);
+        atomicOr(a->slot_err + slot, 1u);
 }
 
+struct Launch {
+    bool res;
+    const ServeArgs *argp;
+    uint32_t j;
+};
+
 template <int Q, typename T, int NR, bool EX>
-hipError_t launch_qt(const ServeArgs &a, hipStream_t stream)
+hipError_t launch_qt(const Launch &l, hipStream_t stream)
 {
-    if (a.grid + a.nres == 0)
-        return hipSuccess;
-    if (a.nres != 0)
-        hipLaunchKernelGGL((serve_kernel<Q, T, NR, EX, true>), dim3(a.grid + a.nres),
-                           dim3(kBlock), 0, stream, a);
+    const dim3 grid(serve_launch_grid());
+    if (l.res)
+        hipLaunchKernelGGL((serve_kernel<Q, T, NR, EX, true>), grid, dim3(kBlock), 0, stream,
+                           l.argp, l.j);
     else
-        hipLaunchKernelGGL((serve_kernel<Q, T, NR, EX, false>), dim3(a.grid), dim3(kBlock), 0,
-                           stream, a);
+        hipLaunchKernelGGL((serve_kernel<Q, T, NR, EX, false>), grid, dim3(kBlock), 0, stream,
+                           l.argp, l.j);
     return hipGetLastError();
 }
 
 template <int NR, bool EX>
-hipError_t launch_spec(int q, int count_bytes, const ServeArgs &a, hipStream_t stream)
+hipError_t launch_spec(int q, int count_bytes, const Launch &l, hipStream_t stream)
 {
     if (q == 2 && count_bytes == 2)
-        return launch_qt<2, uint16_t, NR, EX>(a, stream);
+        return launch_qt<2, uint16_t, NR, EX>(l, stream);
     if (q == 2 && count_bytes == 4)
-        return launch_qt<2, uint32_t, NR, EX>(a, stream);
+        return launch_qt<2, uint32_t, NR, EX>(l, stream);
     if constexpr (!EX) {
         if (q == 3 && count_bytes == 2)
-            return launch_qt<3, uint16_t, NR, EX>(a, stream);
+            return launch_qt<3, uint16_t, NR, EX>(l, stream);
         if (q == 3 && count_bytes == 4)
-            return launch_qt<3, uint32_t, NR, EX>(a, stream);
+            return launch_qt<3, uint32_t, NR, EX>(l, stream);
         if (q == 5 && count_bytes == 2)
-            return launch_qt<5, uint16_t, NR, EX>(a, stream);
+            return launch_qt<5, uint16_t, NR, EX>(l, stream);
         if (q == 5 && count_bytes == 4)
-            return launch_qt<5, uint32_t, NR, EX>(a, stream);
+            return launch_qt<5, uint32_t, NR, EX>(l, stream);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_rounds(int q, int count_bytes, int rounds, bool exchange, const ServeArgs &a,
+hipError_t launch_rounds(int q, int count_bytes, int rounds, bool exchange, const Launch &l,
                          hipStream_t stream)
 {
     if (rounds == 10)
-        return exchange ? launch_spec<10, true>(q, count_bytes, a, stream)
-                        : launch_spec<10, false>(q, count_bytes, a, stream);
+        return exchange ? launch_spec<10, true>(q, count_bytes, l, stream)
+                        : launch_spec<10, false>(q, count_bytes, l, stream);
     if (rounds == 7)
-        return exchange ? launch_spec<7, true>(q, count_bytes, a, stream)
-                        : launch_spec<7, false>(q, count_bytes, a, stream);
+        return exchange ? launch_spec<7, true>(q, count_bytes, l, stream)
+                        : launch_spec<7, false>(q, count_bytes, l, stream);
     return hipErrorInvalidValue;
 }
 
@@ -333,10 +346,15 @@ uint32_t serve_grid(uint32_t ntiles, uint32_t reserved)
     return grid < ntiles ? grid : ntiles;
 }
 
-hipError_t launch_serve(int q, int count_bytes, int rounds, bool exchange, const ServeArgs &a,
-                        hipStream_t stream)
+uint32_t serve_launch_grid()
 {
-    return launch_rounds(q, count_bytes, rounds, exchange, a, stream);
+    return (uint32_t)device_cu_count() * 2;
+}
+
+hipError_t launch_serve(int q, int count_bytes, int rounds, bool exchange, bool res,
+                        const ServeArgs *argp, uint32_t j, hipStream_t stream)
+{
+    return launch_rounds(q, count_bytes, rounds, exchange, Launch{res, argp, j}, stream);
 }
 
 }  // namespace ilg

@@ -108,6 +108,15 @@ public:
     // as resident slots, several steps per launch; quantum: the scheduler's.
     uint64_t resident_nodes = 0;
     uint32_t quantum = 1;
+    // Each group's launch arguments in device memory, and for a full
+    // quantum of launches a graph of them (with and without resident
+    // slots), captured once on the stream `cap` and replayed every poll
+    // (the kernels read the arguments at run time, and a graph launch costs
+    // a fraction of the separate launches).
+    ilg::ServeArgs *d_args[kGroups] = {};
+    ilg::ServeArgs h_args[kGroups] = {};
+    hipGraphExec_t quanta[kGroups][2] = {};
+    hipStream_t cap = nullptr;
 
     static int group(uint32_t q, uint32_t cb, const ilg::Fixed &fx)
     {
@@ -406,7 +415,8 @@ public:
             SHIP(hipMemcpyAsync(d_tiles[g], tiles[g].data(), tiles[g].size() * sizeof(uint32_t),
                                 hipMemcpyHostToDevice, streams[g]));
             SHIP(hipMemsetAsync(d_err[g], 0, slots[g].size() * sizeof(uint32_t), streams[g]));
-            ilg::ServeArgs a;
+            ilg::ServeArgs &a = h_args[g];
+            std::memset(&a, 0, sizeof(a));
             a.arena = arena;
             a.slots = d_slots[g];
             a.tile_slot = d_tiles[g];
@@ -418,15 +428,55 @@ public:
             a.slot_err = d_err[g];
             a.nres = (uint32_t)res[g].size();
             a.res_first = res_first;
-            const int q = g >= 16 ? 5 : (g & 8) ? 3 : 2, cb = (g & 4) ? 4 : 2;
-            const int rounds = (g & 2) ? 7 : 10;
-            const bool exchange = (g & 1) != 0;
+            SHIP(hipMemcpyAsync(d_args[g], &a, sizeof(a), hipMemcpyHostToDevice, streams[g]));
+            const bool with_res = a.nres != 0;
+            if (maxsteps[g] == quantum) {
+                rc = capture_quantum(g, with_res);
+                if (rc != ILG_OK)
+                    return rc;
+                SHIP(hipGraphLaunch(quanta[g][with_res ? 1 : 0], streams[g]));
+                continue;
+            }
+            int q, cb, rounds;
+            bool exchange;
+            spec_of(g, &q, &cb, &rounds, &exchange);
             for (uint32_t j = 0; j < maxsteps[g]; ++j) {
-                a.j = j;
-                hipError_t e = ilg::launch_serve(q, cb, rounds, exchange, a, streams[g]);
+                hipError_t e = ilg::launch_serve(q, cb, rounds, exchange, with_res, d_args[g], j,
+                                                 streams[g]);
                 if (e != hipSuccess)
                     return shfail(e, "serve launch");
             }
+        }
+        return ILG_OK;
+    }
+
+    // The graph of a full quantum of group g's launches (j = 0 .. quantum - 1
+    // on the arguments in d_args[g]), captured at its first use.
+    int capture_quantum(int g, bool with_res)
+    {
+        hipGraphExec_t &exec = quanta[g][with_res ? 1 : 0];
+        if (exec)
+            return ILG_OK;
+        if (!cap)
+            SHIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        int q, cb, rounds;
+        bool exchange;
+        spec_of(g, &q, &cb, &rounds, &exchange);
+        SHIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (uint32_t j = 0; j < quantum && e == hipSuccess; ++j)
+            e = ilg::launch_serve(q, cb, rounds, exchange, with_res, d_args[g], j, cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess)
+            e = e2;
+        if (e == hipSuccess)
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            exec = nullptr;
+            return shfail(e, "quantum graph");
         }
         return ILG_OK;
     }
@@ -485,6 +535,8 @@ public:
 
     int ensure(int g, size_t nslots, size_t ntiles)
     {
+        if (!d_args[g])
+            SHIP(hipMalloc((void **)&d_args[g], sizeof(ilg::ServeArgs)));
         if (nslots > cap_slots[g]) {
             (void)hipFree(d_slots[g]);
             (void)hipFree(d_err[g]);
@@ -508,11 +560,17 @@ public:
             (void)hipFree(d_slots[g]);
             (void)hipFree(d_err[g]);
             (void)hipFree(d_tiles[g]);
+            (void)hipFree(d_args[g]);
+            for (int k = 0; k < 2; ++k)
+                if (quanta[g][k])
+                    (void)hipGraphExecDestroy(quanta[g][k]);
             if (streams[g])
                 (void)hipStreamDestroy(streams[g]);
         }
         if (io)
             (void)hipStreamDestroy(io);
+        if (cap)
+            (void)hipStreamDestroy(cap);
         (void)hipFree(arena);
         (void)hipFree(shared);
         (void)hipFree(init_err);
