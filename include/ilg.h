@@ -367,7 +367,7 @@ double ilg_server_clock(void);
  * see ilg_server_set_resident). */
 int ilg_server_create(uint64_t budget_bytes, uint32_t quantum_steps, ilg_server **out);
 
-#define ILG_RESIDENT_DEFAULT_NODES 1024u
+#define ILG_RESIDENT_DEFAULT_NODES 4096u
 #define ILG_RESIDENT_MAX_NODES 65536u
 /* Small requests: those of at most max_nodes nodes (default
  * ILG_RESIDENT_DEFAULT_NODES; 0: none; ILG_E_INVALID above

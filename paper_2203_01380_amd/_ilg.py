@@ -406,7 +406,7 @@ class Server:
     def __init__(self, budget_bytes: int, quantum_steps: int = 100, step_nodes: int = 0,
                  resident: Optional[tuple] = None):
         """resident: (max_nodes, max_steps) for ilg_server_set_resident, or
-        None for the library's default (small requests of up to 1024 nodes,
+        None for the library's default (small requests of up to 4096 nodes,
         up to 16 quanta per poll)."""
         self._h = ctypes.c_void_p()
         check(lib.ilg_server_create(budget_bytes, quantum_steps, ctypes.byref(self._h)))
