@@ -339,7 +339,7 @@ hipError_t launch_rounds(int q, int count_bytes, int rounds, bool exchange, cons
 
 uint32_t serve_grid(uint32_t ntiles, uint32_t reserved)
 {
-    // two 1024-thread workgroups per CU, less those of resident launches
+    // two 1024-thread workgroups per CU, less the launch's resident slots
     const uint32_t slots = (uint32_t)device_cu_count() * 2;
     const uint32_t floor = slots / 2;
     const uint32_t grid = reserved + floor < slots ? slots - reserved : floor;

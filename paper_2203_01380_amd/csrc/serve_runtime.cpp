@@ -308,6 +308,10 @@ public:
         taken_steps = steps;
         launched_slot.assign(active.size(), {0, 0});
         uint32_t maxsteps[kGroups] = {};
+        // Resident slots of a group: at most half the launch grid, so that
+        // the tile walk (at least the other half) and they fit the grid.
+        const uint32_t max_res = std::min<uint32_t>(ilg::kResidentMaxWg,
+                                                    ilg::serve_launch_grid() / 2);
         for (size_t i = 0; i < active.size(); ++i) {
             Req &r = *active[i];
             Payload *p = payload_of(r);
@@ -316,7 +320,7 @@ public:
             const uint32_t nt = (uint32_t)((nodes_of(c) + ilg::kServeTile - 1) / ilg::kServeTile);
             const double w = 1.0 + p->fx.omega_star;
             if (resident_nodes != 0 && nodes_of(c) <= resident_nodes &&
-                res[g].size() < ilg::kResidentMaxWg) {
+                res[g].size() < max_res) {
                 res[g].push_back({i, make_slot(r, p, steps[i]), nt * w + kResidentStep});
                 continue;
             }
@@ -415,6 +419,8 @@ public:
             SHIP(hipMemcpyAsync(d_tiles[g], tiles[g].data(), tiles[g].size() * sizeof(uint32_t),
                                 hipMemcpyHostToDevice, streams[g]));
             SHIP(hipMemsetAsync(d_err[g], 0, slots[g].size() * sizeof(uint32_t), streams[g]));
+            if (grid[g] + (uint32_t)res[g].size() > ilg::serve_launch_grid())
+                return sfail(ILG_E_DEVICE, "serving launch needs more workgroups than its grid");
             ilg::ServeArgs &a = h_args[g];
             std::memset(&a, 0, sizeof(a));
             a.arena = arena;
