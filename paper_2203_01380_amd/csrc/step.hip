@@ -30,9 +30,18 @@ using sampler::Wide;
 
 using sampler::row_elem;
 
+// Waves per SIMD the kernel must fit.  The uint32 D1Q3 kernel is held to
+// eight (two 1024-thread workgroups per CU, at most 64 registers): left free
+// it takes 74 and runs one workgroup per CU, which measured slower than the
+// capped kernel with its 12-byte spill.  The uint32 D2Q5 kernel spills far
+// more under that cap and measured slower with it, so it and the rest keep
+// the compiler's choice.
+template <int Q, typename T>
+constexpr int kMinWaves = (Q == 3 && sizeof(T) == 4) ? 8 : 1;
+
 // EX: the D1Q2 exchange form (Q = 2 only).
 template <int Q, typename T, int NB, int GB, int BLOCK, bool FLIP, bool PZ, int NR, bool EX>
-__global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kMinWaves<Q, T>))) void step_kernel(StepArgs a)
 {
     using W = typename Wide<T>::type;
     constexpr int kTabs = (Q == 2) ? 2 : 3;
