@@ -227,6 +227,9 @@ struct ServeArgs {
     // slots res_first .. res_first + nres - 1.
     uint32_t nres;
     uint32_t res_first;
+    // Clock ticks of each tile-walk workgroup's range in the launch with
+    // j = 0 (written by workgroups with a nonempty range only).
+    uint64_t *wg_time;
 };
 // Most resident slots in one launch.
 constexpr uint32_t kResidentMaxWg = 128;

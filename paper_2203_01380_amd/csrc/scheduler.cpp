@@ -264,5 +264,38 @@ bool Scheduler::release(uint64_t id)
     return true;
 }
 
+void tile_cost_correction(const uint32_t *range, uint32_t grid, const double *w,
+                          const uint32_t *tile_slot, const uint64_t *time, uint32_t nslots,
+                          double lo, double hi, double *corr)
+{
+    std::vector<double> est(grid, 0.0), num(nslots, 0.0), den(nslots, 0.0);
+    double total_t = 0.0, total_e = 0.0;
+    for (uint32_t b = 0; b < grid; ++b) {
+        for (uint32_t t = range[b]; t < range[b + 1]; ++t)
+            est[b] += w[t];
+        if (est[b] > 0.0) {
+            total_t += (double)time[b];
+            total_e += est[b];
+        }
+    }
+    for (uint32_t s = 0; s < nslots; ++s)
+        corr[s] = 1.0;
+    if (total_t <= 0.0 || total_e <= 0.0)
+        return;
+    const double scale = total_e / total_t;  // estimated units per clock tick
+    for (uint32_t b = 0; b < grid; ++b) {
+        if (est[b] <= 0.0)
+            continue;
+        const double r = (double)time[b] * scale / est[b];
+        for (uint32_t t = range[b]; t < range[b + 1]; ++t) {
+            num[tile_slot[t]] += w[t] * r;
+            den[tile_slot[t]] += w[t];
+        }
+    }
+    for (uint32_t s = 0; s < nslots; ++s)
+        if (den[s] > 0.0)
+            corr[s] = std::min(hi, std::max(lo, num[s] / den[s]));
+}
+
 }  // namespace serve
 }  // namespace ilg

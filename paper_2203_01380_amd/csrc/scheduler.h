@@ -149,5 +149,18 @@ private:
     std::map<uint64_t, std::unique_ptr<Req>> all_;
 };
 
+// Measured correction of the estimated cost of the slots of one launch's
+// tile walk.  Workgroup b walked tiles [range[b], range[b + 1]) in time[b]
+// (any clock; workgroups with an empty range are ignored); tile t belongs to
+// slot tile_slot[t] < nslots and was estimated at w[t] > 0.  The times are
+// first scaled so that their total equals the estimated total (only relative
+// cost matters), then each workgroup's ratio of measured to estimated work
+// is shared among the slots of its range in proportion to their estimated
+// work there.  corr[s] is that weighted ratio, clamped to [lo, hi]; a slot no
+// measured workgroup walked gets 1.
+void tile_cost_correction(const uint32_t *range, uint32_t grid, const double *w,
+                          const uint32_t *tile_slot, const uint64_t *time, uint32_t nslots,
+                          double lo, double hi, double *corr);
+
 }  // namespace serve
 }  // namespace ilg

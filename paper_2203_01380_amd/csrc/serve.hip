@@ -227,12 +227,14 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(const ServeArgs *argp, ui
 
     // The host splits the tile list into contiguous ranges of equal
     // estimated work (the work per node grows with a slot's collision
-    // fraction), so a launch does not wait on the workgroups of its most
-    // expensive requests.
+    // fraction; the estimate is corrected from the measured times below), so
+    // a launch does not wait on the workgroups of its most expensive
+    // requests.
     const uint32_t lo = a->wg_tiles[blockIdx.x];
     const uint32_t hi = a->wg_tiles[blockIdx.x + 1];
     if (lo >= hi)
         return;
+    const uint64_t t_begin = clock64();
     // The first tile's slot (from its own list, so that its read does not
     // wait for lo) gives the tables staged with the half table.
     // Only the slot index is carried from tile to tile: the descriptor is a
@@ -282,6 +284,14 @@ __global__ __launch_bounds__(kBlock) void serve_kernel(const ServeArgs *argp, ui
     }
     if (ovf > kMax)
         atomicOr(a->slot_err + slot, 1u);
+    // The first launch of a quantum (all of its slots take that step) times
+    // each workgroup's range, from its start to its last wave's end; the host
+    // corrects the slots' estimated cost per tile from these times.
+    if (j == 0) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            a->wg_time[blockIdx.x] = clock64() - t_begin;
+    }
 }
 
 struct Launch {

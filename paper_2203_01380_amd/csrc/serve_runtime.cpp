@@ -72,6 +72,10 @@ struct Payload {
     bool device_init = false;
     double nave = 0.0, amp = 0.0;
     uint64_t init_seed = 0;
+    // Measured cost per tile relative to the model 1 + omega*, learned from
+    // the tile walk's workgroup times (density and the sampler's chunking
+    // make the true cost depart from the model).
+    double cost = 1.0;
 };
 
 Payload *payload_of(Req &r)
@@ -102,6 +106,7 @@ public:
     ilg::ServeSlot *d_slots[kGroups] = {};
     uint32_t *d_err[kGroups] = {};    // error word of each slot of the last launch
     uint32_t *d_tiles[kGroups] = {};  // as h_tiles
+    uint64_t *d_time[kGroups] = {};   // clock of each workgroup's range (launch j = 0)
     size_t cap_slots[kGroups] = {}, cap_tiles[kGroups] = {};
     hipStream_t io = nullptr;  // copies in and out
     // Small requests (at most resident_nodes nodes, 0: none) are advanced
@@ -226,6 +231,9 @@ public:
     // each workgroup's first tile
     std::vector<uint32_t> h_tiles[kGroups];
     std::vector<double> h_weight[kGroups];     // estimated work of each tile
+    std::vector<Payload *> h_walk[kGroups];    // request of each tile-walk slot
+    std::vector<uint64_t> h_time;
+    std::vector<double> h_corr;
     std::vector<uint32_t> h_err[kGroups];
     std::vector<Req *> launched;
     std::vector<uint32_t> launched_steps;  // planned by the scheduler
@@ -302,6 +310,7 @@ public:
             slots[g].clear();
             tiles[g].clear();
             h_weight[g].clear();
+            h_walk[g].clear();
         }
         launched = active;
         launched_steps = steps;
@@ -318,7 +327,7 @@ public:
             const ilg_config &c = p->cfg;
             const int g = group(c.q, c.count_bytes, p->fx);
             const uint32_t nt = (uint32_t)((nodes_of(c) + ilg::kServeTile - 1) / ilg::kServeTile);
-            const double w = 1.0 + p->fx.omega_star;
+            const double w = (1.0 + p->fx.omega_star) * p->cost;
             if (resident_nodes != 0 && nodes_of(c) <= resident_nodes &&
                 res[g].size() < max_res) {
                 res[g].push_back({i, make_slot(r, p, steps[i]), nt * w + kResidentStep});
@@ -330,6 +339,7 @@ public:
             const uint32_t idx = (uint32_t)slots[g].size();
             launched_slot[i] = {g, idx};
             slots[g].push_back(make_slot(r, p, taken_steps[i]));
+            h_walk[g].push_back(p);
             slots[g].back().tile_begin = (uint32_t)tiles[g].size();
             slots[g].back().tile_end = (uint32_t)tiles[g].size() + nt;
             tiles[g].insert(tiles[g].end(), nt, idx);
@@ -434,6 +444,7 @@ public:
             a.slot_err = d_err[g];
             a.nres = (uint32_t)res[g].size();
             a.res_first = res_first;
+            a.wg_time = d_time[g];
             SHIP(hipMemcpyAsync(d_args[g], &a, sizeof(a), hipMemcpyHostToDevice, streams[g]));
             const bool with_res = a.nres != 0;
             if (maxsteps[g] == quantum) {
@@ -498,6 +509,8 @@ public:
             if (e == hipSuccess)
                 e = hipMemcpy(h_err[g].data(), d_err[g], h_err[g].size() * sizeof(uint32_t),
                               hipMemcpyDeviceToHost);
+            if (e == hipSuccess)
+                e = calibrate(g);
             if (e != hipSuccess)
                 rc = shfail(e, "serve quantum");
         }
@@ -524,6 +537,29 @@ public:
         return rc;
     }
 
+    // Corrects the cost factor of each request of group g's last tile walk
+    // from the times its workgroups took (at most a third up or a quarter
+    // down per quantum, so that one noisy time cannot swing the split).
+    hipError_t calibrate(int g)
+    {
+        const uint32_t ntiles = h_args[g].ntiles, grid = h_args[g].grid;
+        if (ntiles == 0 || grid == 0 || h_walk[g].empty())
+            return hipSuccess;
+        h_time.resize(grid);
+        hipError_t e = hipMemcpy(h_time.data(), d_time[g], grid * sizeof(uint64_t),
+                                 hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return e;
+        h_corr.resize(h_walk[g].size());
+        ilg::serve::tile_cost_correction(h_tiles[g].data() + ntiles, grid, h_weight[g].data(),
+                                         h_tiles[g].data(), h_time.data(),
+                                         (uint32_t)h_walk[g].size(), 0.75, 4.0 / 3.0,
+                                         h_corr.data());
+        for (size_t s = 0; s < h_walk[g].size(); ++s)
+            h_walk[g][s]->cost = std::min(4.0, std::max(0.25, h_walk[g][s]->cost * h_corr[s]));
+        return hipSuccess;
+    }
+
     int unload(Req &r) override
     {
         Payload *p = payload_of(r);
@@ -543,6 +579,8 @@ public:
     {
         if (!d_args[g])
             SHIP(hipMalloc((void **)&d_args[g], sizeof(ilg::ServeArgs)));
+        if (!d_time[g])
+            SHIP(hipMalloc((void **)&d_time[g], ilg::serve_launch_grid() * sizeof(uint64_t)));
         if (nslots > cap_slots[g]) {
             (void)hipFree(d_slots[g]);
             (void)hipFree(d_err[g]);
@@ -566,6 +604,7 @@ public:
             (void)hipFree(d_slots[g]);
             (void)hipFree(d_err[g]);
             (void)hipFree(d_tiles[g]);
+            (void)hipFree(d_time[g]);
             (void)hipFree(d_args[g]);
             for (int k = 0; k < 2; ++k)
                 if (quanta[g][k])

@@ -300,4 +300,11 @@ int h_load_order(void *hv, uint64_t *out, int cap)
     return n;
 }
 
+void h_tile_cost_correction(const uint32_t *range, uint32_t grid, const double *w,
+                            const uint32_t *tile_slot, const uint64_t *time, uint32_t nslots,
+                            double lo, double hi, double *corr)
+{
+    ilg::serve::tile_cost_correction(range, grid, w, tile_slot, time, nslots, lo, hi, corr);
+}
+
 }  // extern "C"

@@ -400,3 +400,102 @@ def test_resident_random_stress(H):
     drain(s)
     assert H.h_violations(s.h) == 0 and H.h_used(s.h) == 0
     s.close()
+
+
+def _correction(H, ranges, w, tile_slot, times, nslots, lo=0.5, hi=2.0):
+    f = H.h_tile_cost_correction
+    f.restype = None
+    f.argtypes = [ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32,
+                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint32),
+                  ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint32, ctypes.c_double,
+                  ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    r = np.ascontiguousarray(ranges, dtype=np.uint32)
+    wv = np.ascontiguousarray(w, dtype=np.float64)
+    ts = np.ascontiguousarray(tile_slot, dtype=np.uint32)
+    tm = np.ascontiguousarray(times, dtype=np.uint64)
+    out = np.zeros(nslots, dtype=np.float64)
+    f(r.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), len(r) - 1,
+      wv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+      ts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+      tm.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), nslots, lo, hi,
+      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def test_tile_cost_correction_attribution(H):
+    """Slot 0's workgroups took 1.2 times as long per estimated unit as slot
+    1's; slot 2 shares one workgroup with slot 1; slot 3 is walked by nobody
+    (its workgroup's range is empty)."""
+    # tiles: slot 0 x4 (w 1), slot 1 x4 (w 1), slot 2 x2 (w 2)
+    w = [1.0] * 8 + [2.0, 2.0]
+    slot = [0] * 4 + [1] * 4 + [2, 2]
+    ranges = [0, 2, 4, 6, 10, 10]   # wg 2: slot 1 (2 tiles); wg 3: slot 1 + slot 2
+    times = [240, 240, 200, 600, 999_999]
+    c = _correction(H, ranges, w, slot, times, 4)
+    # estimated 2, 2, 2, 6 units (wg 4 ignored): scale 12 / 1280 per tick,
+    # ratios 1.125, 1.125, 0.9375, 0.9375 -- slot 0 at 1.2 times the others,
+    # and the estimate-weighted mean ratio is 1
+    np.testing.assert_allclose(c, [1.125, 0.9375, 0.9375, 1.0])
+    # clamping
+    c = _correction(H, ranges, w, slot, [900, 900, 100, 300, 0], 4, lo=0.8, hi=1.25)
+    assert c[0] == 1.25 and c[1] == 0.8 and c[2] == 0.8 and c[3] == 1.0
+    # no time measured: no correction
+    np.testing.assert_array_equal(_correction(H, ranges, w, slot, [0] * 5, 4), [1.0] * 4)
+
+
+def test_tile_cost_correction_shared_workgroup(H):
+    """A workgroup's ratio goes to every slot of its range in proportion to
+    the slot's estimated work there."""
+    w = [3.0, 1.0, 1.0, 1.0, 1.0, 1.0]
+    slot = [0, 1, 2, 2, 2, 2]
+    ranges = [0, 2, 6]              # wg 0: slot 0 (3) + slot 1 (1); wg 1: slot 2 (4)
+    c = _correction(H, ranges, w, slot, [150, 100], 3)
+    # scale 8/250; ratios 150*8/250/4 = 1.2, 100*8/250/4 = 0.8
+    np.testing.assert_allclose(c, [1.2, 1.2, 0.8])
+
+
+def _split(w, grid):
+    """The executor's split: boundary b where the running weight passes
+    b / grid of the total, each tile to the range holding its larger half."""
+    total = sum(w)
+    out, acc, t = [0], 0.0, 0
+    for b in range(1, grid):
+        target = total * b / grid
+        while t < len(w) and acc + 0.5 * w[t] < target:
+            acc += w[t]
+            t += 1
+        out.append(t)
+    out.append(len(w))
+    return out
+
+
+def test_tile_cost_correction_balances_the_walk(H):
+    """Requests whose true cost per tile departs from the model by up to
+    +-30 %: a few rounds of correction bring the slowest workgroup of the
+    split within a few per cent of the mean."""
+    rng = np.random.default_rng(3)
+    nslots, grid = 64, 256
+    ntile = rng.integers(8, 200, size=nslots)
+    model = 1.0 + rng.uniform(0.05, 1.0, size=nslots)
+    true = model * rng.uniform(0.7, 1.3, size=nslots)
+    factor = np.ones(nslots)
+
+    def walk():
+        w, slot = [], []
+        for s in range(nslots):
+            for k in range(ntile[s]):
+                w.append(model[s] * factor[s])
+                slot.append(s)
+        r = _split(w, grid)
+        times = [int(1000 * sum(true[slot[t]] for t in range(r[b], r[b + 1])))
+                 for b in range(grid)]
+        return w, slot, r, times
+
+    imb = []
+    for _ in range(6):
+        w, slot, r, times = walk()
+        tv = np.array(times, dtype=np.float64)
+        imb.append(tv.max() / tv[tv > 0].mean())
+        factor *= _correction(H, r, w, slot, times, nslots, lo=0.75, hi=1.33)
+    assert imb[0] > 1.15
+    assert imb[-1] < 1.05 and imb[-1] < imb[0]
