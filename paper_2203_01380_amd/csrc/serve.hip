@@ -164,8 +164,15 @@ constexpr int kNB = (Q == 5) ? 3 : (Q == 3) ? 2 : 1;
 // walk ran a quarter slower (D1Q2, saturated).
 using ConstArgs = const __attribute__((address_space(4))) ServeArgs;
 
+// Waves per SIMD the kernel must fit: the uint32 D1Q3 kernel is held to
+// eight (at most 64 registers), so that two of its 1024-thread workgroups
+// share a CU as the launch grid assumes; left free it takes 70 registers and
+// one workgroup per CU.
+template <int Q, typename T>
+constexpr int kServeMinWaves = (Q == 3 && sizeof(T) == 4) ? 8 : 1;
+
 template <int Q, typename T, int NR, bool EX, bool RES>
-__global__ __launch_bounds__(kBlock) void serve_kernel(const ServeArgs *argp, uint32_t j)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kServeMinWaves<Q, T>))) void serve_kernel(const ServeArgs *argp, uint32_t j)
 {
     using W = typename Wide<T>::type;
     // The launch's arguments from device memory (scalar loads): the grid is
