@@ -116,6 +116,21 @@ __device__ __forceinline__ uint32_t pick3(bool c2, bool c3, uint32_t a, uint32_t
     return c3 ? c : lo;
 }
 
+// b ? y : x on values (see pick3).
+__device__ __forceinline__ uint32_t pick2(bool b, uint32_t x, uint32_t y)
+{
+    return b ? y : x;
+}
+
+// f3 ? d : (f2 ? c : (f1 ? b : a)) on values, for f3 => f2 => f1.
+__device__ __forceinline__ uint32_t pick_ge(bool f1, bool f2, bool f3, uint32_t a, uint32_t b,
+                                            uint32_t c, uint32_t d)
+{
+    const uint32_t lo = f1 ? b : a;
+    const uint32_t mid = f2 ? c : lo;
+    return f3 ? d : mid;
+}
+
 // Word j of the lane's draw stream (lanes may ask for different j).
 template <int NB, int NR, typename K>
 __device__ __forceinline__ uint32_t draw_word(const Draws<NB, NR, K> &d, uint32_t j)
@@ -552,6 +567,76 @@ __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Dra
     return true;
 }
 
+// q = 3 node update when every lane has every count in 1..128, so each
+// removal binomial takes one or two chunks (D_i = 1 + (a_i > 64), the first
+// chunk 64 trials where there are two).  The draws are consumed in order:
+// the chunks of a_0 from draw 0, of a_1 from D_0, of a_2 from D_0 + D_1, and
+// the redistribution from D_0 + D_1 + D_2 (3..6) on; each lane selects its
+// words among the eight computed.  The six removal chunks are probed
+// together (a lane's absent second chunk probes row 1 and is clamped to 0).
+// Where some lane has M > 64 the redistribution goes on chunk by chunk from
+// the lane's first redistribution word, as the generic path takes it.
+template <typename W, int NB, int GB, int NR, typename K>
+__device__ __forceinline__ void node_wide3(const W (&av)[3], W (&c)[3], const Draws<NB, NR, K> &d,
+                                           const Tabs &tb, bool p_zero)
+{
+    static_assert(NB >= 2, "draws 0..7 must be computed up front");
+    uint32_t lo[3], hi[3];
+    bool two[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const uint32_t a = (uint32_t)av[i];
+        two[i] = a > (uint32_t)kChunk;
+        lo[i] = two[i] ? (uint32_t)kChunk : a;
+        hi[i] = two[i] ? a - (uint32_t)kChunk : 0u;
+    }
+    // e1, e2: D_0 + D_1 - 2 is at least 1, is 2; f1..f3: D_0 + D_1 + D_2 - 3
+    // is at least 1, 2, is 3
+    const bool e1 = two[0] || two[1], e2 = two[0] && two[1];
+    const bool f1 = e1 || two[2], f2 = e2 || (e1 && two[2]), f3 = e2 && two[2];
+    W kv[3];
+    if (p_zero) {
+        kv[0] = kv[1] = kv[2] = 0;
+    } else {
+        const uint32_t u[6] = {d.w[0],
+                               d.w[1],
+                               pick2(two[0], d.w[1], d.w[2]),
+                               pick2(two[0], d.w[2], d.w[3]),
+                               pick3(e1, e2, d.w[2], d.w[3], d.w[4]),
+                               pick3(e1, e2, d.w[3], d.w[4], d.w[5])};
+        // one binomial's two chunks probed together at a time (all six at
+        // once hold too many registers)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const uint32_t rows[2] = {lo[i], hi[i] != 0 ? hi[i] : 1u};
+            const uint32_t ui[2] = {u[2 * i], u[2 * i + 1]};
+            const Probe p[2] = {probe_row<kTidP, GB>(tb.g_p, rows[0], ui[0]),
+                                probe_row<kTidP, GB>(tb.g_p, rows[1], ui[1])};
+            uint32_t cc[2];
+            finish_all<2>(p, rows, ui, cc);
+            kv[i] = (W)(clamp_to(cc[0], lo[i]) + clamp_to(cc[1], hi[i]));
+        }
+    }
+    const W M = kv[0] + kv[1] + kv[2];
+    W mv[3];
+    if (wave_any(M > (W)kChunk)) {
+        const uint32_t j = 3u + (two[0] ? 1u : 0u) + (two[1] ? 1u : 0u) + (two[2] ? 1u : 0u);
+        redistribute_generic<3, W, NB, GB>(M, j, mv, d, tb);
+    } else {
+        // m_1 at the first redistribution word, m_0 at the next (for M = 0
+        // neither consumes a word and both are 0)
+        const uint32_t u1 = pick_ge(f1, f2, f3, d.w[3], d.w[4], d.w[5], d.w[6]);
+        const uint32_t u0 = pick_ge(f1, f2, f3, d.w[4], d.w[5], d.w[6], d.w[7]);
+        mv[1] = (W)chunk_or_zero<kTidRest, GB>(tb.g_rest, (uint32_t)M, u1);
+        const W R = M - mv[1];
+        mv[0] = (W)chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)R, u0);
+        mv[2] = R - mv[0];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        c[i] = av[i] - kv[i] + mv[i];
+}
+
 // OR of the counts.  Kernels accumulate it over their nodes in an integer
 // register: a count above kMax = 2^b - 1 exists exactly when the accumulated
 // OR exceeds kMax (a loop-carried integer is far cheaper than a loop-carried
@@ -756,6 +841,21 @@ __device__ __forceinline__ void node_update(const W (&av)[Q], W (&cn)[Q], uint32
 #pragma unroll
             for (int i = 0; i < Q; ++i)
                 cn[i] = (W)c32[i];
+        }
+    }
+    if constexpr (Q == 3) {
+        // every count in 1..128 (at a density of about 150 most waves have
+        // some outer count above one chunk)
+        if (!done && ballot((m1(av[0]) | m1(av[1]) | m1(av[2])) < 2u * kChunk) == lanes) {
+            uint32_t a32[3], c32[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                a32[i] = (uint32_t)av[i];
+            node_wide3<uint32_t, NB, GB>(a32, c32, d, tb, p_zero);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                cn[i] = (W)c32[i];
+            done = true;
         }
     }
     if (!done) {

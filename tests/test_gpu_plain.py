@@ -147,6 +147,39 @@ def test_mixed_middle_chunk_layouts(ilg, oracle_lib, cb, omega):
     _run_both(ilg, oracle_lib, 3, L, cb, omega, init, steps=6, seed=13)
 
 
+@pytest.mark.parametrize("cb,omega", [(2, 1.8), (4, 1.5), (2, 1.0), (4, 0.6)])
+def test_two_chunk_outer_layouts(ilg, oracle_lib, cb, omega):
+    """D1Q3 wavefronts whose three counts all lie in 1..128 with some outer
+    count above 64 (each removal binomial one or two chunks, its draws
+    shifted per lane): blocks of 64 nodes with every count two chunks, every
+    count random in 1..128, the edges 1/63/64/65/127/128, only the outer
+    counts above 64, and a block with one count beyond 128 (the generic
+    path).  omega 1.0 and 0.6 collide most particles, so M exceeds one
+    chunk and the redistribution goes on from each lane's own word."""
+    rng = np.random.default_rng(57 + cb)
+    nblk = 50
+    L = 64 * nblk + 33
+    dt = np.uint16 if cb == 2 else np.uint32
+    cols = []
+    for b in range(nblk + 1):
+        mode = b % 5
+        if mode == 0:
+            v = rng.integers(65, 129, (3, 64))
+        elif mode == 1:
+            v = rng.integers(1, 129, (3, 64))
+        elif mode == 2:
+            v = rng.choice([1, 63, 64, 65, 127, 128], (3, 64))
+        elif mode == 3:
+            v = np.stack([rng.integers(65, 129, 64), rng.integers(1, 65, 64),
+                          rng.integers(65, 129, 64)])
+        else:
+            v = rng.integers(65, 129, (3, 64))
+            v[rng.integers(0, 3), rng.integers(0, 64)] = 129 + rng.integers(0, 100)
+        cols.append(v)
+    init = np.concatenate(cols, axis=1)[:, :L].astype(dt)
+    _run_both(ilg, oracle_lib, 3, L, cb, omega, init, steps=6, seed=19)
+
+
 @pytest.mark.parametrize("q,omega,theta,mean", [(2, 1.0, 0.0, 60.0), (2, 1.1, 0.0, 60.0),
                                                  (3, 1.0, 0.0, 60.0), (3, 0.9, 0.0, 45.0),
                                                  (3, 1.05, 0.9, 40.0), (3, 1.0, 0.0, 95.0),
