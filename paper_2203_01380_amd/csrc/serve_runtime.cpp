@@ -285,9 +285,10 @@ public:
     }
 
     // Cost model of a launch, in units of one full tile of the tile walk at
-    // omega* = 0 (about 2 us): a tile costs 1 + omega* (more collided
-    // particles, larger redistribution binomials; a partial tile about as
-    // much as a full one, its waves being latency bound), and a workgroup
+    // omega* = 0 (about 2 us): a tile costs (1 + omega*) times the request's
+    // measured factor (more collided particles, larger redistribution
+    // binomials; a partial tile about as much as a full one, its waves being
+    // latency bound; see calibrate()), and a workgroup
     // entering a slot pays about half a tile to stage the slot's tables.  A
     // resident step of a request of n tiles costs n (1 + omega*) plus half a
     // tile (the step's barrier and latency-bound waves).  A launch also
