@@ -291,6 +291,26 @@ def bench_philox7(ilg, W, stream, warmup: int, steps: int = 1000):
             "alg_gbs": alg_bytes / (ms / 1e3) / 1e9}
 
 
+def bench_dense(ilg, W, stream, warmup: int, steps: int = 500):
+    """A dense D1Q3 lattice whose moving populations exceed one 64-trial
+    chunk: L = 2^24, uint16, Poisson(90) per velocity, theta = 2/3 (equal
+    weights, so every count stays near 90), omega = 1.8."""
+    L = 1 << 24
+    init = W.init_poisson_iid(3, L, 90.0, 2, init_seed=8)
+    lat = ilg.Lattice(3, L, 2, 1.8, 4, init, theta=2.0 / 3.0)
+    mass0 = int(init.astype(np.int64).sum())
+    lat.step(warmup)
+    sec = timed(stream, lambda: lat.step(steps))
+    if lat.moments()["mass"] != mass0:
+        raise SystemExit("dense D1Q3: mass not conserved")
+    lat.close()
+    ms = sec * 1e3 / steps
+    return {"workload": "D1Q3 with flip, L=2^24 periodic, uint16, Poisson(90) per velocity, "
+                        "theta=2/3, omega=1.8",
+            "steps": steps, "ms_per_step": ms, "node_updates_per_s": L / (ms / 1e3),
+            "alg_gbs": 12 * L / (ms / 1e3) / 1e9}
+
+
 def bench_exchange(ilg, W, stream, warmup: int, steps: int = 1000):
     """D1Q2, L = 2^24, uint16, Poisson(40), omega = 1.5: the three-binomial
     collision against the exchange form (draw specification v3, two
@@ -621,7 +641,7 @@ def main():
     ap.add_argument("--length", type=int, default=1 << 24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,probes,mallfree,philox7,exchange,d2q5,batched,batched_specs,batched_d2q5,decay,serving_saturated,serving",
+    ap.add_argument("--forms", default="plain,probes,mallfree,philox7,dense,exchange,d2q5,batched,batched_specs,batched_d2q5,decay,serving_saturated,serving",
                     help="comma list of plain (always), probes, mallfree, philox7, exchange, "
                          "d2q5, batched, batched_specs, batched_d2q5, decay, serving_saturated, "
                          "serving")
@@ -728,6 +748,9 @@ def main():
     if "philox7" in forms:
         say("plain step with 7-round draws")
         out["philox7"] = bench_philox7(ilg, W, stream, args.warmup)
+    if "dense" in forms:
+        say("dense D1Q3 lattice")
+        out["d1q3_dense"] = bench_dense(ilg, W, stream, args.warmup)
     if "exchange" in forms:
         say("D1Q2: three binomials against the exchange form")
         out["d1q2_exchange"] = bench_exchange(ilg, W, stream, args.warmup)
