@@ -2,11 +2,11 @@
 # rocprofv3 runs behind the committed summaries of the batched kernel (the
 # ragged D1Q2 ensemble with S(k) sampling and the D2Q5 ensemble, each after
 # its shape autotuning): kernel trace, then SQ instruction counters per
-# kernel instantiation.  Run from the repository root on the GPU host; raw
-# output goes to gpurun_out/.
+# kernel instantiation.  Run from the repository root on the GPU host as
+# `bash paper_2203_01380_amd/profile_batch.sh OUTPUT_DIR`; raw output goes to OUTPUT_DIR.
 set -eo pipefail
 R=$(pwd)
-OUT=$R/gpurun_out
+OUT=$(mkdir -p "${1:?usage: $0 OUTPUT_DIR}" && cd "$1" && pwd)
 cd /tmp
 export TMPDIR=/tmp
 # (two members in the batched form's plain-loop comparison: under the

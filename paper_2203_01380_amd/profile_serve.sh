@@ -3,10 +3,11 @@
 # kernel trace of the request streams (3 s at 200, 100 and 50 req/s), and
 # SQ instruction counters of the saturated runs (64 requests of 2^20 nodes)
 # beside plain lattices at the same rates.  Run from the repository root on
-# the GPU host; raw output goes to gpurun_out/.
+# the GPU host as `bash paper_2203_01380_amd/profile_serve.sh OUTPUT_DIR`; raw output goes
+# to OUTPUT_DIR.
 set -eo pipefail
 R=$(pwd)
-OUT=$R/gpurun_out
+OUT=$(mkdir -p "${1:?usage: $0 OUTPUT_DIR}" && cd "$1" && pwd)
 cd /tmp
 export TMPDIR=/tmp
 echo "[profile] kernel trace of the request streams"

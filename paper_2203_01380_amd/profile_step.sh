@@ -3,10 +3,11 @@
 # (D1Q3, L = 2^24 and 2^26, uint16): kernel trace, HBM traffic (FETCH_SIZE,
 # WRITE_SIZE, each scaled by a plain 768 MiB copy), SQ instruction counters,
 # and the clock per dispatch after an idle start.  Run from the repository
-# root on the GPU host; raw output goes to gpurun_out/.
+# root on the GPU host as `bash paper_2203_01380_amd/profile_step.sh OUTPUT_DIR`;
+# raw output goes to OUTPUT_DIR.
 set -eo pipefail
 R=$(pwd)
-OUT=$R/gpurun_out
+OUT=$(mkdir -p "${1:?usage: $0 OUTPUT_DIR}" && cd "$1" && pwd)
 cd /tmp
 export TMPDIR=/tmp
 B="python $R/bench.py --no-cpu-baseline"
