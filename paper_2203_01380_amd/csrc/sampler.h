@@ -681,6 +681,71 @@ __device__ __forceinline__ void redistribute_generic(W M, uint32_t j, W (&mv)[Q]
     }
 }
 
+// Word idx of the lane's stream for idx in [LO, LO + N) (lanes may differ),
+// among the words computed up front: a select chain on values.
+template <int LO, int N, int NB, int NR, typename K>
+__device__ __forceinline__ uint32_t word_in(const Draws<NB, NR, K> &d, uint32_t idx)
+{
+    static_assert(LO + N <= 4 * NB, "only the words computed up front");
+    uint32_t r = d.w[LO];
+    static_for<1, N>([&](auto kc) {
+        constexpr int k = LO + decltype(kc)::value;
+        r = pick2(idx == (uint32_t)k, r, d.w[k]);
+    });
+    return r;
+}
+
+// D2Q5 redistribution of M <= 192 collided particles from draw o = 5 + two
+// on (two: the lane's rest removal took two chunks), in straight-line code:
+// the rest Bin(M, P_rest) over up to three chunks at words o, o + 1, o + 2,
+// the x/y split Bin(R, 1/2) over up to two chunks from word b1 = o + c1
+// (c1 = ceil(M / 64) chunks before it), then Bin(m_x, 1/2) for -x from word
+// b2 = b1 + ceil(R / 64) and Bin(m_y, 1/2) for -y after it; a binomial of
+// no trials consumes no word.  Each lane selects its words among the twelve
+// computed (the -y word may be the thirteenth, computed for the lanes that
+// need it).  Where some lane has m_x or m_y above one chunk, the last two
+// binomials go on chunk by chunk from word b2 as the generic path takes
+// them.  Returns false (nothing written) where some lane has M > 192 or
+// R > 128; the caller then takes the generic redistribution.
+template <typename W, int NB, int GB, int NR, typename K>
+__device__ __forceinline__ bool redistribute5(uint32_t M, bool two, W (&mv)[5],
+                                              const Draws<NB, NR, K> &d, const Tabs &tb)
+{
+    static_assert(NB >= 3, "draws 0..11 must be computed up front");
+    if (wave_any(M > 3u * kChunk))
+        return false;
+    const uint32_t ur[3] = {pick2(two, d.w[5], d.w[6]), pick2(two, d.w[6], d.w[7]),
+                            pick2(two, d.w[7], d.w[8])};
+    const uint32_t rest = chunks_upto<kTidRest, 3, GB>(tb.g_rest, M, ur);
+    const uint32_t R = M - rest;
+    if (wave_any(R > 2u * kChunk))
+        return false;
+    const uint32_t b1 = (two ? 6u : 5u) + (M + kChunk - 1) / kChunk;  // 5..9
+    const uint32_t us[2] = {word_in<5, 5>(d, b1), word_in<6, 5>(d, b1 + 1u)};
+    const uint32_t mx = chunks_upto<kTidHalf, 2, GB>(tb.g_half, R, us);
+    const uint32_t my = R - mx;
+    uint32_t j = b1 + (R + kChunk - 1) / kChunk;  // 5..11
+    mv[2] = (W)rest;
+    if (wave_any(mx > (uint32_t)kChunk || my > (uint32_t)kChunk)) {
+        mv[0] = binomial<kTidHalf, W, NB, GB>((W)mx, j, tb.g_half, false, d);
+        mv[1] = binomial<kTidHalf, W, NB, GB>((W)my, j, tb.g_half, false, d);
+    } else {
+        const uint32_t u0 = word_in<5, 7>(d, j);
+        const uint32_t u1 = draw_word(d, j + (mx != 0 ? 1u : 0u));  // 5..12
+        const uint32_t rows[2] = {mx != 0 ? mx : 1u, my != 0 ? my : 1u};
+        const uint32_t u[2] = {u0, u1};
+        const Probe p[2] = {probe_row<kTidHalf, GB>(tb.g_half, rows[0], u[0]),
+                            probe_row<kTidHalf, GB>(tb.g_half, rows[1], u[1])};
+        uint32_t cc[2];
+        finish_all<2>(p, rows, u, cc);
+        mv[0] = (W)clamp_to(cc[0], mx);
+        mv[1] = (W)clamp_to(cc[1], my);
+    }
+    mv[4] = (W)mx - mv[0];
+    mv[3] = (W)my - mv[1];
+    return true;
+}
+
 // D2Q5 node update when every lane has the movers' counts in 1..64 and the
 // rest count in 1..128 (one or two chunks: D = 1 or 2 by lane) and the
 // redistribution fits one chunk per binomial (M <= 64).  Draws: movers -x
@@ -735,7 +800,8 @@ __device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Dr
     W mv[5];
     if (wave_any(M > (W)kChunk)) {
         // the removal took draws 0..4, and 5 with a two-chunk rest count
-        redistribute_generic<5, W, NB, GB>(M, two ? 6u : 5u, mv, d, tb);
+        if (!redistribute5<W, NB, GB>((uint32_t)M, two, mv, d, tb))
+            redistribute_generic<5, W, NB, GB>(M, two ? 6u : 5u, mv, d, tb);
 #pragma unroll
         for (int i = 0; i < 5; ++i)
             c[i] = av[i] - kv[i] + mv[i];
