@@ -82,6 +82,35 @@ def test_collided_beyond_one_chunk(ilg, omega):
     _run_both(ilg, 96, 80, 2, omega, init, steps=8, seed=21, r=5)
 
 
+@pytest.mark.parametrize("cb,omega", [(2, 1.0), (4, 1.0), (2, 1.15)])
+def test_redistribution_layouts(ilg, cb, omega):
+    """Rows of 64 nodes (one wave each) whose counts put M = sum k_i in
+    129..192 with some rest removals of two chunks (the last split's word is
+    then the thirteenth), M near 192 (R above two chunks: the generic
+    redistribution), M above 192, M in 65..128, and M about 180 (m_x or m_y
+    above one chunk in some lanes: the last two splits chunk by chunk)."""
+    rng = np.random.default_rng(77 + cb)
+    lx, ly = 64, 40
+    dt = np.uint16 if cb == 2 else np.uint32
+    init = np.empty((5, ly, lx), dtype=dt)
+    for y in range(ly):
+        mode = y % 5
+        if mode == 0:
+            mov, rest = (18, 27), (58, 72)
+        elif mode == 1:
+            mov, rest = (30, 33), (58, 65)
+        elif mode == 2:
+            mov, rest = (38, 45), (60, 70)
+        elif mode == 3:
+            mov, rest = (10, 21), (30, 51)
+        else:
+            mov, rest = (28, 31), (60, 66)
+        for i in (0, 1, 3, 4):
+            init[i, y] = rng.integers(mov[0], mov[1], lx)
+        init[2, y] = rng.integers(rest[0], rest[1], lx)
+    _run_both(ilg, lx, ly, cb, omega, init, steps=4, seed=23, r=2)
+
+
 def test_multi_chunk_counts(ilg):
     """Counts above 64 (several chunks, draws past the eager blocks)."""
     rng = np.random.default_rng(4)
