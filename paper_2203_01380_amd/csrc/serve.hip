@@ -252,9 +252,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kServeMi
     uint32_t slot = __builtin_amdgcn_readfirstlane(a->wg_slot[blockIdx.x]);  // uniform
     stage_slot<Q>(a->arena, const_space(a->slots)[slot].table_off, s_tab, s_guide);
     uint32_t staged = slot;
+    // D1Q3 carries the current slot's end in a scalar register, so that a
+    // tile's first scalar read is not a wait of its own; D1Q2 reads it per
+    // tile (carried, its walk measured a quarter slower).
+    uint32_t s_end = const_space(a->slots)[slot].tile_end;
     __syncthreads();  // every table is visible to every wave
     for (uint32_t tile = lo; tile < hi; ++tile) {
-        if (tile >= const_space(a->slots)[slot].tile_end) {
+        if (Q != 3)
+            s_end = const_space(a->slots)[slot].tile_end;
+        if (tile >= s_end) {
             // leaving a slot: its overflow is reported in its own error word
             if (ovf > kMax)
                 atomicOr(a->slot_err + slot, 1u);
@@ -262,6 +268,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kServeMi
             do
                 ++slot;
             while (tile >= const_space(a->slots)[slot].tile_end);
+            s_end = const_space(a->slots)[slot].tile_end;
         }
         ConstSlot *sl = const_space(a->slots) + slot;
         if (j >= sl->steps)
