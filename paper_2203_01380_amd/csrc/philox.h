@@ -44,13 +44,15 @@ struct PhiloxSchedule {
     __device__ __forceinline__ uint32_t b(int i) const { return kb[i]; }
 };
 
-template <int R, typename K>
+// RUN: rounds run (R, or R - 1 for the state before the last round).
+template <int R, typename K, int RUN = R>
 __device__ __forceinline__ uint4 philox4x32(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                             const K &key)
 {
     static_assert(R == 7 || R == 10, "draw specifications use 10 or 7 rounds");
+    static_assert(RUN == R || RUN == R - 1, "all rounds, or all but the last");
 #pragma unroll
-    for (int round = 0; round < R; ++round) {
+    for (int round = 0; round < RUN; ++round) {
         const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
         const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
         const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, key.a(round));
@@ -77,11 +79,12 @@ __device__ __forceinline__ uint4 philox4x32(uint32_t c0, uint32_t c1, uint32_t c
 // vector instruction; fed uniform operands it pulls the first round's word
 // into vector registers and its product into quarter-rate vector
 // multiplies).  Same function as philox4x32.
-template <int R, typename K>
+template <int R, typename K, int RUN = R>
 __device__ __forceinline__ uint4 philox4x32_x(uint32_t x, uint32_t t, uint32_t r, uint32_t b,
                                               const K &key)
 {
     static_assert(R == 7 || R == 10, "draw specifications use 10 or 7 rounds");
+    static_assert(RUN == R || RUN == R - 1, "all rounds, or all but the last");
     // round 1 on (x, t, r, b)
     const uint64_t p0 = (uint64_t)kPhiloxM0 * x;
     const uint64_t q1 = (uint64_t)kPhiloxM1 * r;                    // uniform
@@ -106,7 +109,7 @@ __device__ __forceinline__ uint4 philox4x32_x(uint32_t x, uint32_t t, uint32_t r
         c3 = (uint32_t)a0;
     }
 #pragma unroll
-    for (int round = 3; round < R; ++round) {
+    for (int round = 3; round < RUN; ++round) {
         const uint64_t a0 = (uint64_t)kPhiloxM0 * c0;
         const uint64_t a1 = (uint64_t)kPhiloxM1 * c2;
         const uint32_t n0 = xor3((uint32_t)(a1 >> 32), c1, key.a(round));

@@ -78,9 +78,16 @@ __device__ __forceinline__ bool wave_any(bool p)
 // beforehand (PhiloxSchedule); both give the same draws.
 template <int NB, int NR, typename K = PhiloxKey>
 struct Draws {
+    // Words of the eager blocks.  With two or more blocks the last block's
+    // final round stops after its first product: its words 4 NB - 4 and
+    // 4 NB - 3 are complete, while w[4 NB - 2] and w[4 NB - 1] hold the
+    // inputs (counter words 0 and 3) of the second product, from which
+    // word() forms words 4 NB - 2 and 4 NB - 1 where a path reads them (the
+    // straight-line paths of most nodes read neither).
     uint32_t w[4 * NB];
     uint32_t x, t, r;
     K key;
+    static constexpr bool kLazy = NB >= 2;
 
     __device__ __forceinline__ void init(uint32_t x_, uint32_t t_, uint32_t r_, const K &key_)
     {
@@ -90,13 +97,36 @@ struct Draws {
             // with a precomputed schedule (serving slots) the uniform words
             // of the first rounds are per tile, so they are written for the
             // scalar unit; elsewhere the compiler hoists them anyway
+            constexpr int kRun = NR;
             uint4 o;
+            if (kLazy && b == NB - 1) {
+                if constexpr (std::is_same<K, PhiloxSchedule>::value)
+                    o = philox4x32_x<NR, K, NR - 1>(x, t, r, (uint32_t)b, key);
+                else
+                    o = philox4x32<NR, K, NR - 1>(x, t, r, (uint32_t)b, key);
+                const uint64_t p1 = (uint64_t)kPhiloxM1 * o.z;
+                w[4 * b + 0] = xor3((uint32_t)(p1 >> 32), o.y, key.a(NR - 1));
+                w[4 * b + 1] = (uint32_t)p1;
+                w[4 * b + 2] = o.x;
+                w[4 * b + 3] = o.w;
+                continue;
+            }
             if constexpr (std::is_same<K, PhiloxSchedule>::value)
-                o = philox4x32_x<NR>(x, t, r, (uint32_t)b, key);
+                o = philox4x32_x<kRun>(x, t, r, (uint32_t)b, key);
             else
-                o = philox4x32<NR>(x, t, r, (uint32_t)b, key);
+                o = philox4x32<kRun>(x, t, r, (uint32_t)b, key);
             w[4 * b + 0] = o.x; w[4 * b + 1] = o.y; w[4 * b + 2] = o.z; w[4 * b + 3] = o.w;
         }
+    }
+
+    // Word k (a compile-time index below 4 NB) of the eager blocks.
+    __device__ __forceinline__ uint32_t word(int k) const
+    {
+        if (!kLazy || k < 4 * NB - 2)
+            return w[k];
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * w[4 * NB - 2];
+        return k == 4 * NB - 2 ? xor3((uint32_t)(p0 >> 32), w[4 * NB - 1], key.b(NR - 1))
+                               : (uint32_t)p0;
     }
 };
 
@@ -142,31 +172,31 @@ __device__ __forceinline__ uint32_t draw_word(const Draws<NB, NR, K> &d, uint32_
         // wave-uniform index: scalar branches pick the register
         static_assert(kEager <= 12, "at most three eager Philox blocks");
         switch (j0) {
-        case 0: r = d.w[0]; break;
-        case 1: r = d.w[1]; break;
-        case 2: r = d.w[2]; break;
-        case 3: r = d.w[3]; break;
-        case 4: r = d.w[4 % kEager]; break;
-        case 5: r = d.w[5 % kEager]; break;
-        case 6: r = d.w[6 % kEager]; break;
-        case 7: r = d.w[7 % kEager]; break;
-        case 8: r = d.w[8 % kEager]; break;
-        case 9: r = d.w[9 % kEager]; break;
-        case 10: r = d.w[10 % kEager]; break;
-        default: r = d.w[kEager - 1]; break;
+        case 0: r = d.word(0); break;
+        case 1: r = d.word(1); break;
+        case 2: r = d.word(2); break;
+        case 3: r = d.word(3); break;
+        case 4: r = d.word(4 % kEager); break;
+        case 5: r = d.word(5 % kEager); break;
+        case 6: r = d.word(6 % kEager); break;
+        case 7: r = d.word(7 % kEager); break;
+        case 8: r = d.word(8 % kEager); break;
+        case 9: r = d.word(9 % kEager); break;
+        case 10: r = d.word(10 % kEager); break;
+        default: r = d.word(kEager - 1); break;
         }
     } else {
         const uint32_t jc = j < kEager ? j : kEager - 1;
         if constexpr (NB == 1) {
-            r = pick4(d.w[0], d.w[1], d.w[2], d.w[3], jc);
+            r = pick4(d.word(0), d.word(1), d.word(2), d.word(3), jc);
         } else if constexpr (NB == 2) {
-            const uint32_t lo = pick4(d.w[0], d.w[1], d.w[2], d.w[3], jc & 3u);
-            const uint32_t hi = pick4(d.w[4], d.w[5], d.w[6], d.w[7], jc & 3u);
+            const uint32_t lo = pick4(d.word(0), d.word(1), d.word(2), d.word(3), jc & 3u);
+            const uint32_t hi = pick4(d.word(4), d.word(5), d.word(6), d.word(7), jc & 3u);
             r = (jc & 4u) ? hi : lo;
         } else {
-            const uint32_t b0 = pick4(d.w[0], d.w[1], d.w[2], d.w[3], jc & 3u);
-            const uint32_t b1 = pick4(d.w[4], d.w[5], d.w[6], d.w[7], jc & 3u);
-            const uint32_t b2 = pick4(d.w[8], d.w[9], d.w[10], d.w[11], jc & 3u);
+            const uint32_t b0 = pick4(d.word(0), d.word(1), d.word(2), d.word(3), jc & 3u);
+            const uint32_t b1 = pick4(d.word(4), d.word(5), d.word(6), d.word(7), jc & 3u);
+            const uint32_t b2 = pick4(d.word(8), d.word(9), d.word(10), d.word(11), jc & 3u);
             r = (jc >= 8u) ? b2 : ((jc >= 4u) ? b1 : b0);
         }
         if (wave_any(j >= kEager)) {
@@ -425,7 +455,7 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
             kv[i] = 0;
     } else if constexpr (Q == 2) {
         const uint32_t rows[2] = {(uint32_t)av[0], (uint32_t)av[1]};
-        const uint32_t u[2] = {d.w[0], d.w[1]};
+        const uint32_t u[2] = {d.word(0), d.word(1)};
         const Probe p[2] = {probe_row<kTidP, GB>(tb.g_p, rows[0], u[0]),
                             probe_row<kTidP, GB>(tb.g_p, rows[1], u[1])};
         uint32_t cc[2];
@@ -434,7 +464,7 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
         kv[1] = clamp_to(cc[1], rows[1]);
     } else if constexpr (D1 == 1) {
         const uint32_t rows[3] = {(uint32_t)av[0], (uint32_t)av[1], (uint32_t)av[2]};
-        const uint32_t u[3] = {d.w[0], d.w[1], d.w[2]};
+        const uint32_t u[3] = {d.word(0), d.word(1), d.word(2)};
         const Probe p[3] = {probe_row<kTidP, GB>(tb.g_p, rows[0], u[0]),
                             probe_row<kTidP, GB>(tb.g_p, rows[1], u[1]),
                             probe_row<kTidP, GB>(tb.g_p, rows[2], u[2])};
@@ -448,7 +478,7 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
         // remainder (word 2); the outer ones take words 0 and 3
         const uint32_t rows[4] = {(uint32_t)av[0], (uint32_t)kChunk,
                                   (uint32_t)av[1] - (uint32_t)kChunk, (uint32_t)av[2]};
-        const uint32_t u[4] = {d.w[0], d.w[1], d.w[2], d.w[3]};
+        const uint32_t u[4] = {d.word(0), d.word(1), d.word(2), d.word(3)};
         const Probe p[4] = {probe_row<kTidP, GB>(tb.g_p, rows[0], u[0]),
                             probe_full<GB>(tb, u[1]),
                             probe_row<kTidP, GB>(tb.g_p, rows[2], u[2]),
@@ -468,28 +498,28 @@ __device__ __forceinline__ bool node_fast(const W (&av)[Q], W (&c)[Q], const Dra
     if (!wave_any(M > (W)kChunk)) {
         // the common case: every redistribution binomial takes one chunk
         if constexpr (Q == 2) {
-            mv[0] = chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)M, d.w[kFirst]);
+            mv[0] = chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)M, d.word(kFirst));
             mv[1] = M - mv[0];
         } else {
             // m_0 uses the next word only if m_1 consumed one (M > 0); if M = 0
             // then R = 0 and m_0 consumes nothing, so the word is irrelevant.
-            mv[1] = chunk_or_zero<kTidRest, GB>(tb.g_rest, (uint32_t)M, d.w[kFirst]);
+            mv[1] = chunk_or_zero<kTidRest, GB>(tb.g_rest, (uint32_t)M, d.word(kFirst));
             const W R = M - mv[1];
-            mv[0] = chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)R, d.w[kFirst + 1]);
+            mv[0] = chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)R, d.word(kFirst + 1));
             mv[2] = R - mv[0];
         }
     } else if constexpr (Q == 2) {
         // M <= 128: m_0 over one or two chunks, words 2 and 3
         if (wave_any(M > (W)(2 * kChunk)))
             return false;
-        const uint32_t u[2] = {d.w[2], d.w[3]};
+        const uint32_t u[2] = {d.word(2), d.word(3)};
         mv[0] = (W)chunks_upto<kTidHalf, 2, GB>(tb.g_half, (uint32_t)M, u);
         mv[1] = M - mv[0];
     } else {
         // M <= 192: words kFirst .. kFirst + 3 (at most 7 for D1 <= 2)
         if (wave_any(M > (W)(3 * kChunk)))
             return false;
-        const uint32_t u[4] = {d.w[kFirst], d.w[kFirst + 1], d.w[kFirst + 2], d.w[kFirst + 3]};
+        const uint32_t u[4] = {d.word(kFirst), d.word(kFirst + 1), d.word(kFirst + 2), d.word(kFirst + 3)};
         if (!redistribute3<W, GB>(M, u, mv, tb))
             return false;
     }
@@ -523,7 +553,7 @@ __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Dra
         const uint32_t m1b = c3 ? (uint32_t)kChunk : (c2 ? a1 - kChunk : 0u);
         const uint32_t rows[4] = {(uint32_t)av[0], c2 ? (uint32_t)kChunk : a1,
                                   m1b != 0 ? m1b : 1u, (uint32_t)av[2]};
-        const uint32_t u[4] = {d.w[0], d.w[1], d.w[2], pick3(c2, c3, d.w[2], d.w[3], d.w[4])};
+        const uint32_t u[4] = {d.word(0), d.word(1), d.word(2), pick3(c2, c3, d.word(2), d.word(3), d.word(4))};
         const Probe p[4] = {probe_row<kTidP, GB>(tb.g_p, rows[0], u[0]),
                             probe_row<kTidP, GB>(tb.g_p, rows[1], u[1]),
                             probe_row<kTidP, GB>(tb.g_p, rows[2], u[2]),
@@ -533,7 +563,7 @@ __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Dra
         kv[0] = clamp_to(cc[0], rows[0]);
         uint32_t k1 = clamp_to(cc[1], rows[1]) + clamp_to(cc[2], m1b);
         if (wave_any(c3))
-            k1 += chunk_or_zero<kTidP, GB>(tb.g_p, c3 ? a1 - 2u * kChunk : 0u, d.w[3]);
+            k1 += chunk_or_zero<kTidP, GB>(tb.g_p, c3 ? a1 - 2u * kChunk : 0u, d.word(3));
         kv[1] = (W)k1;
         kv[2] = clamp_to(cc[3], rows[3]);
     }
@@ -543,10 +573,10 @@ __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Dra
         // the common case: m_1 and m_0 take one chunk each, at draws 2 + D1
         // and 3 + D1 (for M = 0 neither consumes a word)
         mv[1] = chunk_or_zero<kTidRest, GB>(tb.g_rest, (uint32_t)M,
-                                            pick3(c2, c3, d.w[3], d.w[4], d.w[5]));
+                                            pick3(c2, c3, d.word(3), d.word(4), d.word(5)));
         const W R = M - mv[1];
         mv[0] = chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)R,
-                                            pick3(c2, c3, d.w[4], d.w[5], d.w[6]));
+                                            pick3(c2, c3, d.word(4), d.word(5), d.word(6)));
         mv[2] = R - mv[0];
     } else {
         // Redistribution words start at 2 + D1; the fourth of them would be
@@ -554,10 +584,10 @@ __device__ __forceinline__ bool node_var3(const W (&av)[3], W (&c)[3], const Dra
         // generic path.
         if (wave_any(M > (W)(3 * kChunk) || (c3 && M > (W)(2 * kChunk))))
             return false;
-        const uint32_t u[4] = {pick3(c2, c3, d.w[3], d.w[4], d.w[5]),
-                               pick3(c2, c3, d.w[4], d.w[5], d.w[6]),
-                               pick3(c2, c3, d.w[5], d.w[6], d.w[7]),
-                               pick3(c2, c3, d.w[6], d.w[7], 0u)};
+        const uint32_t u[4] = {pick3(c2, c3, d.word(3), d.word(4), d.word(5)),
+                               pick3(c2, c3, d.word(4), d.word(5), d.word(6)),
+                               pick3(c2, c3, d.word(5), d.word(6), d.word(7)),
+                               pick3(c2, c3, d.word(6), d.word(7), 0u)};
         if (!redistribute3<W, GB>(M, u, mv, tb))
             return false;
     }
@@ -598,12 +628,12 @@ __device__ __forceinline__ void node_wide3(const W (&av)[3], W (&c)[3], const Dr
     if (p_zero) {
         kv[0] = kv[1] = kv[2] = 0;
     } else {
-        const uint32_t u[6] = {d.w[0],
-                               d.w[1],
-                               pick2(two[0], d.w[1], d.w[2]),
-                               pick2(two[0], d.w[2], d.w[3]),
-                               pick3(e1, e2, d.w[2], d.w[3], d.w[4]),
-                               pick3(e1, e2, d.w[3], d.w[4], d.w[5])};
+        const uint32_t u[6] = {d.word(0),
+                               d.word(1),
+                               pick2(two[0], d.word(1), d.word(2)),
+                               pick2(two[0], d.word(2), d.word(3)),
+                               pick3(e1, e2, d.word(2), d.word(3), d.word(4)),
+                               pick3(e1, e2, d.word(3), d.word(4), d.word(5))};
         // one binomial's two chunks probed together at a time (all six at
         // once hold too many registers)
 #pragma unroll
@@ -625,8 +655,8 @@ __device__ __forceinline__ void node_wide3(const W (&av)[3], W (&c)[3], const Dr
     } else {
         // m_1 at the first redistribution word, m_0 at the next (for M = 0
         // neither consumes a word and both are 0)
-        const uint32_t u1 = pick_ge(f1, f2, f3, d.w[3], d.w[4], d.w[5], d.w[6]);
-        const uint32_t u0 = pick_ge(f1, f2, f3, d.w[4], d.w[5], d.w[6], d.w[7]);
+        const uint32_t u1 = pick_ge(f1, f2, f3, d.word(3), d.word(4), d.word(5), d.word(6));
+        const uint32_t u0 = pick_ge(f1, f2, f3, d.word(4), d.word(5), d.word(6), d.word(7));
         mv[1] = (W)chunk_or_zero<kTidRest, GB>(tb.g_rest, (uint32_t)M, u1);
         const W R = M - mv[1];
         mv[0] = (W)chunk_or_zero<kTidHalf, GB>(tb.g_half, (uint32_t)R, u0);
@@ -687,10 +717,10 @@ template <int LO, int N, int NB, int NR, typename K>
 __device__ __forceinline__ uint32_t word_in(const Draws<NB, NR, K> &d, uint32_t idx)
 {
     static_assert(LO + N <= 4 * NB, "only the words computed up front");
-    uint32_t r = d.w[LO];
+    uint32_t r = d.word(LO);
     static_for<1, N>([&](auto kc) {
         constexpr int k = LO + decltype(kc)::value;
-        r = pick2(idx == (uint32_t)k, r, d.w[k]);
+        r = pick2(idx == (uint32_t)k, r, d.word(k));
     });
     return r;
 }
@@ -714,8 +744,8 @@ __device__ __forceinline__ bool redistribute5(uint32_t M, bool two, W (&mv)[5],
     static_assert(NB >= 3, "draws 0..11 must be computed up front");
     if (wave_any(M > 3u * kChunk))
         return false;
-    const uint32_t ur[3] = {pick2(two, d.w[5], d.w[6]), pick2(two, d.w[6], d.w[7]),
-                            pick2(two, d.w[7], d.w[8])};
+    const uint32_t ur[3] = {pick2(two, d.word(5), d.word(6)), pick2(two, d.word(6), d.word(7)),
+                            pick2(two, d.word(7), d.word(8))};
     const uint32_t rest = chunks_upto<kTidRest, 3, GB>(tb.g_rest, M, ur);
     const uint32_t R = M - rest;
     if (wave_any(R > 2u * kChunk))
@@ -769,7 +799,7 @@ __device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Dr
     // word k of the layout after the rest binomial, shifted by one if it took two chunks
     auto wk = [&](auto kc) -> uint32_t {
         constexpr int k = decltype(kc)::value;
-        return two ? d.w[k + 1] : d.w[k];
+        return two ? d.word(k + 1) : d.word(k);
     };
     W kv[5];
     if (p_zero) {
@@ -781,7 +811,7 @@ __device__ __forceinline__ bool node_fast5(const W (&av)[5], W (&c)[5], const Dr
         const uint32_t rows[6] = {(uint32_t)av[0], (uint32_t)av[1],
                                   two ? (uint32_t)kChunk : a2, m2b != 0 ? m2b : 1u,
                                   (uint32_t)av[3], (uint32_t)av[4]};
-        const uint32_t u[6] = {d.w[0], d.w[1], d.w[2], d.w[3],
+        const uint32_t u[6] = {d.word(0), d.word(1), d.word(2), d.word(3),
                                wk(std::integral_constant<int, 3>{}),
                                wk(std::integral_constant<int, 4>{})};
         Probe p[6];
@@ -968,7 +998,7 @@ __device__ __forceinline__ void node_exchange(const W (&av)[2], W (&cn)[2], uint
             X = Y = 0;
         } else {
             const uint32_t rows[2] = {(uint32_t)av[0], (uint32_t)av[1]};
-            const uint32_t u[2] = {d.w[0], d.w[1]};
+            const uint32_t u[2] = {d.word(0), d.word(1)};
             const Probe p[2] = {probe_row<kTidP, GB>(tb.g_p, rows[0], u[0]),
                                 probe_row<kTidP, GB>(tb.g_p, rows[1], u[1])};
             uint32_t cc[2];
