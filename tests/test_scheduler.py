@@ -499,3 +499,27 @@ def test_tile_cost_correction_balances_the_walk(H):
         factor *= _correction(H, r, w, slot, times, nslots, lo=0.75, hi=1.33)
     assert imb[0] > 1.15
     assert imb[-1] < 1.05 and imb[-1] < imb[0]
+
+
+def test_tile_cost_correction_invariances(H):
+    """Times proportional to the estimates leave every slot at 1, and a
+    change of clock (all times scaled) leaves the corrections unchanged;
+    an empty walk corrects nothing."""
+    rng = np.random.default_rng(9)
+    nslots, grid = 12, 40
+    ntile = rng.integers(1, 30, size=nslots)
+    w, slot = [], []
+    for s in range(nslots):
+        for k in range(ntile[s]):
+            w.append(float(rng.uniform(1.0, 2.0)))
+            slot.append(s)
+    r = _split(w, grid)
+    est = [sum(w[r[b]:r[b + 1]]) for b in range(grid)]
+    times = [int(round(1e6 * e)) for e in est]
+    np.testing.assert_allclose(_correction(H, r, w, slot, times, nslots), 1.0, rtol=1e-5)
+    skew = [int(t * (1.0 + 0.3 * ((b * 7) % 5) / 4)) for b, t in enumerate(times)]
+    c1 = _correction(H, r, w, slot, skew, nslots)
+    c2 = _correction(H, r, w, slot, [3 * t for t in skew], nslots)
+    np.testing.assert_allclose(c1, c2, rtol=1e-12)
+    assert not np.allclose(c1, 1.0)
+    np.testing.assert_array_equal(_correction(H, [0], [], [], [], 3), [1.0, 1.0, 1.0])
