@@ -737,6 +737,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": counter_traffic(spec.length),
                      "alg_bytes_per_node_update": ALG_BYTES_PER_NODE_UPDATE,
+                     "traffic_source": (os.path.relpath(traffic_file(spec.length), ROOT)
+                                        + " (step sources digest " + step_source_digest() + ")"),
                      "limiter": "integer VALU (alu_roofline; probes)"},
         "alu_roofline": alu_roofline(ms_per_step, spec.length),
     }
